@@ -1,0 +1,300 @@
+/*
+ * FP64 CPU oracle for the averaged randomized sparse Kaczmarz method (RSKA).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test-suite, the smoke entry and the CPU
+ * baseline leg of the benchmark may load this library. It shares no code,
+ * header, table or helper with the HIP implementation.
+ *
+ * Everything is plain double-precision loops in the order the paper states:
+ *   - the RSKA iteration, eq. (rska) in Sec. 1.1 and Algorithm 1 (RSKA):
+ *       x*_{k+1} = x*_k - (1/eta) sum_{i in tau_k} w_i (<a_i,x_k> - b_i)/||a_i||^2 a_i
+ *       x_{k+1}  = S_lambda(x*_{k+1}),  x_0 = x*_0 = 0
+ *     with uniform weights w_i = alpha (variant v2 of Sec. 5), or a per-step
+ *     alpha_k when one is given;
+ *   - the soft shrinkage S_lambda(x) = max(|x|-lambda, 0) sign(x) (Sec. 1.1);
+ *   - the dual variable y with x* = A^T y, which the update keeps by
+ *     construction (the sketch-and-project form, eq. (rska1), and the start of
+ *     Sec. 4): y_i -= c_t for every sampled row i = tau_k[t].
+ * The index multiset tau_k is an input (eta indices per step, drawn with
+ * replacement; duplicates are counted each time), so the oracle contains no
+ * random number generator.
+ *
+ * Readings of points the paper leaves open (all residuals of one step use the
+ * same x_k; delta is formed before it is subtracted; j ascending in dots and t
+ * ascending in the column sums) are listed with the design notes.
+ *
+ * Return codes: 0 ok, 1 invalid argument, 5 zero-norm row referenced,
+ * 6 index out of range, 7 non-finite iterate.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_INVALID 1
+#define OR_ZERO_ROW 5
+#define OR_INDEX 6
+#define OR_NONFINITE 7
+
+/* Soft shrinkage, Sec. 1.1. |v| == lambda gives 0. */
+static double shrink(double v, double lambda) {
+  double a = fabs(v) - lambda;
+  if (a <= 0.0) return 0.0;
+  return v > 0.0 ? a : -a;
+}
+
+/* ||a_i||^2 for every row of a dense row-major matrix (Def. 1, the matrix D). */
+int oracle_rownorm2_dense(int64_t m, int64_t n, int64_t ld, const double *A, double *r2) {
+  if (m < 0 || n < 0 || ld < n || (m > 0 && (!A || !r2))) return OR_INVALID;
+  for (int64_t i = 0; i < m; ++i) {
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j) s += A[i * ld + j] * A[i * ld + j];
+    r2[i] = s;
+  }
+  return OR_OK;
+}
+
+int oracle_rownorm2_csr(int64_t m, const int64_t *row_ptr, const double *val, double *r2) {
+  if (m < 0 || (m > 0 && (!row_ptr || !r2))) return OR_INVALID;
+  for (int64_t i = 0; i < m; ++i) {
+    double s = 0.0;
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) s += val[p] * val[p];
+    r2[i] = s;
+  }
+  return OR_OK;
+}
+
+/* Shared argument checks of the two solvers. */
+static int check_common(int64_t m, int64_t n, double lambda, int32_t eta, double alpha,
+                        const double *alpha_k, int64_t K, const int32_t *idx, const double *b,
+                        double *z, double *x) {
+  if (m <= 0 || n <= 0 || eta < 1 || K < 0) return OR_INVALID;
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return OR_INVALID;
+  if (!alpha_k && (!(alpha > 0.0) || !isfinite(alpha))) return OR_INVALID;
+  if (!b || !z || !x || (K > 0 && !idx)) return OR_INVALID;
+  return OR_OK;
+}
+
+/* Relative error ||x - xref|| / ||xref|| (the error measure of Sec. 5). */
+static double rel_err(int64_t n, const double *x, const double *xref) {
+  double num = 0.0, den = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    double d = x[j] - xref[j];
+    num += d * d;
+    den += xref[j] * xref[j];
+  }
+  return den > 0.0 ? sqrt(num / den) : sqrt(num);
+}
+
+/*
+ * Dense RSKA. A is m x n row-major with leading dimension ld.
+ * z (= x*) is in/out: the run starts from the given z (pass zeros for the
+ * paper's x*_0 = 0) and x_0 = S_lambda(z). x receives S_lambda(z_K).
+ * y (nullable, length m) is in/out: y[i_t] -= c_t each step.
+ * Step k uses indices idx[off + k*eta + t], t = 0..eta-1, and the relaxation
+ * alpha_k[k] if alpha_k is given, else alpha.
+ * If check_every > 0 and xref/err_hist are given, err_hist[q] receives the
+ * relative error after step (q+1)*check_every.
+ * *k_done receives the number of completed steps (nullable).
+ */
+int oracle_rska_dense(int64_t m, int64_t n, int64_t ld, const double *A, const double *b,
+                      double lambda, int32_t eta, double alpha, const double *alpha_k,
+                      int64_t K, const int32_t *idx, int64_t off,
+                      double *z, double *x, double *y,
+                      int64_t check_every, const double *xref, double *err_hist,
+                      int64_t *k_done) {
+  int st = check_common(m, n, lambda, eta, alpha, alpha_k, K, idx, b, z, x);
+  if (st) return st;
+  if (!A || ld < n) return OR_INVALID;
+  if (k_done) *k_done = 0;
+  double *c = (double *)malloc(sizeof(double) * (size_t)eta);
+  double *delta = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!c || !delta) { free(c); free(delta); return OR_INVALID; }
+
+  for (int64_t j = 0; j < n; ++j) x[j] = shrink(z[j], lambda);
+  for (int64_t k = 0; k < K; ++k) {
+    const int32_t *tau = idx + off + k * (int64_t)eta;
+    double ak = alpha_k ? alpha_k[k] : alpha;
+    /* residuals of all eta rows at the same x_k, then the coefficients */
+    for (int32_t t = 0; t < eta; ++t) {
+      int64_t i = tau[t];
+      if (i < 0 || i >= m) { st = OR_INDEX; goto done; }
+      const double *ai = A + i * ld;
+      double r2 = 0.0, dot = 0.0;
+      for (int64_t j = 0; j < n; ++j) r2 += ai[j] * ai[j];
+      if (r2 == 0.0) { st = OR_ZERO_ROW; goto done; }
+      for (int64_t j = 0; j < n; ++j) dot += ai[j] * x[j];
+      c[t] = (ak / (double)eta) * (dot - b[i]) / r2;
+    }
+    /* delta_k = sum_t c_t a_{tau_t}, formed first, then subtracted */
+    for (int64_t j = 0; j < n; ++j) delta[j] = 0.0;
+    for (int32_t t = 0; t < eta; ++t) {
+      const double *ai = A + (int64_t)tau[t] * ld;
+      for (int64_t j = 0; j < n; ++j) delta[j] += c[t] * ai[j];
+    }
+    int finite = 1;
+    for (int64_t j = 0; j < n; ++j) {
+      z[j] -= delta[j];
+      x[j] = shrink(z[j], lambda);
+      if (!isfinite(z[j])) finite = 0;
+    }
+    if (y)
+      for (int32_t t = 0; t < eta; ++t) y[tau[t]] -= c[t];
+    if (k_done) *k_done = k + 1;
+    if (!finite) { st = OR_NONFINITE; goto done; }
+    if (check_every > 0 && xref && err_hist && (k + 1) % check_every == 0)
+      err_hist[(k + 1) / check_every - 1] = rel_err(n, x, xref);
+  }
+done:
+  free(c);
+  free(delta);
+  return st;
+}
+
+/*
+ * CSR RSKA: the same iteration with the rows stored as (row_ptr, col, val).
+ * Column indices of a row need not be sorted; repeated columns add up.
+ */
+int oracle_rska_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *val, const double *b,
+                    double lambda, int32_t eta, double alpha, const double *alpha_k,
+                    int64_t K, const int32_t *idx, int64_t off,
+                    double *z, double *x, double *y,
+                    int64_t check_every, const double *xref, double *err_hist,
+                    int64_t *k_done) {
+  int st = check_common(m, n, lambda, eta, alpha, alpha_k, K, idx, b, z, x);
+  if (st) return st;
+  if (!row_ptr || !col || !val) return OR_INVALID;
+  if (k_done) *k_done = 0;
+  double *c = (double *)malloc(sizeof(double) * (size_t)eta);
+  double *delta = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!c || !delta) { free(c); free(delta); return OR_INVALID; }
+
+  for (int64_t j = 0; j < n; ++j) x[j] = shrink(z[j], lambda);
+  for (int64_t k = 0; k < K; ++k) {
+    const int32_t *tau = idx + off + k * (int64_t)eta;
+    double ak = alpha_k ? alpha_k[k] : alpha;
+    for (int32_t t = 0; t < eta; ++t) {
+      int64_t i = tau[t];
+      if (i < 0 || i >= m) { st = OR_INDEX; goto done; }
+      double r2 = 0.0, dot = 0.0;
+      for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        if (col[p] < 0 || col[p] >= n) { st = OR_INDEX; goto done; }
+        r2 += val[p] * val[p];
+        dot += val[p] * x[col[p]];
+      }
+      if (r2 == 0.0) { st = OR_ZERO_ROW; goto done; }
+      c[t] = (ak / (double)eta) * (dot - b[i]) / r2;
+    }
+    for (int64_t j = 0; j < n; ++j) delta[j] = 0.0;
+    for (int32_t t = 0; t < eta; ++t) {
+      int64_t i = tau[t];
+      for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) delta[col[p]] += c[t] * val[p];
+    }
+    int finite = 1;
+    for (int64_t j = 0; j < n; ++j) {
+      z[j] -= delta[j];
+      x[j] = shrink(z[j], lambda);
+      if (!isfinite(z[j])) finite = 0;
+    }
+    if (y)
+      for (int32_t t = 0; t < eta; ++t) y[tau[t]] -= c[t];
+    if (k_done) *k_done = k + 1;
+    if (!finite) { st = OR_NONFINITE; goto done; }
+    if (check_every > 0 && xref && err_hist && (k + 1) % check_every == 0)
+      err_hist[(k + 1) / check_every - 1] = rel_err(n, x, xref);
+  }
+done:
+  free(c);
+  free(delta);
+  return st;
+}
+
+/*
+ * Reverse mode of K unrolled dense RSKA steps from z_0 = 0, for one right-hand
+ * side. The forward map is the iteration above with per-step relaxations
+ * alpha_k[k]; the loss gradient with respect to x_K is given (xbar_K).
+ * All K+1 iterates z_k are stored (no checkpointing: this is the plain
+ * definition of the chain rule, taken step by step backwards):
+ *   z_{k+1} = z_k - A_k^T c_k,   c_{k,t} = (alpha_k/eta) (a_t.x_k - b_t)/r2_t,
+ *   x_k = S_lambda(z_k),  dS/dz = 1[|z| > lambda],  dS/dlambda = -sign(z) 1[|z| > lambda].
+ * Outputs: bbar (m, accumulated: +=), *lambda_bar (+=), alpha_bar (K, +=).
+ */
+int oracle_rska_dense_adjoint(int64_t m, int64_t n, int64_t ld, const double *A, const double *b,
+                              double lambda, int32_t eta, const double *alpha_k,
+                              int64_t K, const int32_t *idx, int64_t off,
+                              const double *xbar_K,
+                              double *bbar, double *lambda_bar, double *alpha_bar) {
+  if (m <= 0 || n <= 0 || eta < 1 || K < 0 || !A || ld < n || !b || !alpha_k || !xbar_K ||
+      !bbar || !lambda_bar || !alpha_bar || (K > 0 && !idx) || !(lambda >= 0.0))
+    return OR_INVALID;
+  int st = OR_OK;
+  double *Z = (double *)calloc((size_t)(K + 1) * (size_t)n, sizeof(double));
+  double *xk = (double *)malloc(sizeof(double) * (size_t)n);
+  double *zbar = (double *)malloc(sizeof(double) * (size_t)n);
+  double *xbar = (double *)malloc(sizeof(double) * (size_t)n);
+  double *r = (double *)malloc(sizeof(double) * (size_t)eta);
+  double *r2 = (double *)malloc(sizeof(double) * (size_t)eta);
+  double *cbar = (double *)malloc(sizeof(double) * (size_t)eta);
+  if (!Z || !xk || !zbar || !xbar || !r || !r2 || !cbar) { st = OR_INVALID; goto done; }
+
+  /* forward, storing every z_k */
+  for (int64_t k = 0; k < K; ++k) {
+    const int32_t *tau = idx + off + k * (int64_t)eta;
+    double *zk = Z + k * n, *zn = Z + (k + 1) * n;
+    for (int64_t j = 0; j < n; ++j) { xk[j] = shrink(zk[j], lambda); zn[j] = zk[j]; }
+    for (int32_t t = 0; t < eta; ++t) {
+      int64_t i = tau[t];
+      if (i < 0 || i >= m) { st = OR_INDEX; goto done; }
+      const double *ai = A + i * ld;
+      double s2 = 0.0, dot = 0.0;
+      for (int64_t j = 0; j < n; ++j) { s2 += ai[j] * ai[j]; dot += ai[j] * xk[j]; }
+      if (s2 == 0.0) { st = OR_ZERO_ROW; goto done; }
+      double ct = (alpha_k[k] / (double)eta) * (dot - b[i]) / s2;
+      for (int64_t j = 0; j < n; ++j) zn[j] -= ct * ai[j];
+    }
+  }
+  /* seed: x_K = S(z_K) */
+  {
+    const double *zK = Z + K * n;
+    for (int64_t j = 0; j < n; ++j) {
+      int on = fabs(zK[j]) > lambda;
+      zbar[j] = on ? xbar_K[j] : 0.0;
+      if (on) *lambda_bar -= (zK[j] > 0.0 ? 1.0 : -1.0) * xbar_K[j];
+    }
+  }
+  /* backwards through the steps */
+  for (int64_t k = K - 1; k >= 0; --k) {
+    const int32_t *tau = idx + off + k * (int64_t)eta;
+    const double *zk = Z + k * n;
+    for (int64_t j = 0; j < n; ++j) xk[j] = shrink(zk[j], lambda);
+    double abar = 0.0;
+    for (int32_t t = 0; t < eta; ++t) {
+      const double *ai = A + (int64_t)tau[t] * ld;
+      double s2 = 0.0, dot = 0.0, g = 0.0;
+      for (int64_t j = 0; j < n; ++j) { s2 += ai[j] * ai[j]; dot += ai[j] * xk[j]; g += ai[j] * zbar[j]; }
+      r[t] = dot - b[tau[t]];
+      r2[t] = s2;
+      cbar[t] = -g;                                   /* dL/dc_t = -<a_t, zbar_{k+1}> */
+      abar += cbar[t] * r[t] / ((double)eta * s2);    /* dc_t/dalpha_k */
+    }
+    alpha_bar[k] += abar;
+    for (int64_t j = 0; j < n; ++j) xbar[j] = 0.0;
+    for (int32_t t = 0; t < eta; ++t) {
+      double rbar = cbar[t] * alpha_k[k] / ((double)eta * r2[t]);
+      bbar[tau[t]] -= rbar;                           /* r_t = a_t.x_k - b_t */
+      const double *ai = A + (int64_t)tau[t] * ld;
+      for (int64_t j = 0; j < n; ++j) xbar[j] += rbar * ai[j];
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      if (fabs(zk[j]) > lambda) {
+        zbar[j] += xbar[j];
+        *lambda_bar -= (zk[j] > 0.0 ? 1.0 : -1.0) * xbar[j];
+      }
+    }
+  }
+done:
+  free(Z); free(xk); free(zbar); free(xbar); free(r); free(r2); free(cbar);
+  return st;
+}
