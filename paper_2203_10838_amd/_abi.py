@@ -1,0 +1,62 @@
+"""ctypes declarations of the C ABI in include/rsk.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librsk.so")
+
+RSK_F32, RSK_F64 = 0, 1
+STATUS_NAMES = {
+    0: "RSK_OK", 1: "RSK_ERR_INVALID_ARG", 2: "RSK_ERR_UNSUPPORTED", 3: "RSK_ERR_WORKSPACE",
+    4: "RSK_ERR_HIP", 5: "RSK_ERR_ZERO_ROW", 6: "RSK_ERR_INDEX_RANGE", 7: "RSK_ERR_NONFINITE",
+    8: "RSK_ERR_ABORTED",
+}
+
+c_i64, c_i32, c_dbl, c_vp, c_sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class RskDense(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("n", c_i64), ("ld", c_i64), ("dtype", c_i32), ("val", c_vp)]
+
+
+class RskCsr(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("n", c_i64), ("nnz", c_i64), ("dtype", c_i32), ("row_ptr", c_vp),
+                ("col", c_vp), ("val", c_vp)]
+
+
+class RskParams(ctypes.Structure):
+    _fields_ = [("lambda_", c_dbl), ("eta", c_i32), ("alpha", c_dbl), ("alpha_k", c_vp), ("K", c_i64),
+                ("index_stream", c_vp), ("stream_offset", c_i64), ("rownorm2", c_vp), ("warm_start", c_i32),
+                ("x_ref", c_vp), ("check_every", c_i64), ("tol", c_dbl), ("err_hist", c_vp), ("y_out", c_vp),
+                ("status_dev", c_vp), ("grid", c_i32)]
+
+
+# name -> (restype, argtypes); every symbol include/rsk.h declares
+SIGNATURES = {
+    "rsk_abi_version": (c_i32, []),
+    "rsk_status_string": (ctypes.c_char_p, [c_i32]),
+    "rsk_rownorm2_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_vp]),
+    "rsk_workspace_size_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(RskParams),
+                                         ctypes.POINTER(c_sz)]),
+    "rsk_avg_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
+                                    c_vp, c_sz, c_vp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librsk.so and declare its signatures. Raises if the library is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"librsk.so not built ({path}); run `python -m paper_2203_10838_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib

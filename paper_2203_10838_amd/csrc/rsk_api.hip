@@ -1,0 +1,211 @@
+// C ABI of librsk: validation, planning, workspace layout and launches.
+// The operation every entry point performs is documented in include/rsk.h.
+#include <math.h>
+#include <string.h>
+
+#include "rsk.h"
+#include "rsk_kernels.hpp"
+
+using rsk::u64;
+
+namespace {
+
+constexpr int kMaxEtaDense = 16384;
+constexpr size_t kTileCacheBytes = 96 * 1024;
+constexpr size_t kBytesPerWg = 96 * 1024;  // target row bytes per workgroup per step
+constexpr int64_t kOneHopWords = 4096;     // G*eta at or below which every workgroup reduces every row
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+size_t elem_size(int32_t dt) { return dt == RSK_F64 ? 8 : 4; }
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return cus;
+}
+
+int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+int32_t check_params(const rsk_params* p, int64_t m) {
+  if (!p) return RSK_ERR_INVALID_ARG;
+  if (p->eta < 1 || p->K < 0 || p->K >= (int64_t(1) << 31) || p->stream_offset < 0) return RSK_ERR_INVALID_ARG;
+  if (!(p->lambda >= 0.0) || !isfinite(p->lambda)) return RSK_ERR_INVALID_ARG;
+  if (!p->alpha_k && !finite_pos(p->alpha)) return RSK_ERR_INVALID_ARG;
+  if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
+  if (!p->rownorm2 || !p->status_dev) return RSK_ERR_INVALID_ARG;
+  if (p->check_every < 0 || !(p->tol >= 0.0) || p->grid < 0) return RSK_ERR_INVALID_ARG;
+  if (p->x_ref && p->check_every > 0 && p->err_hist == nullptr && p->tol <= 0.0) return RSK_ERR_INVALID_ARG;
+  (void)m;
+  return RSK_OK;
+}
+
+struct DensePlan {
+  int vec, G, two_hop, tile_cache, wq_max, lpr, W;
+  int64_t nchunks;
+  size_t offP, offC, offM, bytes;
+};
+
+size_t dense_ws_layout(int Gmax, int eta, int W, DensePlan* pl) {
+  size_t o = 0;
+  pl->offP = o; o = align256(o + 2 * (size_t)Gmax * eta * W * sizeof(u64));
+  pl->offC = o; o = align256(o + (size_t)eta * W * sizeof(u64));
+  pl->offM = o; o = align256(o + (size_t)Gmax * 4 * sizeof(u64));
+  pl->bytes = o;
+  return o;
+}
+
+int dense_grid_cap(const rsk_dense* A, const rsk_params* p) {
+  const int cus = device_cus();
+  int cap = p->grid > 0 ? p->grid : (cus > 0 ? cus : 1);
+  if (cap > A->n) cap = (int)A->n;
+  return cap < 1 ? 1 : cap;
+}
+
+int32_t check_dense(const rsk_dense* A) {
+  if (!A || !A->val) return RSK_ERR_INVALID_ARG;
+  if (A->m <= 0 || A->n <= 0 || A->ld < A->n) return RSK_ERR_INVALID_ARG;
+  if (A->m > INT32_MAX) return RSK_ERR_UNSUPPORTED;
+  if (A->dtype != RSK_F32 && A->dtype != RSK_F64) return RSK_ERR_UNSUPPORTED;
+  return RSK_OK;
+}
+
+template <typename T>
+int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
+  const size_t s = sizeof(T);
+  const int vmax = (int)(16 / s);
+  pl->vec = ((A->ld % vmax) == 0 && (((uintptr_t)A->val) % 16) == 0) ? vmax : 1;
+  pl->W = (int)(s / 4);
+  pl->nchunks = (A->n + pl->vec - 1) / pl->vec;
+  const int cap = dense_grid_cap(A, p);
+  int G;
+  if (p->grid > 0) {
+    G = p->grid;
+  } else {
+    const double step_bytes = (double)p->eta * (double)A->n * (double)s;
+    G = (int)ceil(step_bytes / (double)kBytesPerWg);
+    if (G < 1) G = 1;
+    if (G >= 16) G -= G % 8;
+  }
+  if (G > cap) G = cap;
+  if (G > pl->nchunks) G = (int)pl->nchunks;
+  if (G < 1) G = 1;
+  for (;;) {
+    pl->G = G;
+    pl->wq_max = (int)((pl->nchunks + G - 1) / G);
+    pl->lpr = next_pow2(pl->wq_max) < 64 ? next_pow2(pl->wq_max) : 64;
+    pl->tile_cache = ((size_t)p->eta * pl->wq_max * pl->vec * s) <= kTileCacheBytes;
+    pl->two_hop = ((int64_t)G * p->eta) > kOneHopWords;
+    size_t lds = 0;
+    int maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, pl->tile_cache, &lds);
+    if (maxg == 0 && pl->tile_cache) {
+      pl->tile_cache = 0;
+      maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, 0, &lds);
+    }
+    if (maxg >= G) break;
+    if (maxg == 0) {
+      if (G >= cap) return RSK_ERR_UNSUPPORTED;  // slice too wide for LDS even at the largest grid
+      G = cap;  // wider grid, narrower slices
+      continue;
+    }
+    if (p->grid > 0) return RSK_ERR_UNSUPPORTED;
+    G = maxg;
+  }
+  dense_ws_layout(cap > pl->G ? cap : pl->G, p->eta, pl->W, pl);
+  return RSK_OK;
+}
+
+template <typename T>
+int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, void* x_star, void* x,
+                      void* ws, size_t ws_bytes, hipStream_t stream) {
+  DensePlan pl;
+  int32_t st = plan_dense<T>(A, p, &pl);
+  if (st) return st;
+  if (!ws || ws_bytes < pl.bytes) return RSK_ERR_WORKSPACE;
+  if (((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  unsigned char* w = (unsigned char*)ws;
+  rsk::DenseArgs<T> a;
+  a.A = (const T*)A->val; a.m = A->m; a.n = A->n; a.ld = A->ld;
+  a.b = (const T*)b; a.r2 = (const T*)p->rownorm2;
+  a.lambda = (T)p->lambda; a.alpha = (T)p->alpha; a.alpha_k = (const T*)p->alpha_k;
+  a.eta = p->eta; a.K = p->K;
+  a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
+  a.x_star = (T*)x_star; a.x = (T*)x; a.warm = p->warm_start ? 1 : 0;
+  a.y = (T*)p->y_out;
+  a.xref = (const T*)p->x_ref; a.check_every = p->x_ref ? p->check_every : 0; a.tol = p->tol;
+  a.err_hist = p->err_hist; a.status = p->status_dev;
+  a.xP = (u64*)(w + pl.offP); a.xC = (u64*)(w + pl.offC); a.xM = (u64*)(w + pl.offM);
+  a.G = pl.G; a.two_hop = pl.two_hop; a.tile_cache = pl.tile_cache;
+  a.nchunks = pl.nchunks; a.wq_max = pl.wq_max; a.lpr = pl.lpr;
+  if (rsk::launch_zero_words((u64*)w, pl.bytes / sizeof(u64), stream) != hipSuccess) return RSK_ERR_HIP;
+  if (rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
+  int maxg = 0;
+  if (rsk::launch_dense<T>(a, pl.vec, stream, &maxg) != hipSuccess) return RSK_ERR_HIP;
+  return RSK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rsk_abi_version(void) { return RSK_ABI_VERSION; }
+
+const char* rsk_status_string(int32_t s) {
+  switch (s) {
+    case RSK_OK: return "RSK_OK";
+    case RSK_ERR_INVALID_ARG: return "RSK_ERR_INVALID_ARG";
+    case RSK_ERR_UNSUPPORTED: return "RSK_ERR_UNSUPPORTED";
+    case RSK_ERR_WORKSPACE: return "RSK_ERR_WORKSPACE";
+    case RSK_ERR_HIP: return "RSK_ERR_HIP";
+    case RSK_ERR_ZERO_ROW: return "RSK_ERR_ZERO_ROW";
+    case RSK_ERR_INDEX_RANGE: return "RSK_ERR_INDEX_RANGE";
+    case RSK_ERR_NONFINITE: return "RSK_ERR_NONFINITE";
+    case RSK_ERR_ABORTED: return "RSK_ERR_ABORTED";
+    default: return "RSK_ERR_UNKNOWN";
+  }
+}
+
+int32_t rsk_rownorm2_dense(const rsk_dense* A, void* rownorm2, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!rownorm2) return RSK_ERR_INVALID_ARG;
+  hipError_t e = A->dtype == RSK_F64
+      ? rsk::launch_rownorm2_dense<double>((const double*)A->val, A->m, A->n, A->ld, (double*)rownorm2, (hipStream_t)stream)
+      : rsk::launch_rownorm2_dense<float>((const float*)A->val, A->m, A->n, A->ld, (float*)rownorm2, (hipStream_t)stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_workspace_size_dense(const rsk_dense* A, const rsk_params* p, size_t* bytes) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (p->eta > kMaxEtaDense) return RSK_ERR_UNSUPPORTED;
+  DensePlan pl;
+  st = A->dtype == RSK_F64 ? plan_dense<double>(A, p, &pl) : plan_dense<float>(A, p, &pl);
+  if (st) return st;
+  *bytes = pl.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_avg_solve_dense(const rsk_dense* A, const void* b, const rsk_params* p, void* x_star, void* x,
+                            void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (!b || !x_star || !x) return RSK_ERR_INVALID_ARG;
+  if (p->eta > kMaxEtaDense) return RSK_ERR_UNSUPPORTED;
+  return A->dtype == RSK_F64
+      ? solve_dense_t<double>(A, b, p, x_star, x, workspace, ws_bytes, (hipStream_t)stream)
+      : solve_dense_t<float>(A, b, p, x_star, x, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

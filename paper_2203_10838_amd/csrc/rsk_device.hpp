@@ -1,0 +1,114 @@
+// Device-side building blocks shared by the RSKA kernels (gfx950, wave64).
+//
+// Cross-workgroup exchange. The persistent kernels never use a fenced grid
+// barrier: a release/acquire fence at agent scope writes back and invalidates
+// the XCD's L2, which costs tens of microseconds per step on an 8-XCD part.
+// Instead every value that crosses workgroups travels as 64-bit words
+// (tag << 32 | 32 payload bits) written and read with relaxed agent-scope
+// atomics. Those bypass the non-coherent per-XCD L2 state by themselves, and
+// a 64-bit atomic store is single-copy atomic, so a reader that sees the tag
+// of the current exchange also sees its payload. Tags count exchanges within
+// one launch (the host zeroes the exchange area first), so no stale word can
+// match. Every wait is bounded: an expired wait reports RSK_ERR_ABORTED and
+// the kernel runs to its end.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsk {
+
+typedef unsigned long long u64;
+
+enum : int { ST_OK = 0, ST_ZERO_ROW = 5, ST_INDEX = 6, ST_NONFINITE = 7, ST_ABORTED = 8 };
+
+// About 2^22 polls of roughly a microsecond each: seconds, far beyond any
+// legitimate wait between two steps.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void xstore(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 xload(const u64* p) {
+  return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T> struct Words;
+template <> struct Words<float> { static constexpr int N = 1; };
+template <> struct Words<double> { static constexpr int N = 2; };
+
+__device__ __forceinline__ void put_tagged(u64* s, float v, unsigned tag) {
+  xstore(s, ((u64)tag << 32) | (u64)__float_as_uint(v));
+}
+__device__ __forceinline__ void put_tagged(u64* s, double v, unsigned tag) {
+  const u64 bits = (u64)__double_as_longlong(v);
+  xstore(s, ((u64)tag << 32) | (bits & 0xffffffffull));
+  xstore(s + 1, ((u64)tag << 32) | (bits >> 32));
+}
+__device__ __forceinline__ bool try_tagged(const u64* s, unsigned tag, float& v) {
+  const u64 w = xload(s);
+  if ((unsigned)(w >> 32) != tag) return false;
+  v = __uint_as_float((unsigned)w);
+  return true;
+}
+__device__ __forceinline__ bool try_tagged(const u64* s, unsigned tag, double& v) {
+  const u64 lo = xload(s), hi = xload(s + 1);
+  if ((unsigned)(lo >> 32) != tag || (unsigned)(hi >> 32) != tag) return false;
+  v = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+  return true;
+}
+// Spin until the slot carries `tag`; on expiry set `err` and return 0. Once
+// `err` is set every later wait returns at once, so a broken exchange ends
+// the launch after one expired wait rather than one per slot.
+template <typename T>
+__device__ __forceinline__ T wait_tagged(const u64* s, unsigned tag, int& err) {
+  T v;
+  if (err) return T(0);
+  unsigned spins = 0;
+  while (!try_tagged(s, tag, v)) {
+    if (++spins > kSpinLimit) { err = ST_ABORTED; return T(0); }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return v;
+}
+
+// First error wins.
+__device__ __forceinline__ void set_status(int* status, int code) {
+  if (code) atomicCAS(status, 0, code);
+}
+
+template <typename T>
+__device__ __forceinline__ T shrink(T v, T lambda) {
+  // S_lambda(v) = max(|v| - lambda, 0) sign(v); |v| == lambda gives 0.
+  const T a = fabs(v) - lambda;
+  return a > T(0) ? (v > T(0) ? a : -a) : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum within aligned groups of `width` lanes (width a power of two <= 64).
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Workgroup g -> slice index such that the 8 XCDs (dispatch is round-robin
+// over XCDs by workgroup id) each own one contiguous range of columns; a
+// boundary cache line is then shared inside one XCD's L2 rather than fetched
+// by two. Only performance depends on this mapping, never correctness.
+__device__ __forceinline__ int xcd_slice(int g, int G) {
+  if (G % 8 != 0) return g;
+  return (g % 8) * (G / 8) + g / 8;
+}
+
+template <typename T, int N>
+struct __attribute__((aligned(sizeof(T) * N))) Vec {
+  T v[N];
+};
+
+}  // namespace rsk

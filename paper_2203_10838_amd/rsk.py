@@ -1,0 +1,160 @@
+"""Python binding of librsk over torch device tensors.
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Tensors must live on the GPU; there is no CPU path. Names follow include/rsk.h
+and the paper's notation (lambda -> ``lam``, eta, alpha, K, tau -> ``index_stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _abi
+
+
+class RskError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = int(code)
+        self.name = _abi.STATUS_NAMES.get(self.code, f"code {code}")
+        super().__init__(f"{where}: {self.name}")
+
+
+def _lib():
+    return _abi.load()
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return _abi.RSK_F32
+    if t.dtype == torch.float64:
+        return _abi.RSK_F64
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _dev(t: Optional[torch.Tensor], name: str, dtype=None, numel=None) -> int:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def dense_desc(A: torch.Tensor) -> _abi.RskDense:
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    if not A.is_cuda:
+        raise TypeError("A must be a GPU tensor")
+    if A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        raise ValueError("A must be row-major with leading dimension >= n")
+    return _abi.RskDense(A.shape[0], A.shape[1], A.stride(0), _dtype_code(A), A.data_ptr())
+
+
+def rownorm2(A: torch.Tensor) -> torch.Tensor:
+    """||a_i||^2 of every row of a dense A (Definition 1's D, squared)."""
+    d = dense_desc(A)
+    out = torch.empty(A.shape[0], dtype=A.dtype, device=A.device)
+    st = _lib().rsk_rownorm2_dense(ctypes.byref(d), out.data_ptr(), _stream())
+    if st:
+        raise RskError(st, "rsk_rownorm2_dense")
+    return out
+
+
+@dataclass
+class SolveResult:
+    x_star: torch.Tensor
+    x: torch.Tensor
+    status: Optional[int]
+    k_done: Optional[int]
+    err_hist: Optional[torch.Tensor]
+    status_dev: torch.Tensor
+
+
+def make_params(*, lam, eta, alpha, K, index_stream, rownorm2_t, status_dev, stream_offset=0, alpha_k=None,
+                warm_start=False, x_ref=None, check_every=0, tol=0.0, err_hist=None, y_out=None, grid=0,
+                dtype=None) -> _abi.RskParams:
+    if K > 0:
+        _dev(index_stream, "index_stream", torch.int32, stream_offset + K * eta)
+    return _abi.RskParams(
+        float(lam), int(eta), float(alpha),
+        _dev(alpha_k, "alpha_k", dtype, K if K > 0 else None),
+        int(K), _dev(index_stream, "index_stream") if index_stream is not None else None, int(stream_offset),
+        _dev(rownorm2_t, "rownorm2", dtype), 1 if warm_start else 0,
+        _dev(x_ref, "x_ref", dtype), int(check_every), float(tol),
+        _dev(err_hist, "err_hist", torch.float64), _dev(y_out, "y_out", dtype),
+        _dev(status_dev, "status_dev", torch.int32, 2), int(grid))
+
+
+def workspace_size_dense(A: torch.Tensor, params: _abi.RskParams) -> int:
+    d = dense_desc(A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_dense(ctypes.byref(d), ctypes.byref(params), ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_dense")
+    return int(nbytes.value)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha: float, K: int,
+                index_stream: torch.Tensor, stream_offset: int = 0, alpha_k: Optional[torch.Tensor] = None,
+                rownorm2_t: Optional[torch.Tensor] = None, x_star: Optional[torch.Tensor] = None,
+                warm_start: bool = False, x_ref: Optional[torch.Tensor] = None, check_every: int = 0,
+                tol: float = 0.0, y_out: Optional[torch.Tensor] = None, grid: int = 0,
+                workspace: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
+    """K steps of RSKA (eq. (rska), Algorithm 1) on a dense system, one persistent launch.
+
+    ``x_star`` (optional, in/out) receives x*_K; with ``warm_start`` it is also x*_0.
+    With ``check`` the call synchronises, reads the device status and raises
+    ``RskError`` on a device-side fault.
+    """
+    m, n = A.shape
+    dt = A.dtype
+    _dev(b, "b", dt, m)
+    if rownorm2_t is None:
+        rownorm2_t = rownorm2(A)
+    if x_star is None:
+        if warm_start:
+            raise ValueError("warm_start needs x_star")
+        x_star = torch.empty(n, dtype=dt, device=A.device)
+    _dev(x_star, "x_star", dt, n)
+    x = torch.empty(n, dtype=dt, device=A.device)
+    status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
+    nh = (K // check_every) if (x_ref is not None and check_every > 0) else 0
+    err_hist = torch.full((max(nh, 1),), float("nan"), dtype=torch.float64, device=A.device) if nh else None
+    params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
+                         status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k,
+                         warm_start=warm_start, x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist,
+                         y_out=y_out, grid=grid, dtype=dt)
+    if y_out is not None:
+        _dev(y_out, "y_out", dt, m)
+    d = dense_desc(A)
+    need = workspace_size_dense(A, params)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, A.device)
+    st = _lib().rsk_avg_solve_dense(ctypes.byref(d), b.data_ptr(), ctypes.byref(params), x_star.data_ptr(),
+                                    x.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_avg_solve_dense")
+    status = k_done = None
+    if check:
+        s = status_dev.cpu().tolist()
+        status, k_done = int(s[0]), int(s[1])
+        if status:
+            raise RskError(status, "rsk_avg_solve_dense (device)")
+    return SolveResult(x_star, x, status, k_done, err_hist, status_dev)

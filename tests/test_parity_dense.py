@@ -1,0 +1,166 @@
+"""GPU parity of the dense RSKA kernel against the FP64 oracle on the same index stream.
+
+Bars: FP64 kernel within 1e-10 relative of the oracle; FP32 kernel within
+1e-4 relative (x_K and x*_K, 2-norm); x = S_lambda(x*) exactly in the kernel's
+own precision; bitwise determinism and exact resume.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_10838_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def _alpha_star(A, eta):
+    A64 = np.asarray(A, dtype=np.float64)
+    s = np.linalg.svd(A64, compute_uv=False)
+    return oracle.optimal_alpha(eta, float((A64 * A64).sum()), float(s[0] ** 2))
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _to(t, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(t)).to(dev)
+
+
+def _case(m, n, s, dtype, seed, eta, K, lam, noise=0.0):
+    sysd = inputs.dense_system(m, n, s, dtype=dtype, seed=seed, noise_rel=noise)
+    w = inputs.row_sampling_weights(sysd["A"])
+    idx = inputs.index_stream(w, K, eta, seed + 1)
+    return sysd, idx
+
+
+def _gpu_solve(sysd, idx, dev, **kw):
+    from paper_2203_10838_amd import rsk
+    A = _to(sysd["A"], dev)
+    b = _to(sysd["b"], dev)
+    ix = _to(idx, dev)
+    return rsk.solve_dense(A, b, index_stream=ix, **kw)
+
+
+@pytest.mark.parametrize("dtype,m,n,eta,K,grid,lam", [
+    ("f64", 1000, 500, 10, 3000, 0, 1.0),     # the plain FP64 workload at full size
+    ("f64", 300, 97, 7, 400, 5, 0.5),         # ragged: odd n (scalar path), 5 slices
+    ("f32", 700, 340, 16, 300, 8, 1.0),       # vector path, 8 slices, one-hop reduce
+    ("f32", 600, 333, 9, 300, 3, 0.3),        # odd n, 3 slices
+    ("f32", 2000, 1024, 130, 60, 64, 1.0),    # two-hop reduce (G*eta > 4096)
+    ("f32", 1500, 600, 64, 80, 1, 2.0),       # single workgroup
+])
+def test_dense_matches_oracle(cuda, rsk_lib, dtype, m, n, eta, K, grid, lam):
+    sysd, idx = _case(m, n, max(1, n // 20), dtype, 1234 + m, eta, K, lam)
+    alpha = _alpha_star(sysd["A"], eta)
+    res = _gpu_solve(sysd, idx, cuda, lam=lam, eta=eta, alpha=alpha, K=K, grid=grid)
+    assert res.status == 0 and res.k_done == K
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], lam, eta, alpha, K, idx)
+    xs = res.x_star.cpu().numpy()
+    x = res.x.cpu().numpy()
+    assert _rel(xs, ref["z"]) <= TOL[dtype], _rel(xs, ref["z"])
+    assert _rel(x, ref["x"]) <= TOL[dtype], _rel(x, ref["x"])
+    # x = S_lambda(x*) in the kernel's own precision (closed form of Sec. 1.1)
+    lam_t = np.asarray(lam, dtype=xs.dtype)
+    expect = np.where(np.abs(xs) - lam_t > 0, np.sign(xs) * (np.abs(xs) - lam_t), 0).astype(xs.dtype)
+    assert np.array_equal(x, expect)
+
+
+def test_dense_deterministic_and_resume(cuda, rsk_lib):
+    import torch
+    sysd, idx = _case(900, 256, 12, "f32", 77, 24, 200, 1.0)
+    alpha = _alpha_star(sysd["A"], 24)
+    r1 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=200, grid=8)
+    r2 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=200, grid=8)
+    assert torch.equal(r1.x_star, r2.x_star) and torch.equal(r1.x, r2.x)
+    # resume: 120 + 80 steps == 200 steps, bitwise
+    h = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=120, grid=8)
+    xs = h.x_star.clone()
+    r3 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=80, grid=8, x_star=xs, warm_start=True,
+                    stream_offset=120 * 24)
+    assert torch.equal(r3.x_star, r1.x_star) and torch.equal(r3.x, r1.x)
+
+
+def test_dense_one_hop_equals_two_hop(cuda, rsk_lib):
+    """The two cross-workgroup reductions use the same summation order."""
+    import torch
+    sysd, idx = _case(3000, 2048, 40, "f32", 5, 80, 50, 1.0)
+    alpha = _alpha_star(sysd["A"], 80)
+    a = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=80, alpha=alpha, K=50, grid=48)   # 48*80 <= 4096: one hop
+    b = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=80, alpha=alpha, K=50, grid=56)   # 56*80 > 4096: two hops
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 1.0, 80, alpha, 50, idx)
+    assert _rel(a.x.cpu().numpy(), ref["x"]) <= 1e-4
+    assert _rel(b.x.cpu().numpy(), ref["x"]) <= 1e-4
+
+
+def test_dense_dual_range_invariant(cuda, rsk_lib):
+    """x*_k = A^T y_k at every k (x*_0 = 0 and the update form, start of Sec. 4)."""
+    import torch
+    sysd, idx = _case(400, 120, 6, "f64", 9, 8, 300, 0.7)
+    alpha = _alpha_star(sysd["A"], 8)
+    y = torch.zeros(400, dtype=torch.float64, device=cuda)
+    res = _gpu_solve(sysd, idx, cuda, lam=0.7, eta=8, alpha=alpha, K=300, grid=4, y_out=y)
+    z = res.x_star.cpu().numpy()
+    At_y = sysd["A"].astype(np.float64).T @ y.cpu().numpy()
+    assert _rel(At_y, z) <= 1e-10
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 0.7, 8, alpha, 300, idx, want_y=True)
+    assert _rel(y.cpu().numpy(), ref["y"]) <= 1e-10
+
+
+def test_dense_monitor_and_early_stop(cuda, rsk_lib):
+    import torch
+    K = 5000
+    sysd, idx = _case(1000, 500, 25, "f64", 20310838, 10, K, 1.0)
+    alpha = _alpha_star(sysd["A"], 10)
+    xr = _to(sysd["xhat"], cuda)
+    res = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=10, alpha=alpha, K=K, x_ref=xr, check_every=50)
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 1.0, 10, alpha, K, idx, check_every=50, xref=sysd["xhat"])
+    h = res.err_hist.cpu().numpy()
+    assert np.allclose(h, ref["hist"], rtol=1e-6, atol=1e-13)
+    # stop at the first checkpoint with error <= 1e-5 (it exists within K steps)
+    assert ref["hist"].min() <= 1e-5
+    kstar = (int(np.argmax(ref["hist"] <= 1e-5)) + 1) * 50
+    res2 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=10, alpha=alpha, K=K, x_ref=xr, check_every=50, tol=1e-5)
+    assert res2.k_done == kstar
+
+
+def test_dense_k0_and_rk_special_case(cuda, rsk_lib):
+    import torch
+    sysd, idx = _case(60, 40, 5, "f64", 3, 1, 500, 0.0)
+    res0 = _gpu_solve(sysd, idx, cuda, lam=0.0, eta=1, alpha=1.0, K=0)
+    assert res0.k_done == 0 and torch.count_nonzero(res0.x) == 0
+    # eta = 1, alpha = 1, lambda = 0: randomized Kaczmarz (Sec. 5, special cases)
+    res = _gpu_solve(sysd, idx, cuda, lam=0.0, eta=1, alpha=1.0, K=500)
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 0.0, 1, 1.0, 500, idx)
+    assert _rel(res.x.cpu().numpy(), ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("grid", [1, 6])
+def test_dense_device_errors(cuda, rsk_lib, grid):
+    import torch
+    from paper_2203_10838_amd import rsk
+    sysd, idx = _case(200, 64, 4, "f32", 11, 4, 30, 0.5)
+    # index out of range at step 7
+    bad = idx.copy()
+    bad[7 * 4 + 2] = 200
+    with pytest.raises(rsk.RskError) as e:
+        _gpu_solve(sysd, bad, cuda, lam=0.5, eta=4, alpha=1.0, K=30, grid=grid)
+    assert e.value.name == "RSK_ERR_INDEX_RANGE"
+    # a referenced zero row
+    z = dict(sysd)
+    z["A"] = sysd["A"].copy()
+    z["A"][idx[5 * 4 + 1]] = 0.0
+    with pytest.raises(rsk.RskError) as e:
+        _gpu_solve(z, idx, cuda, lam=0.5, eta=4, alpha=1.0, K=30, grid=grid)
+    assert e.value.name == "RSK_ERR_ZERO_ROW"
+    # relaxation far beyond the stability bound: the iterate blows up
+    with pytest.raises(rsk.RskError) as e:
+        _gpu_solve(sysd, inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), 3000, 4, 5), cuda,
+                   lam=0.5, eta=4, alpha=1e6, K=3000, grid=grid)
+    assert e.value.name == "RSK_ERR_NONFINITE"
