@@ -94,6 +94,7 @@ typedef struct {
   void *y_out;                 /* nullable device array (m, dtype of A), in/out: y[tau_t] -= c_t, so x* = A^T y */
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
+  int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register tile */
 } rsk_params;
 
 /* Version of this ABI (RSK_ABI_VERSION). */

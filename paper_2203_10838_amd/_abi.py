@@ -30,7 +30,7 @@ class RskParams(ctypes.Structure):
     _fields_ = [("lambda_", c_dbl), ("eta", c_i32), ("alpha", c_dbl), ("alpha_k", c_vp), ("K", c_i64),
                 ("index_stream", c_vp), ("stream_offset", c_i64), ("rownorm2", c_vp), ("warm_start", c_i32),
                 ("x_ref", c_vp), ("check_every", c_i64), ("tol", c_dbl), ("err_hist", c_vp), ("y_out", c_vp),
-                ("status_dev", c_vp), ("grid", c_i32)]
+                ("status_dev", c_vp), ("grid", c_i32), ("kernel", c_i32)]
 
 
 # name -> (restype, argtypes); every symbol include/rsk.h declares

@@ -41,12 +41,15 @@ int32_t check_params(const rsk_params* p, int64_t m) {
   if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
   if (!p->rownorm2 || !p->status_dev) return RSK_ERR_INVALID_ARG;
   if (p->check_every < 0 || !(p->tol >= 0.0) || p->grid < 0) return RSK_ERR_INVALID_ARG;
+  if (p->kernel < 0 || p->kernel > 2) return RSK_ERR_INVALID_ARG;
   if (p->x_ref && p->check_every > 0 && p->err_hist == nullptr && p->tol <= 0.0) return RSK_ERR_INVALID_ARG;
   (void)m;
   return RSK_OK;
 }
 
 struct DensePlan {
+  int kernel;  // 1 general, 2 register tile
+  int nt, rp, cpl;
   int vec, G, two_hop, tile_cache, wq_max, lpr, W;
   int64_t nchunks;
   size_t offP, offC, offM, bytes;
@@ -76,9 +79,44 @@ int32_t check_dense(const rsk_dense* A) {
   return RSK_OK;
 }
 
+// float32 register-tile plan: one 1024-thread workgroup per CU, slices of at
+// most 5 units of 16 floats, eta <= 1024. Returns false if it does not apply.
+bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
+  if (A->dtype != RSK_F32 || (A->n % 4) != 0 || (A->ld % 4) != 0 || (((uintptr_t)A->val) % 16) != 0) return false;
+  const int64_t nchunks = (A->n + 3) / 4;
+  const int64_t nunits = (nchunks + 3) / 4;
+  const int cus = device_cus();
+  int G = p->grid > 0 ? p->grid : cus;
+  if (G > nunits) G = (int)nunits;
+  if (G > 256) return false;
+  if (G < 1) return false;
+  const int cpl = (int)((nunits + G - 1) / G);
+  if (cpl > rsk::kRtMaxCPL || p->eta > rsk::kRtMaxEta) return false;
+  const int nt = p->eta <= 768 ? 1024 : 512;
+  const int rp = (p->eta + nt / 4 - 1) / (nt / 4);
+  if (rsk::dense_rt_max_grid(nt, rp, cpl) < G) return false;
+  pl->kernel = 2; pl->nt = nt; pl->rp = rp; pl->cpl = cpl;
+  pl->vec = 4; pl->W = 1; pl->nchunks = nchunks; pl->G = G;
+  pl->wq_max = 4 * cpl; pl->lpr = 4; pl->tile_cache = 0;
+  pl->two_hop = ((int64_t)G * p->eta) > kOneHopWords;
+  // each wave reduces at most kRtOwnMax rows per step
+  const int waves = nt / 64;
+  if (!pl->two_hop && p->eta > rsk::kRtOwnMax * waves) pl->two_hop = 1;
+  if (pl->two_hop && (p->eta + G - 1) / G > rsk::kRtOwnMax * waves) return false;
+  const int cap = dense_grid_cap(A, p);
+  dense_ws_layout(cap > G ? cap : G, p->eta, 1, pl);
+  return true;
+}
+
 template <typename T>
 int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   const size_t s = sizeof(T);
+  pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0;
+  if (p->kernel == 2 || (p->kernel == 0 && A->dtype == RSK_F32 &&
+                         (double)p->eta * (double)A->n * 4.0 >= 4.0 * 1024 * 1024)) {
+    if (plan_dense_rt(A, p, pl)) return RSK_OK;
+    if (p->kernel == 2) return RSK_ERR_UNSUPPORTED;
+  }
   const int vmax = (int)(16 / s);
   pl->vec = ((A->ld % vmax) == 0 && (((uintptr_t)A->val) % 16) == 0) ? vmax : 1;
   pl->W = (int)(s / 4);
@@ -145,6 +183,11 @@ int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, vo
   a.nchunks = pl.nchunks; a.wq_max = pl.wq_max; a.lpr = pl.lpr;
   if (rsk::launch_zero_words((u64*)w, pl.bytes / sizeof(u64), stream) != hipSuccess) return RSK_ERR_HIP;
   if (rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
+  if (pl.kernel == 2) {
+    if (rsk::launch_dense_rt(*reinterpret_cast<rsk::DenseArgs<float>*>(&a), pl.nt, pl.rp, pl.cpl, stream) != hipSuccess)
+      return RSK_ERR_HIP;
+    return RSK_OK;
+  }
   int maxg = 0;
   if (rsk::launch_dense<T>(a, pl.vec, stream, &maxg) != hipSuccess) return RSK_ERR_HIP;
   return RSK_OK;

@@ -1,0 +1,349 @@
+// Dense RSKA, float32, register-tile persistent kernel (the throughput path).
+//
+// Same iteration and exchange protocol as rska_dense_persistent, laid out for
+// HBM streaming on gfx950:
+//  * NT threads per workgroup (1024, or 512 for eta > 768), one workgroup per
+//    CU, each owning a column slice of at most 4*CPL float4 chunks (slices
+//    are whole 64-byte units).
+//  * Lane l of wave w holds row t = p*(NT/4) + 16*w + (l % 16) of pass p and
+//    chunks q = (l / 16) + 4r, r < CPL. The 16 lanes that hold one chunk
+//    column form one DPP row, so the column sums of the update reduce with
+//    four row_ror adds; the 4 lanes that hold one row reduce with two swaps.
+//  * All RP*CPL float4 loads of a step are issued before the first is used
+//    (up to 20 KB in flight per CU). The addresses never depend on a
+//    predicate: a chunk outside the slice is clamped into the row and meets a
+//    zero x entry in the dot, and its column sum is discarded.
+//  * The step's tile stays in VGPRs from the dots to the transposed update:
+//    A is read from HBM exactly once per step.
+//  * Each pass publishes its partial dots as soon as its own loads have
+//    landed; the next step's indices, and b and ||a||^2 of the rows this
+//    workgroup reduces, are fetched a step ahead.
+//  * Summation orders are fixed, so results are bitwise reproducible.
+#include "rsk_device.hpp"
+#include "rsk_kernels.hpp"
+
+namespace rsk {
+
+namespace {
+
+constexpr int kMaxG = 256;  // workgroups the exchange code is unrolled for (4 slots per lane)
+constexpr int kOwnMax = kRtOwnMax;  // rows one wave reduces per step
+
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+  float s = a.x * b.x;
+  s += a.y * b.y;
+  s += a.z * b.z;
+  s += a.w * b.w;
+  return s;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the 16 lanes of a DPP row; every lane of the row gets the sum.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp<0x128>(v);  // row_ror:8
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x122>(v);  // row_ror:2
+  v += dpp<0x121>(v);  // row_ror:1
+  return v;
+}
+
+}  // namespace
+
+template <int NT, int RP, int CPL>
+__global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
+  constexpr int kRtThreads = NT;
+  constexpr int kRtWaves = NT / 64;
+  constexpr int kRtRowsPerPass = kRtWaves * 16;
+  __shared__ float4 xs4[4 * CPL];                 // x* slice
+  __shared__ float4 xv4[4 * CPL];                 // x slice
+  __shared__ float4 red[kRtWaves][4 * CPL];       // per-wave column sums
+  __shared__ float cs[RP * kRtRowsPerPass];        // step coefficients
+  __shared__ double mon[2 * kRtWaves + 2];
+
+  const int g = blockIdx.x, G = a.G, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int eta = a.eta;
+  const int sl = lane >> 4, ri = lane & 15;
+
+  // slice in 4-chunk (64-byte) units
+  const int s = xcd_slice(g, G);
+  const int64_t nunits = (a.nchunks + 3) / 4;
+  const int64_t u0 = (int64_t)s * nunits / G, u1 = (int64_t)(s + 1) * nunits / G;
+  const int64_t q0 = u0 * 4;
+  int64_t q1 = u1 * 4;
+  if (q1 > a.nchunks) q1 = a.nchunks;
+  const int wq = (int)(q1 - q0);
+  const int64_t c0 = q0 * 4;
+  // last chunk of the row reachable from this slice (clamp target)
+  const int qlast = (int)(a.nchunks - 1 - q0);
+  float* xs = reinterpret_cast<float*>(xs4);
+  float* xv = reinterpret_cast<float*>(xv4);
+
+  // rows this workgroup reduces: a contiguous block (two hops) or all (one hop)
+  const int per = a.two_hop ? (eta + G - 1) / G : eta;
+  const int ot0 = a.two_hop ? g * per : 0;
+  const int ot1 = (ot0 + per < eta) ? ot0 + per : eta;
+
+  for (int j = tid; j < 16 * CPL; j += kRtThreads) {
+    const int64_t c = c0 + j;
+    const float z = (a.warm && j < wq * 4 && c < a.n) ? a.x_star[c] : 0.f;
+    xs[j] = z;
+    xv[j] = shrink(z, a.lambda);
+  }
+
+  // Prefetched per-step inputs: the lane's rows of the step (tile rows), and
+  // for the rows this wave reduces, b and ||a||^2 of the sampled rows.
+  int rowi[RP];
+  float ob[kOwnMax], orn[kOwnMax];
+  int lerr = 0;
+  auto fetch_rows = [&](int64_t k, int (&ri_out)[RP], int& err) {
+    const int32_t* tk = a.idx + k * (int64_t)eta;
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const int t = p * kRtRowsPerPass + 16 * wave + ri;
+      int i = -1;
+      if (t < eta) {
+        i = tk[t];
+        if (i < 0 || (int64_t)i >= a.m) { err = ST_INDEX; i = -1; }
+      }
+      ri_out[p] = i;
+    }
+  };
+  auto fetch_owned = [&](int64_t k) {
+    const int32_t* tk = a.idx + k * (int64_t)eta;
+#pragma unroll
+    for (int j = 0; j < kOwnMax; ++j) {
+      const int t = ot0 + wave + kRtWaves * j;
+      ob[j] = 0.f;
+      orn[j] = 1.f;
+      if (lane == 0 && t < ot1) {
+        const int i = tk[t];
+        if (i >= 0 && (int64_t)i < a.m) { ob[j] = a.b[i]; orn[j] = a.r2[i]; }
+      }
+    }
+  };
+  if (a.K > 0) {
+    fetch_rows(0, rowi, lerr);
+    fetch_owned(0);
+  }
+  int64_t k_done = 0;
+  int stop_code = 0;
+  // every workgroup read the same indices, so all skip the loop alike
+  if (__syncthreads_or(lerr)) stop_code = ST_INDEX;
+
+  for (int64_t k = 0; k < a.K && !stop_code; ++k) {
+    // Re-derive the lane coordinates from an opaque copy of the thread id each
+    // step: otherwise the compiler hoists every lane-dependent address out of
+    // the loop and keeps it in VGPRs that the register tile needs.
+    int tidl = threadIdx.x;
+    asm volatile("" : "+v"(tidl));
+    const int tid = tidl, lane = tidl & 63, wave = tidl >> 6, sl = lane >> 4, ri = lane & 15;
+    const unsigned tag = (unsigned)(k + 1);
+    const float ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
+    u64* xP = a.xP + (size_t)(k & 1) * G * eta;
+    const bool has_next = k + 1 < a.K;
+
+    // every load of the step (rows past eta read row 0 and are never used)
+    float4 tile[RP][CPL];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const float* rowp = a.A + (int64_t)(rowi[p] < 0 ? 0 : rowi[p]) * a.ld + c0;
+#pragma unroll
+      for (int r = 0; r < CPL; ++r) {
+        const int q = sl + 4 * r;  // clamped into the row: past the slice it meets x = 0
+        tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
+      }
+    }
+    int rown[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) rown[p] = -1;
+    int nerr = 0;
+    if (has_next) fetch_rows(k + 1, rown, nerr);
+
+    // partial dots, published pass by pass
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      float acc = 0.f;
+#pragma unroll
+      for (int r = 0; r < CPL; ++r) acc += dot4(tile[p][r], xv4[sl + 4 * r]);
+      acc += __shfl_xor(acc, 16);
+      acc += __shfl_xor(acc, 32);
+      const int t = p * kRtRowsPerPass + 16 * wave + ri;
+      if (sl == 0 && t < eta) put_tagged(&xP[(size_t)g * eta + t], acc, tag);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // reduce the owned rows over the G workgroups; c_t = (alpha/eta)(r_t - b)/||a||^2
+#pragma unroll
+    for (int j = 0; j < kOwnMax; ++j) {
+      const int t = ot0 + wave + kRtWaves * j;
+      if (t < ot1) {
+        float v[kMaxG / 64];
+        wait_tagged_batch(&xP[(size_t)lane * eta + t], (size_t)64 * eta, (G - lane + 63) / 64, tag, v, lerr);
+        float sum = 0.f;
+#pragma unroll
+        for (int i = 0; i < kMaxG / 64; ++i) sum += v[i];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+          float c;
+          if (orn[j] == 0.f) { c = NAN; set_status(a.status, ST_ZERO_ROW); }
+          else c = (ak / (float)eta) * (sum - ob[j]) / orn[j];
+          if (a.two_hop) put_tagged(&a.xC[t], c, tag);
+          else cs[t] = c;
+        }
+      }
+    }
+    if (has_next) fetch_owned(k + 1);
+    if (a.two_hop && tid < kRtRowsPerPass) {
+      float v[RP];
+      wait_tagged_batch(&a.xC[tid], kRtRowsPerPass, (eta - tid + kRtRowsPerPass - 1) / kRtRowsPerPass, tag, v,
+                        lerr);
+#pragma unroll
+      for (int i = 0; i < RP; ++i)
+        if (tid + kRtRowsPerPass * i < eta) cs[tid + kRtRowsPerPass * i] = v[i];
+    }
+    if (lerr) set_status(a.status, lerr);
+    if (__syncthreads_or(lerr)) { stop_code = ST_ABORTED; break; }
+
+    // transposed update: per chunk slot, sum over own rows, then the 16 lanes
+    // holding that chunk, then the waves
+    float cp[RP];
+    int bad = 0;
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const int t = p * kRtRowsPerPass + 16 * wave + ri;
+      cp[p] = t < eta ? cs[t] : 0.f;
+      bad |= !isfinite(cp[p]);
+    }
+    if (a.y && g == 0)
+      for (int t = tid; t < eta; t += kRtThreads) atomicAdd(&a.y[a.idx[k * (int64_t)eta + t]], -cs[t]);
+#pragma unroll
+    for (int r = 0; r < CPL; ++r) {
+      float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < RP; ++p) {
+        d.x += cp[p] * tile[p][r].x;
+        d.y += cp[p] * tile[p][r].y;
+        d.z += cp[p] * tile[p][r].z;
+        d.w += cp[p] * tile[p][r].w;
+      }
+      d.x = row16_sum(d.x);
+      d.y = row16_sum(d.y);
+      d.z = row16_sum(d.z);
+      d.w = row16_sum(d.w);
+      if (ri == 0) red[wave][sl + 4 * r] = d;
+    }
+    // one barrier publishes red[] and agrees on a non-finite coefficient
+    // (every workgroup holds the same c_t, so all stop at this step)
+    if (__syncthreads_or(bad)) { stop_code = ST_NONFINITE; break; }
+    if (tid < 4 * wq) {  // chunks past the slice carry clamped data: discarded
+      const int q = tid >> 2, e = tid & 3;
+      float dsum = 0.f;
+      for (int w = 0; w < kRtWaves; ++w) {
+        const float4 v = red[w][q];
+        dsum += e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+      }
+      const float z = xs[tid] - dsum;
+      xs[tid] = z;
+      xv[tid] = shrink(z, a.lambda);
+    }
+    k_done = k + 1;
+    // the next step's indices were checked by every workgroup alike
+    const int next_bad = __syncthreads_or(nerr);
+
+    if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
+      const unsigned mtag = (unsigned)((k + 1) / a.check_every);
+      double e2 = 0.0, r2s = 0.0;
+      for (int j = tid; j < wq * 4; j += kRtThreads) {
+        const int64_t c = c0 + j;
+        if (c < a.n) {
+          const double rf = (double)a.xref[c];
+          const double d = (double)xv[j] - rf;
+          e2 += d * d;
+          r2s += rf * rf;
+        }
+      }
+      e2 = wave_sum(e2);
+      r2s = wave_sum(r2s);
+      if (lane == 0) { mon[2 * wave] = e2; mon[2 * wave + 1] = r2s; }
+      __syncthreads();
+      if (tid == 0) {
+        double se = 0.0, sr = 0.0;
+        for (int w = 0; w < kRtWaves; ++w) { se += mon[2 * w]; sr += mon[2 * w + 1]; }
+        put_tagged(&a.xM[(size_t)g * 4], se, mtag);
+        put_tagged(&a.xM[(size_t)g * 4 + 2], sr, mtag);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        double se = 0.0, sr = 0.0;
+        for (int q = lane; q < G; q += 64) {
+          se += wait_tagged<double>(&a.xM[(size_t)q * 4], mtag, lerr);
+          sr += wait_tagged<double>(&a.xM[(size_t)q * 4 + 2], mtag, lerr);
+        }
+        se = wave_sum(se);
+        sr = wave_sum(sr);
+        if (lane == 0) {
+          const double err = sr > 0.0 ? sqrt(se / sr) : sqrt(se);
+          if (g == 0 && a.err_hist) a.err_hist[mtag - 1] = err;
+          mon[2 * kRtWaves] = err;
+        }
+      }
+      if (lerr) set_status(a.status, lerr);
+      if (__syncthreads_or(lerr)) { stop_code = ST_ABORTED; break; }
+      if (a.tol > 0.0 && mon[2 * kRtWaves] <= a.tol) break;
+    }
+    if (next_bad) { stop_code = ST_INDEX; break; }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) rowi[p] = rown[p];
+  }
+  if (stop_code && tid == 0) set_status(a.status, stop_code);
+  __syncthreads();
+  for (int j = tid; j < wq * 4; j += kRtThreads) {
+    const int64_t c = c0 + j;
+    if (c < a.n) { a.x_star[c] = xs[j]; a.x[c] = xv[j]; }
+  }
+  if (g == 0 && tid == 0) a.status[1] = (int)k_done;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <int NT, int RP, int CPL>
+static void* rt_ptr() {
+  return reinterpret_cast<void*>(&rska_dense_rt<NT, RP, CPL>);
+}
+
+// 1024 threads for eta <= 768 (RP <= 3), 512 threads (256 VGPRs a lane) for 768 < eta <= 1024.
+static void* rt_kernel(int nt, int rp, int cpl) {
+#define RT_CASE(N, R, C) if (nt == N && rp == R && cpl == C) return rt_ptr<N, R, C>();
+#define RT_CPL(N, R) RT_CASE(N, R, 1) RT_CASE(N, R, 2) RT_CASE(N, R, 3) RT_CASE(N, R, 4) RT_CASE(N, R, 5)
+  RT_CPL(1024, 1) RT_CPL(1024, 2) RT_CPL(1024, 3)
+  RT_CPL(512, 7) RT_CPL(512, 8)
+#undef RT_CPL
+#undef RT_CASE
+  return nullptr;
+}
+
+int dense_rt_max_grid(int nt, int rp, int cpl) {
+  void* fn = rt_kernel(nt, rp, cpl);
+  if (!fn) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) != hipSuccess) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, hipStream_t stream) {
+  void* fn = rt_kernel(nt, rp, cpl);
+  if (!fn) return hipErrorInvalidValue;
+  if (a.G > kMaxG || dense_rt_max_grid(nt, rp, cpl) < a.G) return hipErrorCooperativeLaunchTooLarge;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(fn, dim3(a.G), dim3(nt), args, 0, stream);
+}
+
+}  // namespace rsk

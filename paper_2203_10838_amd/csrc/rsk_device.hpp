@@ -71,6 +71,34 @@ __device__ __forceinline__ T wait_tagged(const u64* s, unsigned tag, int& err) {
   return v;
 }
 
+// Wait until the `cnt` (<= N) float slots base[i*stride] all carry `tag`.
+// All pending slots are loaded before any is checked, so the waits of one
+// lane overlap instead of costing one round trip each.
+template <int N>
+__device__ __forceinline__ void wait_tagged_batch(const u64* base, size_t stride, int cnt, unsigned tag,
+                                                  float (&v)[N], int& err) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = 0.f;
+  if (err || cnt <= 0) return;
+  unsigned pending = cnt >= 32 ? 0xffffffffu : ((1u << cnt) - 1u);
+  unsigned spins = 0;
+  for (;;) {
+    u64 w[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = ((pending >> i) & 1u) ? xload(base + (size_t)i * stride) : 0ull;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (((pending >> i) & 1u) && (unsigned)(w[i] >> 32) == tag) {
+        v[i] = __uint_as_float((unsigned)w[i]);
+        pending &= ~(1u << i);
+      }
+    }
+    if (!pending) return;
+    if (++spins > kSpinLimit) { err = ST_ABORTED; return; }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // First error wins.
 __device__ __forceinline__ void set_status(int* status, int code) {
   if (code) atomicCAS(status, 0, code);

@@ -56,6 +56,11 @@ template <typename T>
 hipError_t launch_rownorm2_csr(const int64_t* row_ptr, const T* val, int64_t m, T* r2, hipStream_t stream);
 
 hipError_t launch_zero_words(u64* p, size_t nwords, hipStream_t stream);
+
+// float32 register-tile kernel: NT threads, RP row passes of NT/4 rows, CPL float4 chunks per lane
+int dense_rt_max_grid(int nt, int rp, int cpl);
+hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, hipStream_t stream);
+constexpr int kRtMaxEta = 1024, kRtMaxCPL = 5, kRtOwnMax = 4;
 hipError_t launch_zero_status(int* status, hipStream_t stream);
 
 // Largest co-resident grid for the dense kernel with these sizes (0 if none).

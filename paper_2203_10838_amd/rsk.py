@@ -84,7 +84,7 @@ class SolveResult:
 
 def make_params(*, lam, eta, alpha, K, index_stream, rownorm2_t, status_dev, stream_offset=0, alpha_k=None,
                 warm_start=False, x_ref=None, check_every=0, tol=0.0, err_hist=None, y_out=None, grid=0,
-                dtype=None) -> _abi.RskParams:
+                kernel=0, dtype=None) -> _abi.RskParams:
     if K > 0:
         _dev(index_stream, "index_stream", torch.int32, stream_offset + K * eta)
     return _abi.RskParams(
@@ -94,7 +94,7 @@ def make_params(*, lam, eta, alpha, K, index_stream, rownorm2_t, status_dev, str
         _dev(rownorm2_t, "rownorm2", dtype), 1 if warm_start else 0,
         _dev(x_ref, "x_ref", dtype), int(check_every), float(tol),
         _dev(err_hist, "err_hist", torch.float64), _dev(y_out, "y_out", dtype),
-        _dev(status_dev, "status_dev", torch.int32, 2), int(grid))
+        _dev(status_dev, "status_dev", torch.int32, 2), int(grid), int(kernel))
 
 
 def workspace_size_dense(A: torch.Tensor, params: _abi.RskParams) -> int:
@@ -115,7 +115,7 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
                 index_stream: torch.Tensor, stream_offset: int = 0, alpha_k: Optional[torch.Tensor] = None,
                 rownorm2_t: Optional[torch.Tensor] = None, x_star: Optional[torch.Tensor] = None,
                 warm_start: bool = False, x_ref: Optional[torch.Tensor] = None, check_every: int = 0,
-                tol: float = 0.0, y_out: Optional[torch.Tensor] = None, grid: int = 0,
+                tol: float = 0.0, y_out: Optional[torch.Tensor] = None, grid: int = 0, kernel: int = 0,
                 workspace: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
     """K steps of RSKA (eq. (rska), Algorithm 1) on a dense system, one persistent launch.
 
@@ -140,7 +140,7 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
     params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
                          status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k,
                          warm_start=warm_start, x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist,
-                         y_out=y_out, grid=grid, dtype=dt)
+                         y_out=y_out, grid=grid, kernel=kernel, dtype=dt)
     if y_out is not None:
         _dev(y_out, "y_out", dt, m)
     d = dense_desc(A)

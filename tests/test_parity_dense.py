@@ -164,3 +164,39 @@ def test_dense_device_errors(cuda, rsk_lib, grid):
         _gpu_solve(sysd, inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), 3000, 4, 5), cuda,
                    lam=0.5, eta=4, alpha=1e6, K=3000, grid=grid)
     assert e.value.name == "RSK_ERR_NONFINITE"
+
+
+@pytest.mark.parametrize("m,n,eta,K,grid", [
+    (3000, 1280, 300, 60, 16),    # 1024 threads, 2 row passes, 5 chunks a lane, two-hop
+    (3000, 1280, 700, 30, 32),    # 512 threads, 6 row passes, 3 chunks a lane
+    (2000, 1280, 40, 200, 20),    # one-hop reduce (G*eta <= 4096)
+    (2500, 1000, 130, 80, 13),    # ragged slices: 62.5 units over 13 workgroups
+    (4000, 2048, 1024, 20, 128),  # largest eta of the register tile
+])
+def test_register_tile_kernel_matches_oracle(cuda, rsk_lib, m, n, eta, K, grid):
+    import torch
+    sysd, idx = _case(m, n, max(1, n // 25), "f32", 4321 + eta, eta, K, 1.0)
+    alpha = _alpha_star(sysd["A"], eta)
+    res = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=eta, alpha=alpha, K=K, grid=grid, kernel=2)
+    assert res.status == 0 and res.k_done == K
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 1.0, eta, alpha, K, idx)
+    assert _rel(res.x_star.cpu().numpy(), ref["z"]) <= TOL["f32"]
+    assert _rel(res.x.cpu().numpy(), ref["x"]) <= TOL["f32"]
+    again = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=eta, alpha=alpha, K=K, grid=grid, kernel=2)
+    assert torch.equal(again.x_star, res.x_star)
+
+
+def test_register_tile_kernel_errors_and_monitor(cuda, rsk_lib):
+    from paper_2203_10838_amd import rsk
+    sysd, idx = _case(1500, 512, 20, "f32", 99, 64, 400, 0.5)
+    alpha = _alpha_star(sysd["A"], 64)
+    bad = idx.copy()
+    bad[3 * 64 + 10] = -1
+    with pytest.raises(rsk.RskError) as e:
+        _gpu_solve(sysd, bad, cuda, lam=0.5, eta=64, alpha=alpha, K=400, grid=8, kernel=2)
+    assert e.value.name == "RSK_ERR_INDEX_RANGE"
+    xr = _to(sysd["xhat"], cuda)
+    res = _gpu_solve(sysd, idx, cuda, lam=0.5, eta=64, alpha=alpha, K=400, grid=8, kernel=2, x_ref=xr,
+                     check_every=20)
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 0.5, 64, alpha, 400, idx, check_every=20, xref=sysd["xhat"])
+    assert np.allclose(res.err_hist.cpu().numpy(), ref["hist"], rtol=1e-3, atol=1e-6)
