@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the averaged randomized sparse Kaczmarz (RSKA) hot path on one MI355X.
+
+Workload (the large dense configuration): A 100000 x 20000 float32 with i.i.d.
+N(0,1) entries drawn on the device, x_hat with 200 N(0,1) nonzeros, b = A x_hat
+plus Gaussian-direction noise of norm 1% of ||A x_hat||, lambda = 5, rows
+sampled with probability proportional to ||a_i||^2, alpha = alpha*(eta) of the
+Corollary (uniform weights). All inputs are synthetic and seeded.
+
+One benchmark step is one call of rsk_avg_solve_dense running --iters RSKA
+iterations (eta = 1024 by default) over inputs already resident in HBM. The
+JSON line reports the algorithmic HBM bandwidth of those iterations
+(eta*n*4 bytes of rows plus 12 bytes of index, b and ||a||^2 per sampled row,
+per iteration), the roofline of the persistent kernel, the FP64 CPU oracle on a
+bounded sample of the same workload, an eta sweep (us/step, GB/s) and the time
+to the error plateau per eta.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+M, N, S_NNZ, LAM, NOISE = 100_000, 20_000, 200, 5.0, 0.01
+SEED = 20310838 + 100
+ETAS = (1, 16, 64, 256, 1024)
+COPY_PROBE_BYTES = 1 << 30
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spectral_norm_sq(A, iters=40):
+    """sigma_max(A)^2 by power iteration on A^T A (float32 products, float64 bookkeeping)."""
+    import torch
+    g = torch.Generator(device=A.device)
+    g.manual_seed(1)
+    v = torch.randn(A.shape[1], generator=g, device=A.device, dtype=torch.float32)
+    v /= v.norm()
+    lam = 0.0
+    for _ in range(iters):
+        w = A.t().mv(A.mv(v))
+        lam = float(w.double().norm())
+        v = w / w.norm()
+    return lam
+
+
+def step_bytes(eta, n):
+    return eta * (n * 4 + 12)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("rsk_dense_rt.hip", "rsk_device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2203_10838_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(bytes_per_launch_alg):
+    """HBM bytes per launch measured by rocprofv3 counters (committed summary), if it matches this kernel."""
+    p = os.path.join(ROOT, "profiles", "dense_rt_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, b, weights, lam, eta, alpha, seconds=12.0, K=200):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload (rank 0, N=1):
+    up to K iterations or `seconds` of oracle time, on the rows those iterations sample."""
+    import oracle
+    from paper_2203_10838_amd import inputs
+
+    idx = inputs.index_stream(weights, K, eta, SEED + 11)
+    uniq = np.unique(idx)
+    rows = A[torch_index(uniq, A.device)].double().cpu().numpy()
+    remap = np.searchsorted(uniq, idx).astype(np.int32)
+    bsub = b.astype(np.float64)[uniq]
+    t0 = time.perf_counter()
+    done = 0
+    z = None
+    while time.perf_counter() - t0 < seconds and done < K:
+        r = oracle.rska_dense(rows, bsub, lam, eta, alpha, 1, remap, off=done * eta, z0=z)
+        z = r["z"]
+        done += 1
+    dt = time.perf_counter() - t0
+    gbs = done * step_bytes(eta, A.shape[1]) / dt / 1e9
+    return {"value": gbs, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} RSKA iterations at eta={eta} on the same 100000x20000 system "
+                      f"(FP64 C loops, one thread, {dt:.1f} s; {done / dt:.2f} iterations/s)"}
+
+
+def torch_index(np_idx, device):
+    import torch
+    return torch.from_numpy(np.asarray(np_idx, dtype=np.int64)).to(device)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eta", type=int, default=1024)
+    ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
+              "(multi-GPU column sharding is a design note, not an implementation); use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_10838_amd import inputs, params, rsk
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
+    A = sysd["A"]
+    b = torch.from_numpy(sysd["b"]).to(dev)
+    xhat = torch.from_numpy(sysd["xhat"]).to(dev)
+    weights = sysd["weights"]
+    r2 = rsk.rownorm2(A)
+    fro2 = float(weights.sum())
+    smax2 = spectral_norm_sq(A)
+    torch.cuda.synchronize()
+    log(f"[bench] data ready in {time.time() - t0:.1f}s; ||A||_F^2/sigma_max^2 = {fro2 / smax2:.1f}")
+
+    def solve(eta, K, idx, **kw):
+        return rsk.solve_dense(A, b, lam=LAM, eta=eta, alpha=params.optimal_alpha(eta, fro2, smax2), K=K,
+                               index_stream=idx, rownorm2_t=r2, **kw)
+
+    # ---------------- headline: eta = args.eta, --iters iterations per step
+    eta, iters = args.eta, args.iters
+    nstream = (args.warmup + args.steps) * iters
+    idx = torch.from_numpy(inputs.index_stream(weights, nstream, eta, SEED + 1)).to(dev)
+    stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        # a plain device copy of known size, so that HBM byte counters read for
+        # the solver can be scaled by what they read for a known transfer
+        src = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for w in range(args.warmup):
+        solve(eta, iters, idx, stream_offset=w * iters * eta, check=False)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    per_launch = []
+    t_wall0 = time.perf_counter()
+    ev0.record(stream)
+    for s in range(args.steps):
+        e_a = torch.cuda.Event(enable_timing=True)
+        e_b = torch.cuda.Event(enable_timing=True)
+        e_a.record(stream)
+        res = solve(eta, iters, idx, stream_offset=(args.warmup + s) * iters * eta, check=False)
+        e_b.record(stream)
+        per_launch.append((e_a, e_b))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    st = res.status_dev.cpu().tolist()
+    if st[0] != 0:
+        raise RuntimeError(f"device status {st}")
+    total_ms = ev0.elapsed_time(ev1)
+    launch_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in per_launch]))
+    bytes_launch = iters * step_bytes(eta, N)
+    value = bytes_launch * args.steps / (total_ms * 1e-3) / 1e9
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    log(f"[bench] eta={eta}: {total_ms / args.steps:.3f} ms/step ({launch_ms * 1e3 / iters:.2f} us/iteration), "
+        f"{value:.1f} GB/s; wall {wall:.2f}s")
+
+    out = {
+        "metric": "time to rel.err 1e-5 & HBM GB/s: plain vs batched RSK-avg; adjoint steps/s",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain RSK-avg, dense 100000x20000 float32, noisy (1%), lambda=5, "
+                               f"eta={eta}, alpha=alpha*, {iters} iterations per step",
+                   "m": M, "n": N, "eta": eta, "iters_per_step": iters},
+        "us_per_iteration": round(launch_ms * 1e3 / iters, 3),
+    }
+    traffic = traffic_from_profile(bytes_launch)
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                       "kernel": "rska_dense_rt (register-tile persistent kernel)",
+                       "bytes_per_launch": bytes_launch}
+
+    # ---------------- eta sweep and time to plateau
+    if not args.no_sweep:
+        sweep = []
+        for e in ETAS:
+            K = max(64, min(20000, int(2e9 / (e * N * 4))))
+            ix = torch.from_numpy(inputs.index_stream(weights, K, e, SEED + 2)).to(dev)
+            solve(e, K, ix, check=False)
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            solve(e, K, ix, check=False)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            ms = a0.elapsed_time(a1)
+            sweep.append({"eta": e, "us_per_iteration": round(ms * 1e3 / K, 3),
+                          "GB/s": round(K * step_bytes(e, N) / (ms * 1e-3) / 1e9, 2)})
+            log(f"[bench] sweep eta={e}: {sweep[-1]}")
+        out["eta_sweep"] = sweep
+        out["time_to_plateau"] = plateau_runs(solve, inputs, weights, xhat, dev, stream)
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(A, sysd["b"], weights, LAM, eta, params.optimal_alpha(eta, fro2, smax2))
+    print(json.dumps(out), flush=True)
+
+
+def plateau_runs(solve, inputs, weights, xhat, dev, stream):
+    """Per eta: a calibration run with the in-kernel monitor finds the error plateau and the first
+    checkpoint within 5% of it; a second run of exactly that many steps, monitor off, is timed."""
+    import torch
+    res = []
+    budget = {1: 1_600_000, 16: 200_000, 64: 60_000, 256: 20_000, 1024: 8_000}
+    for e in ETAS:
+        Kmax = budget[e]
+        C = max(1, Kmax // 400)
+        ix = torch.from_numpy(inputs.index_stream(weights, Kmax, e, SEED + 3)).to(dev)
+        cal = solve(e, Kmax, ix, x_ref=xhat, check_every=C)
+        h = cal.err_hist.cpu().numpy()
+        tail = h[int(len(h) * 0.8):]
+        plateau = float(np.median(tail))
+        kstar = (int(np.argmax(h <= 1.05 * plateau)) + 1) * C
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        solve(e, kstar, ix, check=False)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        ms = a0.elapsed_time(a1)
+        res.append({"eta": e, "plateau_rel_err": plateau, "steps_to_plateau": kstar, "ms_to_plateau": round(ms, 3),
+                    "max_steps_run": Kmax})
+        log(f"[bench] plateau eta={e}: {res[-1]}")
+    return res
+
+
+if __name__ == "__main__":
+    main()

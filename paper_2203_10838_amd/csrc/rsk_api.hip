@@ -112,8 +112,10 @@ template <typename T>
 int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   const size_t s = sizeof(T);
   pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0;
+  // the register-tile kernel pays one cross-CU exchange per step on a full
+  // grid: worth it once a step moves more than a few hundred KB of rows
   if (p->kernel == 2 || (p->kernel == 0 && A->dtype == RSK_F32 &&
-                         (double)p->eta * (double)A->n * 4.0 >= 4.0 * 1024 * 1024)) {
+                         (double)p->eta * (double)A->n * 4.0 >= 512.0 * 1024)) {
     if (plan_dense_rt(A, p, pl)) return RSK_OK;
     if (p->kernel == 2) return RSK_ERR_UNSUPPORTED;
   }
