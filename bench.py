@@ -235,10 +235,44 @@ def main():
         out["eta_sweep"] = sweep
         out["time_to_plateau"] = plateau_runs(solve, inputs, weights, xhat, dev, stream)
 
+    if not args.no_sweep:
+        out["csr"] = csr_run(dev, stream)
+
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, sysd["b"], weights, LAM, eta, params.optimal_alpha(eta, fro2, smax2))
     print(json.dumps(out), flush=True)
+
+
+def csr_run(dev, stream, K=20000):
+    """Sparse (tomography-like) workload: m = 2^20, n = 2^18, 32 uniform nonzeros a row, x_hat 0.5% dense,
+    b = A x_hat, lambda = 2, eta = 512, alpha = alpha* ~ 510, K = 20000 steps in one persistent launch."""
+    import torch
+    from paper_2203_10838_amd import inputs, rsk
+    m, n, eta = 1 << 20, 1 << 18, 512
+    c = inputs.csr_system(m, n, 32, int(0.005 * n), seed=20310838 + 200)
+    w = inputs.csr_sampling_weights(c["row_ptr"], c["val"])
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rp, col, val, b, xh = T(c["row_ptr"]), T(c["col"]), T(c["val"]), T(c["b"]), T(c["xhat"])
+    r2 = rsk.rownorm2_csr(rp, col, val, n)
+    idx = T(inputs.index_stream(w, K, eta, 20310838 + 201))
+    rsk.solve_csr(rp, col, val, n, b, lam=2.0, eta=eta, alpha=510.0, K=50, index_stream=idx, rownorm2_t=r2)
+    torch.cuda.synchronize()
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    res = rsk.solve_csr(rp, col, val, n, b, lam=2.0, eta=eta, alpha=510.0, K=K, index_stream=idx, rownorm2_t=r2,
+                        x_ref=xh, check_every=K, check=False)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ms = a0.elapsed_time(a1)
+    step_b = eta * (32 * 8 + 16 + 12)
+    out = {"workload": "CSR 1048576x262144, 32 nnz/row, eta=512, lambda=2, 20000 steps",
+           "us_per_iteration": round(ms * 1e3 / K, 3), "ms_total": round(ms, 2),
+           "GB/s": round(K * step_b / (ms * 1e-3) / 1e9, 3),
+           "rel_err_at_K": float(res.err_hist.cpu().numpy()[-1]), "status": res.status_dev.cpu().tolist()}
+    log(f"[bench] csr: {out}")
+    return out
 
 
 def plateau_runs(solve, inputs, weights, xhat, dev, stream):

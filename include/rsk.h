@@ -108,9 +108,11 @@ const char *rsk_status_string(int32_t status);
  * rownorm2: device, m entries of A's dtype. Accumulates in double.
  */
 int32_t rsk_rownorm2_dense(const rsk_dense *A, void *rownorm2, void *stream);
+int32_t rsk_rownorm2_csr(const rsk_csr *A, void *rownorm2, void *stream);
 
 /* Workspace bytes needed by the matching solve for this matrix and these parameters. */
 int32_t rsk_workspace_size_dense(const rsk_dense *A, const rsk_params *p, size_t *bytes);
+int32_t rsk_workspace_size_csr(const rsk_csr *A, const rsk_params *p, size_t *bytes);
 
 /*
  * K steps of RSKA on a dense system (eq. (rska), Algorithm 1), in one
@@ -123,6 +125,19 @@ int32_t rsk_workspace_size_dense(const rsk_dense *A, const rsk_params *p, size_t
  */
 int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
                             void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * The same iteration with A in CSR form (eq. (rska) with sparse rows).
+ * Runs as one persistent workgroup: a sparse step moves a few hundred KB
+ * and is bound by latency, which a single CU minimises (no cross-CU exchange).
+ * Columns hit by several sampled rows of a step are summed in int64 fixed
+ * point with a per-step power-of-two quantum (2^-41 of the step's largest
+ * contribution), so results are bitwise reproducible. eta <= 4096.
+ * Workspace: n int64 accumulators (rsk_workspace_size_csr), zeroed by the call.
+ * A column index outside [0, n) in a sampled row is RSK_ERR_INDEX_RANGE.
+ */
+int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, void *x_star, void *x,
+                          void *workspace, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -195,9 +195,76 @@ int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, vo
   return RSK_OK;
 }
 
+int32_t check_csr(const rsk_csr* A) {
+  if (!A || !A->row_ptr || !A->col || !A->val) return RSK_ERR_INVALID_ARG;
+  if (A->m <= 0 || A->n <= 0 || A->nnz < 0) return RSK_ERR_INVALID_ARG;
+  if (A->m > INT32_MAX || A->n > INT32_MAX) return RSK_ERR_UNSUPPORTED;
+  if (A->dtype != RSK_F32 && A->dtype != RSK_F64) return RSK_ERR_UNSUPPORTED;
+  return RSK_OK;
+}
+
+// n column accumulators plus one spare slot for empty lanes
+size_t csr_ws_bytes(const rsk_csr* A) { return align256((size_t)(A->n + 1) * sizeof(long long)); }
+
+template <typename T>
+int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* x_star, void* x, void* ws,
+                    size_t ws_bytes, hipStream_t stream) {
+  if (!ws || ws_bytes < csr_ws_bytes(A) || ((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  rsk::CsrArgs<T> a;
+  a.row_ptr = A->row_ptr; a.col = A->col; a.val = (const T*)A->val; a.m = A->m; a.n = A->n;
+  a.b = (const T*)b; a.r2 = (const T*)p->rownorm2;
+  a.lambda = (T)p->lambda; a.alpha = (T)p->alpha; a.alpha_k = (const T*)p->alpha_k;
+  a.eta = p->eta; a.K = p->K;
+  a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
+  a.x_star = (T*)x_star; a.x = (T*)x; a.warm = p->warm_start ? 1 : 0;
+  a.y = (T*)p->y_out;
+  a.xref = (const T*)p->x_ref; a.check_every = p->x_ref ? p->check_every : 0; a.tol = p->tol;
+  a.err_hist = p->err_hist; a.status = p->status_dev;
+  a.acc = (long long*)ws;
+  if (rsk::launch_zero_words((u64*)ws, (size_t)A->n + 1, stream) != hipSuccess) return RSK_ERR_HIP;
+  if (rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
+  if (rsk::launch_csr<T>(a, stream) != hipSuccess) return RSK_ERR_HIP;
+  return RSK_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t rsk_rownorm2_csr(const rsk_csr* A, void* rownorm2, void* stream) {
+  int32_t st = check_csr(A);
+  if (st) return st;
+  if (!rownorm2) return RSK_ERR_INVALID_ARG;
+  hipError_t e = A->dtype == RSK_F64
+      ? rsk::launch_rownorm2_csr<double>(A->row_ptr, (const double*)A->val, A->m, (double*)rownorm2, (hipStream_t)stream)
+      : rsk::launch_rownorm2_csr<float>(A->row_ptr, (const float*)A->val, A->m, (float*)rownorm2, (hipStream_t)stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_workspace_size_csr(const rsk_csr* A, const rsk_params* p, size_t* bytes) {
+  int32_t st = check_csr(A);
+  if (st) return st;
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (p->eta > rsk::kCsrMaxEta) return RSK_ERR_UNSUPPORTED;
+  *bytes = csr_ws_bytes(A);
+  return RSK_OK;
+}
+
+int32_t rsk_avg_solve_csr(const rsk_csr* A, const void* b, const rsk_params* p, void* x_star, void* x,
+                          void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_csr(A);
+  if (st) return st;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (!b || !x_star || !x) return RSK_ERR_INVALID_ARG;
+  if (p->eta > rsk::kCsrMaxEta) return RSK_ERR_UNSUPPORTED;
+  return A->dtype == RSK_F64
+      ? solve_csr_t<double>(A, b, p, x_star, x, workspace, ws_bytes, (hipStream_t)stream)
+      : solve_csr_t<float>(A, b, p, x_star, x, workspace, ws_bytes, (hipStream_t)stream);
+}
+
 
 int32_t rsk_abi_version(void) { return RSK_ABI_VERSION; }
 

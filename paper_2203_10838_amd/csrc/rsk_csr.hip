@@ -1,0 +1,242 @@
+// CSR RSKA: one persistent workgroup runs K steps of eq. (rska) / Algorithm 1
+// on a sparse A (row_ptr int64, col int32, val).
+//
+// A step of the sparse workloads moves little data (eta rows of a few dozen
+// nonzeros), so it is bound by latency, not bandwidth. One workgroup on one CU
+// keeps every access to x* and x inside one XCD's caches and needs no
+// cross-CU exchange at all.
+//
+// Per step, one thread per sampled row (chunks of 32 nonzeros held in registers):
+//   1. r_t = sum_p val_p x[col_p] - b_{tau_t};  c_t = (alpha_k/eta) r_t / ||a_{tau_t}||^2
+//   2. contributions v_p = c_t val_p are added into x*[col_p]. Columns hit by
+//      several sampled rows must sum in a fixed order to stay reproducible, so
+//      the contributions are accumulated as int64 fixed point with the step's
+//      power-of-two quantum q = 2^(e-40), e = exponent of max |v_p| (integer
+//      adds commute), and every column's total is applied once by the lane
+//      that swaps it out of the accumulator: x*_j -= total*q, x_j = S_lambda(x*_j).
+//      The quantisation error is below 2^-41 of the step's largest
+//      contribution, far under float32 resolution of the update.
+// x*, x and the accumulators live in global memory and are shared only within
+// the workgroup, so workgroup-scope atomics order them (device-scope atomics
+// would cost a serialized memory round trip each).
+#include "rsk_device.hpp"
+#include "rsk_kernels.hpp"
+
+namespace rsk {
+
+namespace {
+
+constexpr int kCsrThreads = 512;
+constexpr int kCsrWaves = kCsrThreads / 64;
+constexpr int kRowChunk = 32;   // nonzeros of a row a thread holds in registers
+constexpr int kSub = 8;         // swaps in flight per thread when applying totals
+
+template <typename T>
+__device__ __forceinline__ T ld_wg(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void st_wg(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The update loops below are branch-free: every slot issues its atomic, an
+// empty slot (-1) on the spare accumulator acc[n] with value 0, so the
+// compiler issues all of them back to back instead of waiting on each.
+
+// Add the chunk's quantised contributions c*val into the column accumulators.
+template <typename T>
+__device__ __forceinline__ void accumulate(long long* acc, int64_t n, const int (&jc)[kRowChunk],
+                                           const T (&vv)[kRowChunk], T c, int e) {
+#pragma unroll
+  for (int i = 0; i < kRowChunk; ++i) {
+    const bool on = jc[i] >= 0;
+    const long long v = on ? (long long)llrint(ldexp((double)(c * vv[i]), 40 - e)) : 0ll;
+    __hip_atomic_fetch_add(&acc[on ? (int64_t)jc[i] : n], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Apply each touched column's total once: the thread that swaps a non-zero
+// total out of the accumulator updates x*_j and x_j.
+template <typename T>
+__device__ __forceinline__ void apply(const CsrArgs<T>& a, const int (&jc)[kRowChunk], int e) {
+#pragma unroll
+  for (int i0 = 0; i0 < kRowChunk; i0 += kSub) {
+    long long tot[kSub];
+#pragma unroll
+    for (int i = 0; i < kSub; ++i) {
+      const int j = jc[i0 + i];
+      tot[i] = __hip_atomic_exchange(&a.acc[j >= 0 ? (int64_t)j : a.n], 0ll, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    T zo[kSub];
+#pragma unroll
+    for (int i = 0; i < kSub; ++i) zo[i] = ld_wg(a.x_star + (tot[i] != 0 ? jc[i0 + i] : 0));
+#pragma unroll
+    for (int i = 0; i < kSub; ++i) {
+      if (tot[i] != 0) {
+        const T z = (T)((double)zo[i] - ldexp((double)tot[i], e - 40));
+        st_wg(a.x_star + jc[i0 + i], z);
+        st_wg(a.x + jc[i0 + i], shrink(z, a.lambda));
+      }
+    }
+  }
+}
+
+// Columns and values of nonzeros [q, q+32) of a row (extent p0..p1, p1 > p0);
+// -1 marks past the end (the load itself is clamped into the row).
+template <typename T>
+__device__ __forceinline__ void load_chunk(const CsrArgs<T>& a, int64_t p0, int64_t p1, int64_t q,
+                                           int (&jc)[kRowChunk], T (&vv)[kRowChunk]) {
+#pragma unroll
+  for (int i = 0; i < kRowChunk; ++i) {
+    const int64_t p = p0 + q + i;
+    const int64_t pc = p < p1 ? p : p1 - 1;
+    const int c = a.col[pc];
+    const T v = a.val[pc];
+    jc[i] = p < p1 ? c : -1;
+    vv[i] = p < p1 ? v : T(0);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
+  __shared__ T cs[kCsrMaxEta];
+  __shared__ double wmax[kCsrWaves];
+  __shared__ double mon[2 * kCsrWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int eta = a.eta;
+  // one sampled row per thread; eta <= 512 keeps each thread's row in registers
+  const bool resident = eta <= kCsrThreads;
+
+  for (int64_t j = tid; j < a.n; j += kCsrThreads) {
+    const T z = a.warm ? a.x_star[j] : T(0);
+    if (!a.warm) st_wg(a.x_star + j, z);
+    st_wg(a.x + j, shrink(z, a.lambda));
+  }
+  __syncthreads();
+
+  int64_t k_done = 0;
+  int stop_code = 0;
+  for (int64_t k = 0; k < a.K; ++k) {
+    const T ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
+    const int32_t* tk = a.idx + k * (int64_t)eta;
+    int lerr = 0;
+
+    // 1. residual and coefficient of each sampled row: r_t = sum_p val_p x[col_p] - b, c_t
+    int jc[kRowChunk];
+    T vv[kRowChunk];
+    int64_t p0 = 0, p1 = 0;
+    double vmax = 0.0;
+    for (int t = tid; t < eta; t += kCsrThreads) {
+      const int i = tk[t];
+      if (i < 0 || (int64_t)i >= a.m) { lerr = ST_INDEX; continue; }
+      p0 = a.row_ptr[i];
+      p1 = a.row_ptr[i + 1];
+      T dot = T(0);
+      for (int64_t q = 0; q < p1 - p0; q += kRowChunk) {
+        load_chunk(a, p0, p1, q, jc, vv);
+        T xg[kRowChunk];
+#pragma unroll
+        for (int u = 0; u < kRowChunk; ++u) {
+          const bool ok = jc[u] >= 0 && (int64_t)jc[u] < a.n;
+          if (!ok && jc[u] != -1) lerr = ST_INDEX;
+          xg[u] = ld_wg(a.x + (ok ? jc[u] : 0));
+          if (!ok) xg[u] = T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kRowChunk; ++u) dot += vv[u] * xg[u];
+      }
+      const T rn = a.r2[i];
+      T c;
+      if (rn == T(0)) { c = T(NAN); lerr = ST_ZERO_ROW; }
+      else c = (ak / T(eta)) * (dot - a.b[i]) / rn;
+      cs[t] = c;
+      if (a.y) atomicAdd(&a.y[i], -c);
+      // the step's largest contribution fixes the quantum
+      for (int64_t q = 0; q < p1 - p0; q += kRowChunk) {
+        if (!(resident && q == 0)) load_chunk(a, p0, p1, q, jc, vv);
+#pragma unroll
+        for (int u = 0; u < kRowChunk; ++u)
+          if (jc[u] >= 0) vmax = fmax(vmax, fabs((double)(c * vv[u])));
+      }
+      if (resident && p1 - p0 > kRowChunk) load_chunk(a, p0, p1, 0, jc, vv);
+    }
+    if (lerr) set_status(a.status, lerr);
+    if (__syncthreads_or(lerr)) {
+      stop_code = ST_INDEX;  // the thread that found the fault set the exact code first
+      break;
+    }
+    int bad = 0;
+    for (int t = tid; t < eta; t += kCsrThreads) bad |= !isfinite(cs[t]);
+    for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+    if (lane == 0) wmax[wave] = vmax;
+    if (__syncthreads_or(bad)) { stop_code = ST_NONFINITE; break; }
+    double gmax = 0.0;
+    for (int w = 0; w < kCsrWaves; ++w) gmax = fmax(gmax, wmax[w]);
+    // power-of-two quantum q = 2^(e-40): |v/q| < 2^41
+    const int e = gmax > 0.0 ? ilogb(gmax) : 0;
+
+    // 2. integer accumulation (integer adds commute: atomic order does not matter)
+    if (gmax > 0.0) {
+      for (int t = tid; t < eta; t += kCsrThreads) {
+        const int i = tk[t];
+        const int64_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+        for (int64_t q = 0; q < r1 - r0; q += kRowChunk) {
+          if (!(resident && q == 0)) load_chunk(a, r0, r1, q, jc, vv);
+          accumulate(a.acc, a.n, jc, vv, cs[t], e);
+        }
+        if (resident && r1 - r0 > kRowChunk) load_chunk(a, r0, r1, 0, jc, vv);
+      }
+    }
+    __syncthreads();
+    // 3. apply every touched column once
+    if (gmax > 0.0) {
+      for (int t = tid; t < eta; t += kCsrThreads) {
+        const int i = tk[t];
+        const int64_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+        for (int64_t q = 0; q < r1 - r0; q += kRowChunk) {
+          if (!(resident && q == 0)) load_chunk(a, r0, r1, q, jc, vv);
+          apply(a, jc, e);
+        }
+      }
+    }
+    __syncthreads();
+    k_done = k + 1;
+
+    if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
+      double e2 = 0.0, r2s = 0.0;
+      for (int64_t j = tid; j < a.n; j += kCsrThreads) {
+        const double rf = (double)a.xref[j];
+        const double d = (double)ld_wg(a.x + j) - rf;
+        e2 += d * d;
+        r2s += rf * rf;
+      }
+      e2 = wave_sum(e2);
+      r2s = wave_sum(r2s);
+      if (lane == 0) { mon[2 * wave] = e2; mon[2 * wave + 1] = r2s; }
+      __syncthreads();
+      double se = 0.0, sr = 0.0;
+      for (int w = 0; w < kCsrWaves; ++w) { se += mon[2 * w]; sr += mon[2 * w + 1]; }
+      const double err = sr > 0.0 ? sqrt(se / sr) : sqrt(se);
+      if (tid == 0 && a.err_hist) a.err_hist[(k + 1) / a.check_every - 1] = err;
+      __syncthreads();
+      if (a.tol > 0.0 && err <= a.tol) break;
+    }
+  }
+  if (stop_code && tid == 0) set_status(a.status, stop_code);
+  if (tid == 0) a.status[1] = (int)k_done;
+}
+
+template <typename T>
+hipError_t launch_csr(CsrArgs<T>& a, hipStream_t stream) {
+  hipLaunchKernelGGL(rska_csr_single<T>, dim3(1), dim3(kCsrThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_csr<float>(CsrArgs<float>&, hipStream_t);
+template hipError_t launch_csr<double>(CsrArgs<double>&, hipStream_t);
+
+}  // namespace rsk

@@ -39,6 +39,36 @@ struct DenseArgs {
   int lpr;                // lanes per row in the dot phase (power of two <= 64)
 };
 
+// One CSR persistent solve (single workgroup).
+constexpr int kCsrMaxEta = 4096;  // rows per step of the CSR kernel
+template <typename T>
+struct CsrArgs {
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const T* val;
+  int64_t m, n;
+  const T* b;
+  const T* r2;
+  T lambda, alpha;
+  const T* alpha_k;
+  int eta;
+  int64_t K;
+  const int32_t* idx;
+  T* x_star;
+  T* x;
+  int warm;
+  T* y;
+  const T* xref;
+  int64_t check_every;
+  double tol;
+  double* err_hist;
+  int* status;
+  long long* acc;         // n + 1 int64 accumulators (the last a spare), zero on entry and on exit
+};
+
+template <typename T>
+hipError_t launch_csr(CsrArgs<T>& a, hipStream_t stream);
+
 struct DenseLaunch {
   int threads;
   size_t lds_bytes;

@@ -158,3 +158,18 @@ def dense_system_device(m: int, n: int, s: int, *, seed: int, noise_rel: float =
     b = bc + (noise_vector(bc, noise_rel, rng) if noise_rel > 0 else 0.0)
     return {"A": A, "xhat": xhat, "b": b.astype(np.float32), "b_clean": bc.astype(np.float32),
             "weights": w.cpu().numpy()}
+
+
+def csr_system_ragged(m: int, n: int, nnz_lo: int, nnz_hi: int, s: int, *, seed: int = 0, dtype="f32"):
+    """Sparse matrix whose rows hold a uniform number of distinct columns in [nnz_lo, nnz_hi] (sorted)."""
+    dt = _DT[dtype]
+    rng = _rng(seed)
+    lens = rng.integers(nnz_lo, nnz_hi + 1, size=m)
+    cols = [np.sort(rng.choice(n, size=int(L), replace=False)) for L in lens]
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate(cols).astype(np.int32) if m else np.zeros(0, np.int32)
+    val = rng.standard_normal(int(row_ptr[-1])).astype(dt)
+    xhat = sparse_vector(n, s, rng, dt)
+    b = np.add.reduceat(val.astype(np.float64) * xhat.astype(np.float64)[col], row_ptr[:-1]) if m else np.zeros(0)
+    b[lens == 0] = 0.0
+    return {"row_ptr": row_ptr, "col": col, "val": val, "xhat": xhat, "b": b.astype(dt), "m": m, "n": n}

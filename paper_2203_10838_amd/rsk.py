@@ -158,3 +158,71 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
         if status:
             raise RskError(status, "rsk_avg_solve_dense (device)")
     return SolveResult(x_star, x, status, k_done, err_hist, status_dev)
+
+
+# ---------------------------------------------------------------------------
+# CSR
+# ---------------------------------------------------------------------------
+
+def csr_desc(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: int) -> _abi.RskCsr:
+    _dev(row_ptr, "row_ptr", torch.int64)
+    _dev(col, "col", torch.int32)
+    _dev(val, "val")
+    m = row_ptr.numel() - 1
+    return _abi.RskCsr(m, int(n), col.numel(), _dtype_code(val), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+
+
+def rownorm2_csr(row_ptr, col, val, n) -> torch.Tensor:
+    """||a_i||^2 of every CSR row."""
+    d = csr_desc(row_ptr, col, val, n)
+    out = torch.empty(d.m, dtype=val.dtype, device=val.device)
+    st = _lib().rsk_rownorm2_csr(ctypes.byref(d), out.data_ptr(), _stream())
+    if st:
+        raise RskError(st, "rsk_rownorm2_csr")
+    return out
+
+
+def solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: int, b: torch.Tensor, *, lam: float,
+              eta: int, alpha: float, K: int, index_stream: torch.Tensor, stream_offset: int = 0,
+              alpha_k: Optional[torch.Tensor] = None, rownorm2_t: Optional[torch.Tensor] = None,
+              x_star: Optional[torch.Tensor] = None, warm_start: bool = False, x_ref: Optional[torch.Tensor] = None,
+              check_every: int = 0, tol: float = 0.0, y_out: Optional[torch.Tensor] = None,
+              workspace: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
+    """K steps of RSKA on a CSR system (one persistent workgroup)."""
+    d = csr_desc(row_ptr, col, val, n)
+    dt = val.dtype
+    dev = val.device
+    _dev(b, "b", dt, d.m)
+    if rownorm2_t is None:
+        rownorm2_t = rownorm2_csr(row_ptr, col, val, n)
+    if x_star is None:
+        if warm_start:
+            raise ValueError("warm_start needs x_star")
+        x_star = torch.empty(n, dtype=dt, device=dev)
+    _dev(x_star, "x_star", dt, n)
+    x = torch.empty(n, dtype=dt, device=dev)
+    status_dev = torch.empty(2, dtype=torch.int32, device=dev)
+    nh = (K // check_every) if (x_ref is not None and check_every > 0) else 0
+    err_hist = torch.full((max(nh, 1),), float("nan"), dtype=torch.float64, device=dev) if nh else None
+    params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
+                         status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, warm_start=warm_start,
+                         x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist, y_out=y_out, dtype=dt)
+    if y_out is not None:
+        _dev(y_out, "y_out", dt, d.m)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_csr(ctypes.byref(d), ctypes.byref(params), ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_csr")
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = _workspace(nbytes.value, dev)
+    st = _lib().rsk_avg_solve_csr(ctypes.byref(d), b.data_ptr(), ctypes.byref(params), x_star.data_ptr(),
+                                  x.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_avg_solve_csr")
+    status = k_done = None
+    if check:
+        s = status_dev.cpu().tolist()
+        status, k_done = int(s[0]), int(s[1])
+        if status:
+            raise RskError(status, "rsk_avg_solve_csr (device)")
+    return SolveResult(x_star, x, status, k_done, err_hist, status_dev)
