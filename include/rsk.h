@@ -139,6 +139,24 @@ int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
 int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, void *x_star, void *x,
                           void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Many right-hand sides sharing A and the index stream (float32 only), on the
+ * matrix cores. Column r of X is the single-RHS iteration for b = B[:, r].
+ * A step is the sketch-and-project form of the update (eq. (rska1), start of
+ * Sec. 4) written as two GEMMs on the sampled rows A_tau:
+ *     R = A_tau X - B_tau,  C = (alpha_k/eta) D_tau^-2 R,  X* -= A_tau^T C,  X = S_lambda(X*).
+ *   B       device, m x R row-major.
+ *   X_star  device, n x R row-major, in/out (read when warm_start = 1).
+ *   X       device, n x R row-major, out.
+ * Requires R % 4 == 0, n % 4 == 0, ld % 4 == 0, A 16-byte aligned; the
+ * monitor and y_out are not supported here (RSK_ERR_UNSUPPORTED).
+ * Device faults and status_dev follow the single-RHS conventions; steps are
+ * queued as kernels on `stream` (four per step).
+ */
+int32_t rsk_workspace_size_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, size_t *bytes);
+int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p, void *X_star,
+                               void *X, void *workspace, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,10 @@ SIGNATURES = {
     "rsk_avg_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                     c_vp, c_sz, c_vp]),
     "rsk_rownorm2_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, c_vp]),
+    "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),
+                                            ctypes.POINTER(c_sz)]),
+    "rsk_avg_solve_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_vp, c_vp,
+                                       c_vp, c_sz, c_vp]),
     "rsk_workspace_size_csr": (c_i32, [ctypes.POINTER(RskCsr), ctypes.POINTER(RskParams), ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                   c_vp, c_sz, c_vp]),

@@ -227,9 +227,78 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
   return RSK_OK;
 }
 
+struct MultiPlan {
+  int S, eta_pad;
+  int64_t kspan;
+  size_t offY, offC, bytes;
+};
+
+int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiPlan* pl) {
+  if (A->dtype != RSK_F32) return RSK_ERR_UNSUPPORTED;
+  if (R <= 0) return RSK_ERR_INVALID_ARG;
+  if ((R % 4) || (A->n % 4) || (A->ld % 4) || (((uintptr_t)A->val) % 16)) return RSK_ERR_UNSUPPORTED;
+  if (p->x_ref || p->y_out || p->check_every) return RSK_ERR_UNSUPPORTED;
+  pl->eta_pad = (p->eta + 63) / 64 * 64;
+  const int tiles = (pl->eta_pad / 64) * ((R + 63) / 64);
+  const int cus = device_cus() > 0 ? device_cus() : 256;
+  int S = (3 * cus + tiles - 1) / tiles;  // about three workgroups per CU for the n-long products
+  const int64_t max_s = (A->n + 255) / 256;  // at least 256 columns a split
+  if (S > max_s) S = (int)max_s;
+  if (S < 1) S = 1;
+  pl->kspan = (A->n + S - 1) / S;
+  pl->kspan = (pl->kspan + 15) / 16 * 16;
+  pl->S = (int)((A->n + pl->kspan - 1) / pl->kspan);
+  size_t o = 0;
+  pl->offY = o; o = align256(o + (size_t)pl->S * pl->eta_pad * R * sizeof(float));
+  pl->offC = o; o = align256(o + (size_t)pl->eta_pad * R * sizeof(float));
+  pl->bytes = o;
+  return RSK_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t rsk_workspace_size_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, size_t* bytes) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  st = check_params(p, A->m);
+  if (st) return st;
+  MultiPlan pl;
+  st = plan_multirhs(A, R, p, &pl);
+  if (st) return st;
+  *bytes = pl.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_avg_solve_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_params* p, void* X_star,
+                               void* X, void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (!B || !X_star || !X) return RSK_ERR_INVALID_ARG;
+  MultiPlan pl;
+  st = plan_multirhs(A, R, p, &pl);
+  if (st) return st;
+  if (!workspace || ws_bytes < pl.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
+  unsigned char* w = (unsigned char*)workspace;
+  rsk::MultiRhsArgs a;
+  a.A = (const float*)A->val; a.m = A->m; a.n = A->n; a.ld = A->ld;
+  a.B = (const float*)B; a.R = R; a.r2 = (const float*)p->rownorm2;
+  a.lambda = (float)p->lambda; a.alpha = (float)p->alpha; a.alpha_k = (const float*)p->alpha_k;
+  a.eta = p->eta; a.K = p->K;
+  a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
+  a.x_star = (float*)X_star; a.x = (float*)X; a.warm = p->warm_start ? 1 : 0;
+  a.status = p->status_dev;
+  a.Y = (float*)(w + pl.offY); a.C = (float*)(w + pl.offC);
+  a.S = pl.S; a.eta_pad = pl.eta_pad; a.kspan = pl.kspan;
+  if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
+  if (rsk::launch_multirhs(a, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
+  return RSK_OK;
+}
+
 
 int32_t rsk_rownorm2_csr(const rsk_csr* A, void* rownorm2, void* stream) {
   int32_t st = check_csr(A);

@@ -69,6 +69,29 @@ struct CsrArgs {
 template <typename T>
 hipError_t launch_csr(CsrArgs<T>& a, hipStream_t stream);
 
+// Multi-RHS (shared A and stream), float32 MFMA GEMMs per step.
+struct MultiRhsArgs {
+  const float* A;
+  int64_t m, n, ld;
+  const float* B;         // m x R row-major
+  int R;
+  const float* r2;
+  float lambda, alpha;
+  const float* alpha_k;   // nullable, device
+  int eta;
+  int64_t K;
+  const int32_t* idx;
+  float* x_star;          // n x R row-major, in/out
+  float* x;               // n x R row-major, out
+  int warm;
+  int* status;
+  float* Y;               // S x eta_pad x R split-K partials
+  float* C;               // eta_pad x R coefficients
+  int S, eta_pad;
+  int64_t kspan;
+};
+hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream);
+
 struct DenseLaunch {
   int threads;
   size_t lds_bytes;

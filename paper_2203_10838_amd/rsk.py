@@ -226,3 +226,51 @@ def solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: in
         if status:
             raise RskError(status, "rsk_avg_solve_csr (device)")
     return SolveResult(x_star, x, status, k_done, err_hist, status_dev)
+
+
+# ---------------------------------------------------------------------------
+# Many right-hand sides sharing A and the stream (matrix cores)
+# ---------------------------------------------------------------------------
+
+def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, alpha: float, K: int,
+                   index_stream: torch.Tensor, stream_offset: int = 0, alpha_k: Optional[torch.Tensor] = None,
+                   rownorm2_t: Optional[torch.Tensor] = None, X_star: Optional[torch.Tensor] = None,
+                   warm_start: bool = False, workspace: Optional[torch.Tensor] = None,
+                   check: bool = True) -> SolveResult:
+    """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major)."""
+    m, n = A.shape
+    if B.dim() != 2 or B.shape[0] != m:
+        raise ValueError("B must be m x R")
+    R = B.shape[1]
+    dt = A.dtype
+    _dev(B, "B", dt)
+    if rownorm2_t is None:
+        rownorm2_t = rownorm2(A)
+    if X_star is None:
+        if warm_start:
+            raise ValueError("warm_start needs X_star")
+        X_star = torch.empty((n, R), dtype=dt, device=A.device)
+    _dev(X_star, "X_star", dt, n * R)
+    X = torch.empty((n, R), dtype=dt, device=A.device)
+    status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
+    params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
+                         status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, warm_start=warm_start,
+                         dtype=dt)
+    d = dense_desc(A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_multirhs(ctypes.byref(d), R, ctypes.byref(params), ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_multirhs")
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = _workspace(nbytes.value, A.device)
+    st = _lib().rsk_avg_solve_multirhs(ctypes.byref(d), B.data_ptr(), R, ctypes.byref(params), X_star.data_ptr(),
+                                       X.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_avg_solve_multirhs")
+    status = k_done = None
+    if check:
+        s = status_dev.cpu().tolist()
+        status, k_done = int(s[0]), int(s[1])
+        if status:
+            raise RskError(status, "rsk_avg_solve_multirhs (device)")
+    return SolveResult(X_star, X, status, k_done, None, status_dev)
