@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["batched", "multirhs", "csr"], default=None,
+                    help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
     args = ap.parse_args()
@@ -132,6 +134,11 @@ def main():
     from paper_2203_10838_amd import inputs, params, rsk
 
     dev = torch.device("cuda:0")
+    if args.only:
+        stream = torch.cuda.current_stream()
+        fn = {"batched": batched_run, "multirhs": multirhs_run, "csr": csr_run}[args.only]
+        print(json.dumps({args.only: fn(dev, stream)}), flush=True)
+        return
     t0 = time.time()
     sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
     A = sysd["A"]
@@ -237,11 +244,157 @@ def main():
 
     if not args.no_sweep:
         out["csr"] = csr_run(dev, stream)
+        out["batched"] = batched_run(dev, stream)
+        torch.cuda.empty_cache()
+        out["multirhs"] = multirhs_run(dev, stream)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, sysd["b"], weights, LAM, eta, params.optimal_alpha(eta, fro2, smax2))
     print(json.dumps(out), flush=True)
+
+
+BATCH_NSYS, BATCH_SEED, BATCH_TOL, BATCH_CHECK, BATCH_KMAX = 512, 20310838 + 300, 1e-5, 10, 20000
+
+
+def batched_systems(dev, kmax=BATCH_KMAX, nsys=BATCH_NSYS):
+    """The batched workload on the device: 512 Gaussian float32 systems, m_i ~ U{500..8000},
+    n_i ~ U{200..m_i/2}, x_hat_i with 5% N(0,1) nonzeros, b_i = A_i x_hat_i, lambda = 1,
+    eta_i = 1 + n_i/10, alpha_i = alpha*(eta_i), own row stream of kmax steps each."""
+    import torch
+    from paper_2203_10838_amd import inputs, params, rsk
+    out = []
+    for d in inputs.batched_workload(nsys, BATCH_SEED, device=dev):
+        A = d["A"]
+        m, n = A.shape
+        if n % 4:
+            # rows padded to a multiple of 16 bytes (leading dimension), so the
+            # solver can use float4 loads; the padding is never read as data
+            buf = torch.zeros((m, n + 4 - n % 4), dtype=A.dtype, device=dev)
+            buf[:, :n] = A
+            A = buf[:, :n]
+        eta = 1 + n // 10
+        fro2 = float(d["weights"].sum())
+        alpha = params.optimal_alpha(eta, fro2, spectral_norm_sq(A, iters=30))
+        out.append(rsk.BatchSystem(A=A, b=torch.from_numpy(d["b"]).to(dev),
+                                   index_stream=inputs.index_stream_device(d["weights"], kmax, eta, d["seed"] + 1, dev),
+                                   eta=eta, K=kmax, alpha=alpha, lam=1.0, rownorm2_t=rsk.rownorm2(A),
+                                   x_ref=torch.from_numpy(d["xhat"]).to(dev), check_every=BATCH_CHECK, tol=BATCH_TOL))
+    return out
+
+
+def _median_ms(fn, stream, reps=3):
+    import torch
+    ts = []
+    for _ in range(reps):
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a0.elapsed_time(a1))
+    return float(np.median(ts))
+
+
+def batched_run(dev, stream, plain=True, wg_bytes=0):
+    """Time to rel.err 1e-5 of every system: one batched launch vs 512 sequential plain solves.
+
+    A calibration launch with the monitor on (every 10 steps, tol 1e-5, at most 20000 steps) finds
+    k*_i per system; the timed runs then do exactly K_i = k*_i steps with the monitor off, batched
+    (median of 3) and as 512 plain single-system solves back to back (one pass). The batched
+    early-stop run (monitor on, K = 20000) is timed as well."""
+    import dataclasses
+    import torch
+    from paper_2203_10838_amd import rsk
+    t0 = time.time()
+    systems = batched_systems(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] batched: {len(systems)} systems ready in {time.time() - t0:.1f}s, "
+        f"{sum(s.A.shape[0] * s.A.shape[1] for s in systems) * 4 / 1e9:.2f} GB of A")
+    cal = rsk.solve_batched(systems, wg_bytes=wg_bytes)
+    k = np.array(cal.k_done, dtype=np.int64)
+    conv = int((k < BATCH_KMAX).sum())
+    t_early = _median_ms(lambda: rsk.solve_batched(systems, check=False, wg_bytes=wg_bytes), stream, reps=1)
+    fixed = [dataclasses.replace(s, K=int(ki), x_ref=None, check_every=0, tol=0.0) for s, ki in zip(systems, k)]
+    res = rsk.solve_batched(fixed, wg_bytes=wg_bytes)
+    if any(res.status):
+        raise RuntimeError(f"batched status {res.status}")
+    errs = np.array([float((x.double() - s.x_ref.double()).norm() / s.x_ref.double().norm())
+                     for x, s in zip(res.x, systems)])
+    t_b = _median_ms(lambda: rsk.solve_batched(fixed, check=False, wg_bytes=wg_bytes), stream)
+    byts = float(sum(int(ki) * step_bytes(s.eta, s.A.shape[1]) for ki, s in zip(k, systems)))
+    gbs = byts / (t_b * 1e-3) / 1e9
+    out = {"workload": "512 float32 systems, m~U{500..8000}, n~U{200..m/2}, eta=1+n/10, alpha*, lambda=1, "
+                       "x_hat 5% nonzeros, K_i = first check (every 10 steps) with rel.err <= 1e-5, at most 20000",
+           "systems": len(systems), "tol": BATCH_TOL, "converged": conv, "k_min": int(k.min()),
+           "k_median": int(np.median(k)), "k_max": int(k.max()),
+           "max_rel_err_converged": float(errs[k < BATCH_KMAX].max()) if conv else None,
+           "batched_ms": round(t_b, 3), "batched_GBps": round(gbs, 2),
+           "batched_frac_hbm": round(gbs / PEAK_HBM_GBS, 4), "bytes": byts,
+           "batched_early_stop_ms": round(t_early, 3)}
+    log(f"[bench] batched: K_i=k*_i {t_b:.1f} ms ({gbs:.0f} GB/s), early-stop {t_early:.1f} ms, "
+        f"converged {conv}/{len(systems)}, k median {out['k_median']} max {out['k_max']}")
+    if plain:
+        ws = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+
+        def run_plain():
+            for s in fixed:
+                rsk.solve_dense(s.A, s.b, lam=s.lam, eta=s.eta, alpha=s.alpha, K=s.K, index_stream=s.index_stream,
+                                rownorm2_t=s.rownorm2_t, workspace=ws, check=False)
+        run_plain()
+        t_p = _median_ms(run_plain, stream, reps=1)
+        out.update({"plain_ms": round(t_p, 3), "plain_GBps": round(byts / (t_p * 1e-3) / 1e9, 2),
+                    "plain_frac_hbm": round(byts / (t_p * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                    "speedup_batched_vs_plain": round(t_p / t_b, 2)})
+        log(f"[bench] plain x{len(systems)}: {t_p:.1f} ms, speedup {t_p / t_b:.2f}x")
+    return out
+
+
+MRHS_M, MRHS_N, MRHS_R, MRHS_ETA, MRHS_SEED = 32768, 8192, 256, 820, 20310838 + 300 + 7
+
+
+def multirhs_run(dev, stream, K=40):
+    """Shared-A multi-RHS: A 32768x8192 float32 N(0,1) drawn on the device, R = 256 right-hand sides
+    B = A X_hat (5% N(0,1) nonzeros per column), one shared stream, eta = 820, alpha = alpha*, lambda = 1.
+    Per-step time and TFLOP/s (4 eta n R flop) against the float32 MFMA peak, and the same work as
+    R single-column plain solves (per-step time of one column x R)."""
+    import torch
+    from paper_2203_10838_amd import inputs, params, rsk
+    m, n, R, eta = MRHS_M, MRHS_N, MRHS_R, MRHS_ETA
+    g = torch.Generator(device=dev)
+    g.manual_seed(MRHS_SEED)
+    A = torch.randn((m, n), generator=g, device=dev, dtype=torch.float32)
+    rng = np.random.Generator(np.random.PCG64(MRHS_SEED + 7))
+    Xh = np.stack([inputs.sparse_vector(n, int(round(0.05 * n)), rng, np.float32) for _ in range(R)], axis=1)
+    Xd = torch.from_numpy(Xh.astype(np.float64)).to(dev)
+    B = torch.empty((m, R), dtype=torch.float32, device=dev)
+    w = torch.empty(m, dtype=torch.float64, device=dev)
+    for r0 in range(0, m, 4096):
+        blk = A[r0:r0 + 4096].double()
+        B[r0:r0 + 4096] = (blk @ Xd).float()
+        w[r0:r0 + 4096] = (blk * blk).sum(1)
+    del Xd
+    wn = w.cpu().numpy()
+    alpha = params.optimal_alpha(eta, float(wn.sum()), spectral_norm_sq(A))
+    r2 = rsk.rownorm2(A)
+    idx = inputs.index_stream_device(wn, K, eta, MRHS_SEED + 1, dev)
+    rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=alpha, K=2, index_stream=idx, rownorm2_t=r2)
+    t_m = _median_ms(lambda: rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=alpha, K=K, index_stream=idx,
+                                                rownorm2_t=r2, check=False), stream)
+    b0 = B[:, 0].contiguous()
+    rsk.solve_dense(A, b0, lam=1.0, eta=eta, alpha=alpha, K=2, index_stream=idx, rownorm2_t=r2)
+    t_1 = _median_ms(lambda: rsk.solve_dense(A, b0, lam=1.0, eta=eta, alpha=alpha, K=K, index_stream=idx,
+                                             rownorm2_t=r2, check=False), stream)
+    fl = 4.0 * eta * n * R
+    out = {"workload": f"shared A {m}x{n} float32, R={R}, eta={eta}, alpha*={alpha:.1f}, lambda=1, {K} steps",
+           "us_per_step": round(t_m * 1e3 / K, 2), "TFLOPs": round(fl * K / (t_m * 1e-3) / 1e12, 2),
+           "frac_fp32_mfma": round(fl * K / (t_m * 1e-3) / 1e12 / 157.3, 4),
+           "plain_one_column_us_per_step": round(t_1 * 1e3 / K, 2),
+           "plain_R_columns_us_per_step": round(t_1 * 1e3 / K * R, 1),
+           "speedup_vs_R_plain": round(t_1 * R / t_m, 2)}
+    log(f"[bench] multirhs: {out}")
+    return out
 
 
 def csr_run(dev, stream, K=20000):

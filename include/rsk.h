@@ -97,6 +97,31 @@ typedef struct {
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register tile */
 } rsk_params;
 
+/*
+ * One system of a batch (rsk_avg_solve_batched). All pointers inside are
+ * device pointers. The solve takes the array twice: in host memory (checked
+ * and planned on the host) and the same bytes in device memory (read by the
+ * kernels).
+ */
+typedef struct {
+  const void *A;               /* row-major m x n, leading dimension ld, dtype of the batch */
+  int64_t m, n, ld;
+  const void *b;               /* m */
+  const void *rownorm2;        /* m, ||a_i||^2 */
+  const int32_t *index_stream; /* K*eta entries, step-major, this system's own stream */
+  int64_t K;                   /* steps (upper bound when a tolerance stops the system early) */
+  int32_t eta;                 /* rows per step, >= 1 */
+  int32_t warm_start;          /* 1: start from x_star */
+  double alpha, lambda;
+  void *x_star;                /* n, in/out */
+  void *x;                     /* n, out */
+  const void *x_ref;           /* nullable monitor target (n) */
+  int64_t check_every;         /* monitor period, with x_ref */
+  double tol;                  /* stop this system once ||x - x_ref||/||x_ref|| <= tol (0: never) */
+  double *err_hist;            /* nullable, K/check_every entries */
+  int32_t *status_dev;         /* int32[2]: status, steps completed */
+} rsk_batch_item;
+
 /* Version of this ABI (RSK_ABI_VERSION). */
 int32_t rsk_abi_version(void);
 
@@ -138,6 +163,41 @@ int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
  */
 int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, void *x_star, void *x,
                           void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Many independent dense systems of uneven shape in one launch (eq. (rska)
+ * per system, each with its own stream, eta, alpha, lambda, monitor, early
+ * stop and status). System s runs on G_s workgroups, chosen so that each
+ * holds about wg_bytes of the step's rows (at most 256); they split its
+ * columns and exchange partial dots through the system's own workspace
+ * region, exactly as rsk_avg_solve_dense does for one system. Persistent
+ * workgroups take (system, rank) tickets in the order `order`.
+ *   nsys       number of systems (0 returns RSK_OK at once).
+ *   dtype      RSK_F32 or RSK_F64, the dtype of every system.
+ *   items      host array of nsys descriptors, checked before any launch
+ *              (RSK_ERR_INVALID_ARG / RSK_ERR_UNSUPPORTED for the first bad one);
+ *              it is not read after the call returns.
+ *   items_dev  device copy of the same nsys descriptors; must stay valid until
+ *              the stream has run the solve.
+ *   order      device int32[nsys], a permutation of 0..nsys-1 (nullable: identity).
+ *              Largest work first balances the CUs best. A repeated entry makes
+ *              two groups write the same x (undefined result).
+ *   wg_bytes   target row bytes per workgroup per step (0: 48 KiB). Must be the
+ *              value given to rsk_workspace_size_batched.
+ * Per-system status_dev[0] is reset by the call; it ends 0 or an RSK_ERR_*
+ * code, status_dev[1] the steps completed. The kernels plan from the device
+ * copy: a device descriptor that is invalid or needs more LDS than the host
+ * plan gives its system RSK_ERR_INVALID_ARG (the system is skipped); if the
+ * device plans need more exchange words than the workspace holds, no system
+ * runs and all report RSK_ERR_WORKSPACE.
+ * Workspace: rsk_workspace_size_batched (plans, ticket counter and one
+ * exchange region per system), zeroed by the call.
+ */
+int32_t rsk_workspace_size_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *items, int64_t wg_bytes,
+                                   size_t *bytes);
+int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *items,
+                              const rsk_batch_item *items_dev, const int32_t *order, int64_t wg_bytes,
+                              void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Many right-hand sides sharing A and the index stream (float32 only), on the

@@ -33,6 +33,13 @@ class RskParams(ctypes.Structure):
                 ("status_dev", c_vp), ("grid", c_i32), ("kernel", c_i32)]
 
 
+class RskBatchItem(ctypes.Structure):
+    _fields_ = [("A", c_vp), ("m", c_i64), ("n", c_i64), ("ld", c_i64), ("b", c_vp), ("rownorm2", c_vp),
+                ("index_stream", c_vp), ("K", c_i64), ("eta", c_i32), ("warm_start", c_i32), ("alpha", c_dbl),
+                ("lambda_", c_dbl), ("x_star", c_vp), ("x", c_vp), ("x_ref", c_vp), ("check_every", c_i64),
+                ("tol", c_dbl), ("err_hist", c_vp), ("status_dev", c_vp)]
+
+
 # name -> (restype, argtypes); every symbol include/rsk.h declares
 SIGNATURES = {
     "rsk_abi_version": (c_i32, []),
@@ -43,6 +50,8 @@ SIGNATURES = {
     "rsk_avg_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                     c_vp, c_sz, c_vp]),
     "rsk_rownorm2_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, c_vp]),
+    "rsk_workspace_size_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, ctypes.POINTER(c_sz)]),
+    "rsk_avg_solve_batched": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),
                                             ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_vp, c_vp,

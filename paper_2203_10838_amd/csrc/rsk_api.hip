@@ -13,7 +13,7 @@ namespace {
 constexpr int kMaxEtaDense = 16384;
 constexpr size_t kTileCacheBytes = 96 * 1024;
 constexpr size_t kBytesPerWg = 96 * 1024;  // target row bytes per workgroup per step
-constexpr int64_t kOneHopWords = 4096;     // G*eta at or below which every workgroup reduces every row
+using rsk::kOneHopWords;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t elem_size(int32_t dt) { return dt == RSK_F64 ? 8 : 4; }
@@ -141,12 +141,13 @@ int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
     pl->wq_max = (int)((pl->nchunks + G - 1) / G);
     pl->lpr = next_pow2(pl->wq_max) < 64 ? next_pow2(pl->wq_max) : 64;
     pl->tile_cache = ((size_t)p->eta * pl->wq_max * pl->vec * s) <= kTileCacheBytes;
-    pl->two_hop = ((int64_t)G * p->eta) > kOneHopWords;
+    pl->two_hop = ((int64_t)G * p->eta * pl->W) > kOneHopWords;
     size_t lds = 0;
-    int maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, pl->tile_cache, &lds);
+    const int64_t xr = pl->two_hop ? 0 : (int64_t)G * p->eta;
+    int maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, pl->tile_cache, xr, &lds);
     if (maxg == 0 && pl->tile_cache) {
       pl->tile_cache = 0;
-      maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, 0, &lds);
+      maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, 0, xr, &lds);
     }
     if (maxg >= G) break;
     if (maxg == 0) {
@@ -255,9 +256,94 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   return RSK_OK;
 }
 
+int32_t check_batch_item(const rsk_batch_item& it) {
+  if (!it.A || !it.b || !it.rownorm2 || !it.x_star || !it.x || !it.status_dev) return RSK_ERR_INVALID_ARG;
+  if (it.m <= 0 || it.n <= 0 || it.ld < it.n || it.eta < 1 || it.K < 0 || it.K >= (int64_t(1) << 31))
+    return RSK_ERR_INVALID_ARG;
+  if (it.K > 0 && !it.index_stream) return RSK_ERR_INVALID_ARG;
+  if (!(it.lambda >= 0.0) || !isfinite(it.lambda) || !finite_pos(it.alpha)) return RSK_ERR_INVALID_ARG;
+  if (it.check_every < 0 || !(it.tol >= 0.0)) return RSK_ERR_INVALID_ARG;
+  if (it.x_ref && it.check_every > 0 && !it.err_hist && it.tol <= 0.0) return RSK_ERR_INVALID_ARG;
+  if (it.m > INT32_MAX || it.eta > kMaxEtaDense) return RSK_ERR_UNSUPPORTED;
+  return RSK_OK;
+}
+
+// Workspace of a batch: [256 B: ticket counter][ticket starts, nsys+1 int64]
+// [region offsets, nsys int64][one exchange region per system].
+struct BatchLayout {
+  int vec, gmax;
+  int64_t wg_bytes, tickets, words;
+  size_t lds, off_t0, off_woff, off_region, bytes;
+};
+
+int32_t batch_layout(int32_t nsys, int32_t dtype, const rsk_batch_item* items, int64_t wg_bytes, BatchLayout* L) {
+  if (nsys < 0 || (nsys > 0 && !items) || wg_bytes < 0) return RSK_ERR_INVALID_ARG;
+  if (dtype != RSK_F32 && dtype != RSK_F64) return RSK_ERR_UNSUPPORTED;
+  const size_t es = elem_size(dtype);
+  const int vmax = (int)(16 / es);
+  L->wg_bytes = wg_bytes ? wg_bytes : rsk::kBatchWgBytes;
+  L->vec = vmax;
+  for (int32_t i = 0; i < nsys; ++i) {
+    const int32_t st = check_batch_item(items[i]);
+    if (st) return st;
+    if ((items[i].ld % vmax) != 0 || ((uintptr_t)items[i].A) % 16 != 0) L->vec = 1;
+  }
+  L->gmax = 0; L->tickets = 0; L->words = 0; L->lds = 0;
+  for (int32_t i = 0; i < nsys; ++i) {
+    rsk::BatchPlan pl;
+    if (!rsk::batched_plan(items[i].n, items[i].eta, (int)es, L->vec, L->wg_bytes, &pl)) return RSK_ERR_UNSUPPORTED;
+    if (pl.G > L->gmax) L->gmax = pl.G;
+    if (pl.lds > L->lds) L->lds = pl.lds;
+    L->tickets += pl.G;
+    L->words += pl.words;
+  }
+  size_t o = 256;
+  L->off_t0 = o; o = align256(o + (size_t)(nsys + 1) * sizeof(int64_t));
+  L->off_woff = o; o = align256(o + (size_t)nsys * sizeof(int64_t));
+  L->off_region = o; o = align256(o + (size_t)L->words * sizeof(u64));
+  L->bytes = o;
+  return RSK_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t rsk_workspace_size_batched(int32_t nsys, int32_t dtype, const rsk_batch_item* items, int64_t wg_bytes,
+                                   size_t* bytes) {
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  BatchLayout L;
+  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, &L);
+  if (st) return st;
+  *bytes = L.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item* items,
+                              const rsk_batch_item* items_dev, const int32_t* order, int64_t wg_bytes,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  BatchLayout L;
+  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, &L);
+  if (st) return st;
+  if (nsys == 0) return RSK_OK;
+  if (!items_dev) return RSK_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < L.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
+  const int maxg = rsk::batched_max_resident(dtype, L.vec, L.lds);
+  if (maxg < L.gmax) return RSK_ERR_UNSUPPORTED;
+  const int grid = L.tickets < maxg ? (int)L.tickets : maxg;
+  unsigned char* w = (unsigned char*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  if (rsk::launch_zero_words((u64*)w, L.bytes / sizeof(u64), s) != hipSuccess) return RSK_ERR_HIP;
+  int64_t* t0 = (int64_t*)(w + L.off_t0);
+  int64_t* wo = (int64_t*)(w + L.off_woff);
+  if (rsk::launch_batched_prep(items_dev, order, nsys, (int)elem_size(dtype), L.vec, L.wg_bytes, L.lds,
+                               L.words, t0, wo, s) != hipSuccess)
+    return RSK_ERR_HIP;
+  if (rsk::launch_batched(items_dev, order, nsys, t0, wo, (u64*)w, (u64*)(w + L.off_region), L.wg_bytes, dtype,
+                          L.vec, L.lds, grid, s) != hipSuccess)
+    return RSK_ERR_HIP;
+  return RSK_OK;
+}
 
 int32_t rsk_workspace_size_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, size_t* bytes) {
   int32_t st = check_dense(A);

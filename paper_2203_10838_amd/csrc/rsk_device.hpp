@@ -118,10 +118,14 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Sum within aligned groups of `width` lanes (width a power of two <= 64).
+// Sum within aligned groups of `width` lanes (width a power of two <= 64),
+// butterfly offsets width/2, ..., 1. Unrolled with a wave-uniform predicate,
+// so no loop back-edge makes the compiler drain outstanding memory operations.
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int width) {
-  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+    if (off < width) v += __shfl_xor(v, off);
   return v;
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rsk.h"
+
 namespace rsk {
 
 typedef unsigned long long u64;
@@ -34,10 +36,42 @@ struct DenseArgs {
   int G;
   int two_hop;            // 1: owners reduce rows, then everyone gathers; 0: everyone reduces everything
   int tile_cache;         // 1: keep the step's row tile in LDS between dot and scatter
+                          // (two_hop == 0 requires G*eta*words <= kOneHopWords)
   int64_t nchunks;        // ceil(n / VEC)
   int wq_max;             // max chunks per workgroup slice
   int lpr;                // lanes per row in the dot phase (power of two <= 64)
 };
+
+constexpr int kDenseThreads = 256;
+
+// LDS layout of one workgroup of the general dense kernel (byte offsets):
+// own slices of x* and x, the step's coefficients, the rows' indices, b and
+// ||a||^2 (two buffers: the next step's are prefetched during the current
+// one), the update's row-group partials, monitor scratch and, optionally, the
+// step's row tile; with the one-hop exchange also the G*eta partials of the step.
+struct DenseSmem {
+  size_t xs, xv, cs, tau, bq, rq, red, xr, flags, tile, total;
+  __host__ __device__ static size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
+  __host__ __device__ DenseSmem(size_t esize, int vec, int wq_max, int eta, int nt, int tile_cache, int64_t xr_elems) {
+    size_t o = 0;
+    xs = o; o += al16(esize * (size_t)wq_max * vec);
+    xv = o; o += al16(esize * (size_t)wq_max * vec);
+    cs = o; o += al16(esize * (size_t)eta);
+    tau = o; o += al16(sizeof(int) * 2 * (size_t)eta);
+    bq = o; o += al16(esize * 2 * (size_t)eta);
+    rq = o; o += al16(esize * 2 * (size_t)eta);
+    red = o; o += al16(esize * (size_t)nt * vec);
+    xr = o; o += al16(esize * (size_t)xr_elems);
+    flags = o; o += 128;
+    tile = o; o += tile_cache ? al16(esize * (size_t)eta * wq_max * vec) : 0;
+    total = o;
+  }
+};
+
+// Exchange words per step (G*eta*words per value) at or below which every
+// workgroup gathers all partials (one flat poll of at most 16 words per
+// thread of a 256-thread workgroup, then per-row sums in LDS).
+constexpr int64_t kOneHopWords = 4096;
 
 // One CSR persistent solve (single workgroup).
 constexpr int kCsrMaxEta = 4096;  // rows per step of the CSR kernel
@@ -92,6 +126,65 @@ struct MultiRhsArgs {
 };
 hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream);
 
+// Batched independent systems. System s is solved by G_s workgroups running
+// the dense kernel's per-workgroup code on its own workspace region. The plan
+// of a system depends only on (n, eta, element size, vector width, target
+// bytes per workgroup) and is computed by the same function on the host
+// (workspace and LDS sizing) and on the device (tickets and offsets).
+constexpr int kBatchGcap = 256;                 // most workgroups one system may use
+constexpr size_t kBatchLdsCap = 80 * 1024;      // LDS of one workgroup: two fit a CU
+constexpr int64_t kBatchWgBytes = 48 * 1024;    // default row bytes per workgroup per step
+constexpr int64_t kBatchRegionHead = 32;        // words: join counter + padding
+
+struct BatchPlan {
+  int G, two_hop, tile_cache, lpr, wq_max;
+  int64_t nchunks, words;
+  size_t lds;
+};
+
+__host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int vec, int64_t wg_bytes,
+                                             BatchPlan* p) {
+  if (n <= 0 || eta <= 0 || vec <= 0 || wg_bytes <= 0) return false;
+  const int64_t nchunks = (n + vec - 1) / vec;
+  const int64_t gmax = nchunks < kBatchGcap ? nchunks : kBatchGcap;
+  int64_t G = ((int64_t)eta * n * esize + wg_bytes - 1) / wg_bytes;
+  if (G < 1) G = 1;
+  if (G > gmax) G = gmax;
+  for (;;) {
+    const int wq = (int)((nchunks + G - 1) / G);
+    const int64_t xr = G * eta * (esize / 4) > kOneHopWords ? 0 : G * eta;
+    const DenseSmem with_tile(esize, vec, wq, eta, kDenseThreads, 1, xr);
+    const DenseSmem no_tile(esize, vec, wq, eta, kDenseThreads, 0, xr);
+    if (with_tile.total <= kBatchLdsCap || no_tile.total <= kBatchLdsCap) {
+      p->tile_cache = with_tile.total <= kBatchLdsCap;
+      p->lds = p->tile_cache ? with_tile.total : no_tile.total;
+      p->wq_max = wq;
+      break;
+    }
+    if (G >= gmax) return false;
+    G = 2 * G < gmax ? 2 * G : gmax;
+  }
+  int lpr = 1;
+  while (lpr < p->wq_max && lpr < 64) lpr <<= 1;
+  const int W = esize / 4;
+  p->G = (int)G;
+  p->lpr = lpr;
+  p->nchunks = nchunks;
+  p->two_hop = G * eta * W > kOneHopWords;
+  const int64_t body = 2 * G * eta * W + (int64_t)eta * W + 4 * G;
+  p->words = kBatchRegionHead + (body + 31) / 32 * 32;
+  return true;
+}
+
+hipError_t launch_batched_prep(const rsk_batch_item* items, const int32_t* order, int nsys, int esize, int vec,
+                               int64_t wg_bytes, size_t lds_launch, int64_t cap_words, int64_t* ticket0,
+                               int64_t* woff, hipStream_t stream);
+// Largest co-resident grid of the batched kernel with this LDS size (0 if none).
+int batched_max_resident(int dtype, int vec, size_t lds);
+hipError_t launch_batched(const rsk_batch_item* items, const int32_t* order, int nsys, const int64_t* ticket0,
+                          const int64_t* woff, u64* queue, u64* regions, int64_t wg_bytes, int dtype, int vec,
+                          size_t lds, int grid, hipStream_t stream);
+
 struct DenseLaunch {
   int threads;
   size_t lds_bytes;
@@ -118,6 +211,6 @@ hipError_t launch_zero_status(int* status, hipStream_t stream);
 
 // Largest co-resident grid for the dense kernel with these sizes (0 if none).
 template <typename T>
-int dense_max_grid(int vec, int eta, int wq_max, int tile_cache, size_t* lds_bytes);
+int dense_max_grid(int vec, int eta, int wq_max, int tile_cache, int64_t xr_elems, size_t* lds_bytes);
 
 }  // namespace rsk

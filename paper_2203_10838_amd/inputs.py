@@ -173,3 +173,31 @@ def csr_system_ragged(m: int, n: int, nnz_lo: int, nnz_hi: int, s: int, *, seed:
     b = np.add.reduceat(val.astype(np.float64) * xhat.astype(np.float64)[col], row_ptr[:-1]) if m else np.zeros(0)
     b[lens == 0] = 0.0
     return {"row_ptr": row_ptr, "col": col, "val": val, "xhat": xhat, "b": b.astype(dt), "m": m, "n": n}
+
+
+def index_stream_device(weights, K: int, eta: int, seed: int, device="cuda"):
+    """``index_stream`` drawn on the device: u ~ U[0,1) float64 from torch's generator, same CDF rule."""
+    import torch
+
+    w = torch.as_tensor(np.asarray(weights, dtype=np.float64), device=device)
+    cdf = torch.cumsum(w, 0)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    u = torch.rand(int(K) * int(eta), generator=g, device=device, dtype=torch.float64)
+    idx = torch.searchsorted(cdf, u * cdf[-1], right=True)
+    return torch.clamp_(idx, max=w.shape[0] - 1).to(torch.int32)
+
+
+def batched_workload(nsys: int, seed: int, device="cuda", m_lo=500, m_hi=8000, n_lo=200, frac_nnz=0.05):
+    """Batch of independent Gaussian float32 systems on the device, shapes from ``batched_shapes``.
+
+    System i uses seed ``seed + 1000*(i+1)`` for its data and ``+1`` for its row stream
+    (drawn by the caller). x_hat_i has round(frac_nnz * n_i) nonzeros; b_i = A_i x_hat_i.
+    """
+    out = []
+    for i, (m, n) in enumerate(batched_shapes(nsys, seed, m_lo, m_hi, n_lo)):
+        si = seed + 1000 * (i + 1)
+        d = dense_system_device(m, n, int(round(frac_nnz * n)), seed=si, device=device)
+        d["seed"] = si
+        out.append(d)
+    return out

@@ -274,3 +274,97 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
         if status:
             raise RskError(status, "rsk_avg_solve_multirhs (device)")
     return SolveResult(X_star, X, status, k_done, None, status_dev)
+
+
+# ---------------------------------------------------------------------------
+# Batched independent systems
+# ---------------------------------------------------------------------------
+
+@dataclass
+class BatchSystem:
+    """One system of a batch: device tensors plus its own parameters."""
+    A: torch.Tensor
+    b: torch.Tensor
+    index_stream: torch.Tensor
+    eta: int
+    K: int
+    alpha: float
+    lam: float
+    rownorm2_t: Optional[torch.Tensor] = None
+    x_star: Optional[torch.Tensor] = None
+    warm_start: bool = False
+    x_ref: Optional[torch.Tensor] = None
+    check_every: int = 0
+    tol: float = 0.0
+
+
+@dataclass
+class BatchResult:
+    x_star: list
+    x: list
+    status: Optional[list]
+    k_done: Optional[list]
+    err_hist: list
+    status_dev: torch.Tensor
+    items_dev: torch.Tensor
+    keep: list
+
+
+def solve_batched(systems, *, order=None, wg_bytes: int = 0, workspace: Optional[torch.Tensor] = None,
+                  check: bool = True) -> BatchResult:
+    """All systems in one launch; system i on G_i workgroups (largest work first by default)."""
+    if not systems:
+        raise ValueError("empty batch")
+    dev = systems[0].A.device
+    dt = systems[0].A.dtype
+    nsys = len(systems)
+    status_dev = torch.zeros((nsys, 2), dtype=torch.int32, device=dev)
+    items = (_abi.RskBatchItem * nsys)()
+    xs_out, x_out, hist_out, keep = [], [], [], []
+    for i, sy in enumerate(systems):
+        A = sy.A
+        if A.dtype != dt:
+            raise TypeError("every system of a batch has the same dtype")
+        d = dense_desc(A)
+        m, n = A.shape
+        _dev(sy.b, "b", dt, m)
+        _dev(sy.index_stream, "index_stream", torch.int32, sy.K * sy.eta)
+        r2 = sy.rownorm2_t if sy.rownorm2_t is not None else rownorm2(A)
+        keep.append(r2)  # must outlive the launch: the kernel reads it through the descriptor
+        xs = sy.x_star if sy.x_star is not None else torch.empty(n, dtype=dt, device=dev)
+        x = torch.empty(n, dtype=dt, device=dev)
+        nh = (sy.K // sy.check_every) if (sy.x_ref is not None and sy.check_every > 0) else 0
+        eh = torch.full((max(nh, 1),), float("nan"), dtype=torch.float64, device=dev) if nh else None
+        items[i] = _abi.RskBatchItem(A.data_ptr(), m, n, d.ld, sy.b.data_ptr(), r2.data_ptr(),
+                                     sy.index_stream.data_ptr(), sy.K, sy.eta, 1 if sy.warm_start else 0,
+                                     float(sy.alpha), float(sy.lam), xs.data_ptr(), x.data_ptr(),
+                                     _dev(sy.x_ref, "x_ref", dt, n), int(sy.check_every), float(sy.tol),
+                                     None if eh is None else eh.data_ptr(), status_dev[i].data_ptr())
+        xs_out.append(xs)
+        x_out.append(x)
+        hist_out.append(eh)
+    items_dev = torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(dev)
+    if order is None:
+        work = [sy.K * sy.eta * sy.A.shape[1] for sy in systems]
+        order = sorted(range(nsys), key=lambda i: -work[i])
+    order_dev = torch.tensor(list(order), dtype=torch.int32, device=dev)
+    code = _dtype_code(systems[0].A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_batched(nsys, code, ctypes.addressof(items), int(wg_bytes), ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_batched")
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = _workspace(nbytes.value, dev)
+    st = _lib().rsk_avg_solve_batched(nsys, code, ctypes.addressof(items), items_dev.data_ptr(), order_dev.data_ptr(),
+                                      int(wg_bytes), workspace.data_ptr(), workspace.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_avg_solve_batched")
+    status = k_done = None
+    if check:
+        s = status_dev.cpu().tolist()
+        status = [int(v[0]) for v in s]
+        k_done = [int(v[1]) for v in s]
+        bad = [(i, c) for i, c in enumerate(status) if c]
+        if bad:
+            raise RskError(bad[0][1], f"rsk_avg_solve_batched (device, system {bad[0][0]})")
+    return BatchResult(xs_out, x_out, status, k_done, hist_out, status_dev, items_dev, keep + [order_dev, workspace])

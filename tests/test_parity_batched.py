@@ -1,0 +1,144 @@
+"""GPU parity of the batched path: every system against its own single-system FP64 oracle run."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_10838_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _alpha(A, eta):
+    A64 = A.astype(np.float64)
+    s = np.linalg.svd(A64, compute_uv=False)
+    return oracle.optimal_alpha(eta, float((A64 * A64).sum()), float(s[0] ** 2))
+
+
+def _batch(nsys, seed, dtype, mult4, K, m_hi=700):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(nsys):
+        m = int(rng.integers(60, m_hi))
+        n = int(rng.integers(20, max(21, m // 2)))
+        if mult4:
+            n = max(4, n - n % 4)
+        sysd = inputs.dense_system(m, n, max(1, n // 20), dtype=dtype, seed=seed * 1000 + i)
+        eta = 1 + n // 10
+        idx = inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), K, eta, seed * 1000 + i + 500)
+        out.append((sysd, eta, idx, _alpha(sysd["A"], eta), 0.2 + 0.1 * (i % 5)))
+    return out
+
+
+def _systems(batch, K, cuda, **kw):
+    from paper_2203_10838_amd import rsk
+    return [rsk.BatchSystem(A=_t(s["A"], cuda), b=_t(s["b"], cuda), index_stream=_t(idx, cuda), eta=eta, K=K,
+                            alpha=al, lam=lam, **kw) for s, eta, idx, al, lam in batch]
+
+
+@pytest.mark.parametrize("dtype,mult4,wg_bytes,tol", [
+    ("f32", True, 0, 1e-4), ("f32", False, 0, 1e-4), ("f64", False, 0, 1e-10),
+    # small targets split every system over several workgroups (one-hop and two-hop exchange)
+    ("f32", True, 2048, 1e-4), ("f64", False, 1024, 1e-10), ("f32", False, 256, 1e-4)])
+def test_batched_matches_single_system_oracle(cuda, rsk_lib, dtype, mult4, wg_bytes, tol):
+    from paper_2203_10838_amd import rsk
+    K = 150
+    batch = _batch(37, 3 if mult4 else 4, dtype, mult4, K, m_hi=700 if wg_bytes != 256 else 2400)
+    res = rsk.solve_batched(_systems(batch, K, cuda), wg_bytes=wg_bytes)
+    assert all(k == K for k in res.k_done)
+    for i, (s, eta, idx, al, lam) in enumerate(batch):
+        ref = oracle.rska_dense(s["A"], s["b"], lam, eta, al, K, idx)
+        assert _rel(res.x_star[i].cpu().numpy(), ref["z"]) <= tol, i
+        assert _rel(res.x[i].cpu().numpy(), ref["x"]) <= tol, i
+
+
+def test_batched_group_equals_single_system_kernel(cuda, rsk_lib):
+    """A system alone in a batch runs the single-system kernel's code on the same G: bitwise equal."""
+    from paper_2203_10838_amd import rsk
+    K = 60
+    (s, eta, idx, al, lam), = _batch(1, 11, "f32", True, K, m_hi=2000)
+    n = s["A"].shape[1]
+    for wg_bytes in (0, 4096):
+        res = rsk.solve_batched(_systems([(s, eta, idx, al, lam)], K, cuda), wg_bytes=wg_bytes)
+        G = max(1, min(256, -(-eta * n * 4 // (wg_bytes or 48 * 1024)), -(-n // 4)))
+        single = rsk.solve_dense(_t(s["A"], cuda), _t(s["b"], cuda), lam=lam, eta=eta, alpha=al, K=K,
+                                 index_stream=_t(idx, cuda), grid=G, kernel=1)
+        a, b = res.x_star[0].cpu().numpy(), single.x_star.cpu().numpy()
+        if G % 8:
+            assert np.array_equal(a, b), (wg_bytes, G)
+        else:  # the single-system kernel permutes slices over XCDs: another partial-sum order
+            assert _rel(a, b) <= 1e-5, (wg_bytes, G)
+
+
+def test_batched_early_stop_and_errors(cuda, rsk_lib):
+    import torch
+    from paper_2203_10838_amd import rsk
+    K = 6000
+    batch = _batch(6, 9, "f64", False, K)
+    for wg_bytes in (0, 1024):
+        systems = [rsk.BatchSystem(A=_t(s["A"], cuda), b=_t(s["b"], cuda), index_stream=_t(idx, cuda), eta=eta,
+                                   K=K, alpha=al, lam=lam, x_ref=_t(s["xhat"], cuda), check_every=25, tol=1e-6)
+                   for s, eta, idx, al, lam in batch]
+        res = rsk.solve_batched(systems, wg_bytes=wg_bytes)
+        for i, (s, eta, idx, al, lam) in enumerate(batch):
+            ref = oracle.rska_dense(s["A"], s["b"], lam, eta, al, K, idx, check_every=25, xref=s["xhat"])
+            h = ref["hist"]
+            expect = (int(np.argmax(h <= 1e-6)) + 1) * 25 if (h <= 1e-6).any() else K
+            assert res.k_done[i] == expect, (wg_bytes, i, res.k_done[i], expect)
+        # a bad index in one system stops that system only
+        s, eta, idx, al, lam = batch[2]
+        bad = idx.copy()
+        bad[3 * eta] = s["A"].shape[0]
+        systems[2] = rsk.BatchSystem(A=_t(s["A"], cuda), b=_t(s["b"], cuda), index_stream=_t(bad, cuda), eta=eta,
+                                     K=100, alpha=al, lam=lam)
+        r = rsk.solve_batched(systems, check=False, wg_bytes=wg_bytes)
+        torch.cuda.synchronize()
+        st = r.status_dev.cpu().numpy()
+        assert st[2, 0] == 6 and st[2, 1] == 3
+        assert all(st[i, 0] == 0 for i in range(6) if i != 2)
+
+
+def test_batched_device_descriptor_outside_plan(cuda, rsk_lib):
+    """A device descriptor whose plan exceeds the launch's LDS is skipped with RSK_ERR_INVALID_ARG."""
+    import torch
+    from paper_2203_10838_amd import _abi, rsk
+    K = 20
+    batch = _batch(3, 21, "f32", True, K)
+    systems = _systems(batch, K, cuda)
+    res = rsk.solve_batched(systems)  # builds descriptors and checks the good path
+    items = (_abi.RskBatchItem * 3).from_buffer_copy(res.items_dev.cpu().numpy().tobytes())
+    dev_items = (_abi.RskBatchItem * 3).from_buffer_copy(bytes(items))
+    dev_items[1].eta = 20000  # needs far more LDS than planned; never read further
+    items_dev = torch.frombuffer(bytearray(bytes(dev_items)), dtype=torch.uint8).to(cuda)
+    nbytes = ctypes.c_size_t(0)
+    lib = rsk._lib()
+    assert lib.rsk_workspace_size_batched(3, 0, ctypes.addressof(items), 0, ctypes.byref(nbytes)) == 0
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=cuda)
+    assert lib.rsk_avg_solve_batched(3, 0, ctypes.addressof(items), items_dev.data_ptr(), None, 0, ws.data_ptr(),
+                                     ws.numel(), rsk._stream()) == 0
+    torch.cuda.synchronize()
+    st = res.status_dev.cpu().numpy()
+    assert st[1, 0] == 1 and st[1, 1] == 0
+    assert st[0, 0] == 0 and st[0, 1] == K and st[2, 0] == 0 and st[2, 1] == K
+
+
+def test_batched_host_checks(cuda, rsk_lib):
+    from paper_2203_10838_amd import rsk
+    K = 5
+    batch = _batch(2, 5, "f32", True, K)
+    systems = _systems(batch, K, cuda)
+    systems[1].alpha = -1.0
+    with pytest.raises(rsk.RskError, match="INVALID_ARG"):
+        rsk.solve_batched(systems)

@@ -88,7 +88,7 @@ def test_dense_deterministic_and_resume(cuda, rsk_lib):
 
 
 def test_dense_one_hop_equals_two_hop(cuda, rsk_lib):
-    """The two cross-workgroup reductions use the same summation order."""
+    """Both cross-workgroup reductions (every workgroup gathers all partials; row owners reduce) match the oracle."""
     import torch
     sysd, idx = _case(3000, 2048, 40, "f32", 5, 80, 50, 1.0)
     alpha = _alpha_star(sysd["A"], 80)
