@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["batched", "multirhs", "csr"], default=None,
+    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr"], default=None,
                     help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
@@ -136,7 +136,7 @@ def main():
     dev = torch.device("cuda:0")
     if args.only:
         stream = torch.cuda.current_stream()
-        fn = {"batched": batched_run, "multirhs": multirhs_run, "csr": csr_run}[args.only]
+        fn = {"batched": batched_run, "multirhs": multirhs_run, "adjoint": adjoint_run, "csr": csr_run}[args.only]
         print(json.dumps({args.only: fn(dev, stream)}), flush=True)
         return
     t0 = time.time()
@@ -247,6 +247,7 @@ def main():
         out["batched"] = batched_run(dev, stream)
         torch.cuda.empty_cache()
         out["multirhs"] = multirhs_run(dev, stream)
+        out["adjoint"] = adjoint_run(dev, stream)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -394,6 +395,67 @@ def multirhs_run(dev, stream, K=40):
            "plain_R_columns_us_per_step": round(t_1 * 1e3 / K * R, 1),
            "speedup_vs_R_plain": round(t_1 * R / t_m, 2)}
     log(f"[bench] multirhs: {out}")
+    return out
+
+
+ADJ_M, ADJ_N, ADJ_R, ADJ_ETA, ADJ_K, ADJ_C, ADJ_SEED = 8192, 4096, 64, 410, 200, 20, 20310838 + 400
+
+
+def adjoint_run(dev, stream):
+    """Differentiable unrolled RSKA: A 8192x4096 float32 N(0,1) (device), R = 64 right-hand sides from
+    x_hat with 40 N(0,1) nonzeros, K = 200 steps, eta = 410, lambda = 1, alpha_k = alpha*, loss
+    sum_r ||x_K - x_hat_r||^2, x* checkpoints every 20 steps. One training step = forward with
+    checkpoints + adjoint (segment recompute and reverse steps); reported as unrolled steps per second."""
+    import torch
+    from paper_2203_10838_amd import inputs, params, rsk
+    m, n, R, eta, K, C = ADJ_M, ADJ_N, ADJ_R, ADJ_ETA, ADJ_K, ADJ_C
+    g = torch.Generator(device=dev)
+    g.manual_seed(ADJ_SEED)
+    A = torch.randn((m, n), generator=g, device=dev, dtype=torch.float32)
+    rng = np.random.Generator(np.random.PCG64(ADJ_SEED + 7))
+    Xh = np.stack([inputs.sparse_vector(n, 40, rng, np.float32) for _ in range(R)], axis=1)
+    Xht = torch.from_numpy(Xh).to(dev)
+    A64 = A.double()
+    B = (A64 @ Xht.double()).float().contiguous()
+    wn = (A64 * A64).sum(1).cpu().numpy()
+    del A64
+    alpha = params.optimal_alpha(eta, float(wn.sum()), spectral_norm_sq(A))
+    ak = torch.full((K,), alpha, dtype=torch.float32, device=dev)
+    r2 = rsk.rownorm2(A)
+    idx = inputs.index_stream_device(wn, K, eta, ADJ_SEED + 1, dev)
+    ckpt = torch.empty((-(-K // C), n, R), dtype=torch.float32, device=dev)
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+
+    def fwd(with_ckpt=True):
+        return rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=1.0, K=K, index_stream=idx, alpha_k=ak,
+                                  rownorm2_t=r2, ckpt=ckpt if with_ckpt else None, ckpt_every=C, workspace=ws,
+                                  check=False)
+
+    def train_step():
+        f = fwd()
+        xbar = 2.0 * (f.x - Xht)
+        return rsk.adjoint_multirhs(A, B, lam=1.0, eta=eta, alpha_k=ak, K=K, index_stream=idx, ckpt=ckpt,
+                                    ckpt_every=C, X_star_K=f.x_star, Xbar_K=xbar, rownorm2_t=r2, workspace=ws,
+                                    check=False)
+    adj = train_step()
+    torch.cuda.synchronize()
+    if int(adj.status_dev[0].item()):
+        raise RuntimeError(f"adjoint status {adj.status_dev.tolist()}")
+    t_train = _median_ms(train_step, stream)
+    t_fwd = _median_ms(lambda: fwd(False), stream)
+    b0 = B[:, 0].contiguous()
+    t_plain = _median_ms(lambda: rsk.solve_dense(A, b0, lam=1.0, eta=eta, alpha=alpha, K=K, index_stream=idx,
+                                                 rownorm2_t=r2, check=False), stream)
+    fl = 4.0 * eta * n * R
+    out = {"workload": f"A {m}x{n} float32, R={R}, eta={eta}, K={K}, checkpoints every {C}, lambda=1, alpha_k=alpha*",
+           "adjoint_steps_per_s": round(K / (t_train * 1e-3), 1), "train_step_ms": round(t_train, 3),
+           "forward_steps_per_s": round(K / (t_fwd * 1e-3), 1), "forward_ms": round(t_fwd, 3),
+           "forward_TFLOPs": round(fl * K / (t_fwd * 1e-3) / 1e12, 2),
+           "train_TFLOPs_3x_forward_flops": round(3 * fl * K / (t_train * 1e-3) / 1e12, 2),
+           "plain_single_rhs_steps_per_s": round(K / (t_plain * 1e-3), 1),
+           "grad_norms": {"B": float(adj.Bbar.norm()), "lambda": float(adj.lambda_bar[0]),
+                          "alpha": float(adj.alpha_bar.norm())}}
+    log(f"[bench] adjoint: {out}")
     return out
 
 

@@ -217,6 +217,39 @@ int32_t rsk_workspace_size_multirhs(const rsk_dense *A, int32_t R, const rsk_par
 int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p, void *X_star,
                                void *X, void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * rsk_avg_solve_multirhs that also writes the x* checkpoints the adjoint
+ * recomputes from: before every step k with k % ckpt_every == 0, X* (n x R)
+ * is copied to ckpt[k / ckpt_every]. ckpt: device, ceil(K / ckpt_every) x n x R
+ * float32, caller-owned. Same workspace as rsk_avg_solve_multirhs.
+ */
+int32_t rsk_avg_solve_multirhs_ckpt(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p,
+                                    int32_t ckpt_every, void *X_star, void *X, void *ckpt, void *workspace,
+                                    size_t ws_bytes, void *stream);
+
+/*
+ * Reverse mode of K unrolled multi-RHS RSKA steps (eq. (rska) with per-step
+ * relaxation alpha_k, the iteration of Algorithm 1 differentiated step by
+ * step). Given Xbar_K = dL/dx_K (n x R) for any loss L of x_K = S_lambda(x*_K),
+ * computes
+ *   Bbar       dL/dB (m x R, float32, overwritten),
+ *   lambda_bar dL/dlambda (device double[1]),
+ *   alpha_bar  dL/dalpha_k (device float32[K]),
+ * with the subgradient of S_lambda taken as 1[|x*| > lambda] (0 at the kink).
+ * The forward must have been run by rsk_avg_solve_multirhs_ckpt with the same
+ * A, B, R, p and ckpt_every; X_star_K is its x*_K. Each segment of ckpt_every
+ * steps is recomputed from its checkpoint (bitwise the forward's iterates),
+ * then walked backwards: two float32 MFMA GEMMs per reverse step. Sums over
+ * workgroups and repeated rows use fixed orders: results are reproducible.
+ * p->alpha_k is required when K > 0; eta <= 4096; float32, R and n multiples of 4.
+ * Workspace: rsk_workspace_size_adjoint.
+ */
+int32_t rsk_workspace_size_adjoint(const rsk_dense *A, int32_t R, const rsk_params *p, int32_t ckpt_every,
+                                   size_t *bytes);
+int32_t rsk_avg_adjoint(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p, int32_t ckpt_every,
+                        const void *ckpt, const void *X_star_K, const void *Xbar_K, void *Bbar, double *lambda_bar,
+                        void *alpha_bar, void *workspace, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

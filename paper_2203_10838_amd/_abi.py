@@ -50,6 +50,12 @@ SIGNATURES = {
     "rsk_avg_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                     c_vp, c_sz, c_vp]),
     "rsk_rownorm2_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, c_vp]),
+    "rsk_avg_solve_multirhs_ckpt": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_i32,
+                                            c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "rsk_workspace_size_adjoint": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams), c_i32,
+                                           ctypes.POINTER(c_sz)]),
+    "rsk_avg_adjoint": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_i32, c_vp, c_vp,
+                                c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_batched": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),

@@ -305,6 +305,45 @@ int32_t batch_layout(int32_t nsys, int32_t dtype, const rsk_batch_item* items, i
   return RSK_OK;
 }
 
+void fill_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_params* p, void* X_star, void* X,
+                   const MultiPlan* plp, void* workspace, rsk::MultiRhsArgs* ap) {
+  const MultiPlan& pl = *plp;
+  rsk::MultiRhsArgs& a = *ap;
+  unsigned char* w = (unsigned char*)workspace;
+  a.A = (const float*)A->val; a.m = A->m; a.n = A->n; a.ld = A->ld;
+  a.B = (const float*)B; a.R = R; a.r2 = (const float*)p->rownorm2;
+  a.lambda = (float)p->lambda; a.alpha = (float)p->alpha; a.alpha_k = (const float*)p->alpha_k;
+  a.eta = p->eta; a.K = p->K;
+  a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
+  a.x_star = (float*)X_star; a.x = (float*)X; a.warm = p->warm_start ? 1 : 0;
+  a.status = p->status_dev;
+  a.Y = (float*)(w + pl.offY); a.C = (float*)(w + pl.offC);
+  a.S = pl.S; a.eta_pad = pl.eta_pad; a.kspan = pl.kspan;
+}
+
+// Adjoint workspace: the forward's (Y, C) then Zh, Rh, x, zbar and the partial sums.
+struct AdjLayout {
+  size_t offZh, offRh, offX, offZbar, offAbar, offLam, bytes;
+};
+
+int32_t adj_layout(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t ckpt_every, const MultiPlan& pl,
+                   AdjLayout* L) {
+  if (ckpt_every < 1) return RSK_ERR_INVALID_ARG;
+  if (p->K > 0 && !p->alpha_k) return RSK_ERR_INVALID_ARG;
+  if (p->eta > rsk::kAdjMaxEtaHost) return RSK_ERR_UNSUPPORTED;
+  const size_t nr = (size_t)A->n * R * sizeof(float), er = (size_t)pl.eta_pad * R * sizeof(float);
+  const int64_t C = ckpt_every < p->K ? ckpt_every : (p->K > 0 ? p->K : 1);
+  size_t o = pl.bytes;
+  L->offZh = o; o = align256(o + (size_t)(C + 1) * nr);
+  L->offRh = o; o = align256(o + (size_t)C * er);
+  L->offX = o; o = align256(o + nr);
+  L->offZbar = o; o = align256(o + nr);
+  L->offAbar = o; o = align256(o + rsk::adjoint_abar_parts(p->K) * sizeof(double));
+  L->offLam = o; o = align256(o + rsk::adjoint_lam_parts(A->n, R, p->K) * sizeof(double));
+  L->bytes = o;
+  return RSK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -369,22 +408,86 @@ int32_t rsk_avg_solve_multirhs(const rsk_dense* A, const void* B, int32_t R, con
   st = plan_multirhs(A, R, p, &pl);
   if (st) return st;
   if (!workspace || ws_bytes < pl.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
-  unsigned char* w = (unsigned char*)workspace;
   rsk::MultiRhsArgs a;
-  a.A = (const float*)A->val; a.m = A->m; a.n = A->n; a.ld = A->ld;
-  a.B = (const float*)B; a.R = R; a.r2 = (const float*)p->rownorm2;
-  a.lambda = (float)p->lambda; a.alpha = (float)p->alpha; a.alpha_k = (const float*)p->alpha_k;
-  a.eta = p->eta; a.K = p->K;
-  a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
-  a.x_star = (float*)X_star; a.x = (float*)X; a.warm = p->warm_start ? 1 : 0;
-  a.status = p->status_dev;
-  a.Y = (float*)(w + pl.offY); a.C = (float*)(w + pl.offC);
-  a.S = pl.S; a.eta_pad = pl.eta_pad; a.kspan = pl.kspan;
+  fill_multirhs(A, B, R, p, X_star, X, &pl, workspace, &a);
   if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
   if (rsk::launch_multirhs(a, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
   return RSK_OK;
 }
 
+
+int32_t rsk_avg_solve_multirhs_ckpt(const rsk_dense* A, const void* B, int32_t R, const rsk_params* p,
+                                    int32_t ckpt_every, void* X_star, void* X, void* ckpt, void* workspace,
+                                    size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (!B || !X_star || !X || !ckpt || ckpt_every < 1) return RSK_ERR_INVALID_ARG;
+  MultiPlan pl;
+  st = plan_multirhs(A, R, p, &pl);
+  if (st) return st;
+  if (!workspace || ws_bytes < pl.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
+  rsk::MultiRhsArgs a;
+  fill_multirhs(A, B, R, p, X_star, X, &pl, workspace, &a);
+  if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
+  if (rsk::launch_multirhs(a, (hipStream_t)stream, (float*)ckpt, ckpt_every) != hipSuccess) return RSK_ERR_HIP;
+  return RSK_OK;
+}
+
+int32_t rsk_workspace_size_adjoint(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t ckpt_every,
+                                   size_t* bytes) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  st = check_params(p, A->m);
+  if (st) return st;
+  MultiPlan pl;
+  st = plan_multirhs(A, R, p, &pl);
+  if (st) return st;
+  AdjLayout L;
+  st = adj_layout(A, R, p, ckpt_every, pl, &L);
+  if (st) return st;
+  *bytes = L.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_avg_adjoint(const rsk_dense* A, const void* B, int32_t R, const rsk_params* p, int32_t ckpt_every,
+                        const void* ckpt, const void* X_star_K, const void* Xbar_K, void* Bbar, double* lambda_bar,
+                        void* alpha_bar, void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (!B || !X_star_K || !Xbar_K || !Bbar || !lambda_bar || (p->K > 0 && (!ckpt || !alpha_bar)))
+    return RSK_ERR_INVALID_ARG;
+  MultiPlan pl;
+  st = plan_multirhs(A, R, p, &pl);
+  if (st) return st;
+  AdjLayout L;
+  st = adj_layout(A, R, p, ckpt_every, pl, &L);
+  if (st) return st;
+  if (!workspace || ws_bytes < L.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
+  unsigned char* w = (unsigned char*)workspace;
+  rsk::AdjointArgs d;
+  fill_multirhs(A, B, R, p, w + L.offZh, w + L.offX, &pl, workspace, &d.f);
+  d.f.warm = 1;
+  d.ckpt = (const float*)ckpt;
+  d.ckpt_every = ckpt_every;
+  d.zK = (const float*)X_star_K;
+  d.xbarK = (const float*)Xbar_K;
+  d.Bbar = (float*)Bbar;
+  d.lambda_bar = lambda_bar;
+  d.alpha_bar = (float*)alpha_bar;
+  d.Zh = (float*)(w + L.offZh);
+  d.Rh = (float*)(w + L.offRh);
+  d.zbar = (float*)(w + L.offZbar);
+  d.abar_part = (double*)(w + L.offAbar);
+  d.lam_part = (double*)(w + L.offLam);
+  if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
+  if (rsk::launch_adjoint(d, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
+  return RSK_OK;
+}
 
 int32_t rsk_rownorm2_csr(const rsk_csr* A, void* rownorm2, void* stream) {
   int32_t st = check_csr(A);

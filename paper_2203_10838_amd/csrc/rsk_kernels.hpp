@@ -124,7 +124,30 @@ struct MultiRhsArgs {
   int S, eta_pad;
   int64_t kspan;
 };
-hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream);
+// ckpt (nullable): x*_k is copied to ckpt[k / ckpt_every] before every step k with k % ckpt_every == 0.
+hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckpt = nullptr, int64_t ckpt_every = 1);
+
+// Reverse mode of K multi-RHS steps. f holds the forward's arguments (alpha_k required);
+// workspace pieces: Zh (ckpt_every+1) n x R, Rh ckpt_every eta_pad x R, zbar n x R, partial sums.
+struct AdjointArgs {
+  MultiRhsArgs f;
+  const float* ckpt;      // ceil(K / ckpt_every) x n x R, x* at steps 0, C, 2C, ...
+  int64_t ckpt_every;
+  const float* zK;        // x*_K of the forward
+  const float* xbarK;     // dL/dx_K, n x R
+  float* Bbar;            // m x R, out
+  double* lambda_bar;     // 1, out
+  float* alpha_bar;       // K, out
+  float* Zh;
+  float* Rh;
+  float* zbar;
+  double* abar_part;
+  double* lam_part;
+};
+constexpr int kAdjMaxEtaHost = 4096;
+size_t adjoint_lam_parts(int64_t n, int R, int64_t K);
+size_t adjoint_abar_parts(int64_t K);
+hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream);
 
 // Batched independent systems. System s is solved by G_s workgroups running
 // the dense kernel's per-workgroup code on its own workspace region. The plan

@@ -109,9 +109,11 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
 
 // C[t][r] = (alpha_k/eta) (sum_s Y[s][t][r] - B[tau_t, r]) / ||a_tau_t||^2; checks the step's
 // indices and coefficients, marks the step done. grid-stride over eta_pad x R.
+// With Rh non-null the residuals R_tau = sum_s Y_s - B_tau are stored as well (the adjoint's recompute).
 __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, const int32_t* __restrict__ tau, int eta,
                             const float* __restrict__ B, int R, const float* __restrict__ r2, float alpha,
-                            const float* __restrict__ alpha_k, int64_t k, float* __restrict__ C, int* status) {
+                            const float* __restrict__ alpha_k, int64_t k, float* __restrict__ C,
+                            float* __restrict__ Rh, int* status) {
   if (status[0]) return;
   const float scale = (alpha_k ? alpha_k[k] : alpha) / (float)eta;
   const size_t total = (size_t)eta_pad * R;
@@ -124,8 +126,12 @@ __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, con
       for (int s = 0; s < S; ++s) y += Y[(size_t)s * total + e];
       const float rn = r2[i];
       if (rn == 0.f) set_status(status, ST_ZERO_ROW);
-      c = scale * (y - B[(int64_t)i * R + r]) / rn;
+      const float res = y - B[(int64_t)i * R + r];
+      if (Rh) Rh[e] = res;
+      c = scale * res / rn;
       if (!isfinite(c)) set_status(status, ST_NONFINITE);
+    } else if (Rh) {
+      Rh[e] = 0.f;
     }
     C[e] = c;
   }
@@ -144,11 +150,13 @@ __global__ void step_check(const int32_t* __restrict__ tau, int eta, int64_t m, 
   }
 }
 
-// W = A_tau^T C; epilogue X*[j][r] -= W, X[j][r] = S_lambda(X*). grid = (ceil(n/64), R/64).
+// W = A_tau^T C; epilogue Zout[j][r] = Zin[j][r] - W, X[j][r] = S_lambda(Zout) (Zin may equal Zout:
+// every element is read and written by one thread). grid = (ceil(n/64), R/64).
 __global__ __launch_bounds__(NTH) void gemm_att_c_update(const float* __restrict__ A, int64_t ld, int64_t n,
                                                          const int32_t* __restrict__ tau, int eta,
-                                                         const float* __restrict__ C, int R, float* __restrict__ Xs,
-                                                         float* __restrict__ X, float lambda, const int* status) {
+                                                         const float* __restrict__ C, int R, const float* Zin,
+                                                         float* Zout, float* __restrict__ X, float lambda,
+                                                         const int* status) {
   if (status[0]) return;
   __shared__ float As[BK][BM];
   __shared__ float Bs[BK][BN];
@@ -186,8 +194,8 @@ __global__ __launch_bounds__(NTH) void gemm_att_c_update(const float* __restrict
         const int r = r0 + wn * 32 + j * 16 + (lane & 15);
         if (jj < n && r < R) {
           const size_t o = (size_t)jj * R + r;
-          const float z = Xs[o] - acc[i][j][v];
-          Xs[o] = z;
+          const float z = Zin[o] - acc[i][j][v];
+          Zout[o] = z;
           X[o] = shrink(z, lambda);
         }
       }
@@ -201,26 +209,294 @@ __global__ void init_multirhs(float* Xs, float* X, size_t total, float lambda, i
   }
 }
 
-hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream) {
+// One forward step k: R_tau from x, C, Zout = Zin - A_tau^T C, x = S_lambda(Zout), then the
+// next step's index check (or the final step count).
+static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, float* zout, float* rh,
+                          hipStream_t stream) {
+  const int gt = (a.eta + BM - 1) / BM;
+  const int gr = (a.R + BN - 1) / BN;
+  const int gn = (int)((a.n + BM - 1) / BM);
+  const int32_t* tk = a.idx + k * (int64_t)a.eta;
+  hipLaunchKernelGGL(gemm_at_x, dim3(gt, gr, a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R, a.Y,
+                     a.eta_pad, a.kspan, a.status);
+  hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
+                     a.alpha, a.alpha_k, k, a.C, rh, a.status);
+  hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R, zin,
+                     zout, a.x, a.lambda, a.status);
+  const int32_t* tn = (k + 1 < a.K) ? tk + a.eta : tk;
+  hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, tn, (k + 1 < a.K) ? a.eta : 0, a.m, a.status,
+                     k + 1);
+}
+
+hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckpt, int64_t ckpt_every) {
   const size_t total = (size_t)a.n * a.R;
   hipLaunchKernelGGL(init_multirhs, dim3(1024), dim3(256), 0, stream, a.x_star, a.x, total, a.lambda, a.warm);
   if (a.K > 0)
     hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, a.idx, a.eta, a.m, a.status, (int64_t)0);
+  for (int64_t k = 0; k < a.K; ++k) {
+    if (ckpt && k % ckpt_every == 0) {
+      hipError_t e = hipMemcpyAsync(ckpt + (size_t)(k / ckpt_every) * total, a.x_star, total * sizeof(float),
+                                    hipMemcpyDeviceToDevice, stream);
+      if (e != hipSuccess) return e;
+    }
+    multirhs_step(a, k, a.x_star, a.x_star, nullptr, stream);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of K unrolled multi-RHS steps (reverse mode, loss gradient dL/dx_K given).
+//
+// With z = x*, m_k = 1[|z_k| > lambda], A_k = A_tau_k, r_k = A_k x_k - B_tau_k and
+// D_k^-2 = diag(1/||a_tau||^2), the step z_{k+1} = z_k - (alpha_k/eta) A_k^T D_k^-2 r_k,
+// x_k = S_lambda(z_k) has the reverse step
+//   cbar = -A_k zbar_{k+1}                        (GEMM over n, as gemm_at_x)
+//   alphabar_k = <cbar, D_k^-2 r_k> / eta           (summed over the R columns)
+//   rbar = (alpha_k/eta) D_k^-2 cbar
+//   Bbar[tau_t] -= rbar_t                           (repeated rows each time)
+//   xbar_k = A_k^T rbar                             (GEMM over eta, as gemm_att)
+//   zbar_k = zbar_{k+1} + m_k . xbar_k,   lambdabar -= sum sign(z_k) m_k xbar_k
+// seeded with zbar_K = m_K . xbar_K and lambdabar = -sum sign(z_K) m_K xbar_K.
+// z_k and r_k of a segment of C steps are recomputed from the segment's x*
+// checkpoint with the forward kernels (bitwise the forward's values). All sums
+// over workgroups go through per-block partials added in a fixed order.
+// ---------------------------------------------------------------------------
+
+constexpr int kAdjCoefBlocks = 64;
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) t += red[w];
+  return t;  // valid in thread 0
+}
+
+// zbar = m_K . xbar_K; partial of lambdabar per block. grid = kAdjSeedBlocks.
+constexpr int kAdjSeedBlocks = 256;
+__global__ __launch_bounds__(256) void adj_seed(const float* __restrict__ zK, const float* __restrict__ xbarK,
+                                                size_t total, float lambda, float* __restrict__ zbar,
+                                                double* __restrict__ lam_part, const int* status) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const float z = zK[e], xb = xbarK[e];
+    const bool on = fabsf(z) > lambda;
+    zbar[e] = on ? xb : 0.f;
+    if (on) acc -= (z > 0.f ? 1.0 : -1.0) * (double)xb;
+  }
+  const double t = block_sum_d(acc, red);
+  if (threadIdx.x == 0) lam_part[blockIdx.x] = status[0] ? 0.0 : t;
+}
+
+// rbar and the alphabar partials of step k. grid = kAdjCoefBlocks, grid-stride over eta_pad x R.
+__global__ __launch_bounds__(256) void adj_coef(const float* __restrict__ Y, int S, int eta_pad,
+                                                const int32_t* __restrict__ tau, int eta, const float* __restrict__ Rk,
+                                                int R, const float* __restrict__ r2, const float* __restrict__ alpha_k,
+                                                int64_t k, float* __restrict__ Rbar, double* __restrict__ abar_part,
+                                                const int* status) {
+  __shared__ double red[4];
+  const size_t total = (size_t)eta_pad * R;
+  const float ak = alpha_k[k];
+  double acc = 0.0;
+  if (!status[0]) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+      const int t = (int)(e / R);
+      float rb = 0.f;
+      if (t < eta) {
+        float y = 0.f;
+        for (int s = 0; s < S; ++s) y += Y[(size_t)s * total + e];
+        const float cbar = -y;
+        const float rn = r2[tau[t]];
+        rb = (ak / (float)eta) * cbar / rn;
+        acc += (double)cbar * (double)Rk[e] / ((double)eta * (double)rn);
+      }
+      Rbar[e] = rb;
+    }
+  }
+  const double t = block_sum_d(acc, red);
+  if (threadIdx.x == 0) abar_part[k * kAdjCoefBlocks + blockIdx.x] = t;
+}
+
+// Bbar[tau_t][r] -= rbar[t][r]; rows repeated within the step are summed in
+// ascending t by the first occurrence (no two threads touch one element).
+constexpr int kAdjMaxEta = 4096;
+__global__ __launch_bounds__(1024) void adj_bbar(const int32_t* __restrict__ tau, int eta,
+                                                 const float* __restrict__ Rbar, int R, float* __restrict__ Bbar,
+                                                 const int* status) {
+  __shared__ int st[kAdjMaxEta];
+  __shared__ int nx[kAdjMaxEta];
+  __shared__ unsigned char first[kAdjMaxEta];
+  if (status[0]) return;
+  for (int t = threadIdx.x; t < eta; t += blockDim.x) {
+    st[t] = tau[t];
+    first[t] = 1;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < eta; t += blockDim.x) {
+    int nt = -1;
+    for (int u = t + 1; u < eta; ++u)
+      if (st[u] == st[t]) { nt = u; break; }
+    nx[t] = nt;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < eta; t += blockDim.x)
+    if (nx[t] >= 0) first[nx[t]] = 0;
+  __syncthreads();
+  for (size_t e = threadIdx.x; e < (size_t)eta * R; e += blockDim.x) {
+    const int t = (int)(e / R), r = (int)(e % R);
+    if (!first[t]) continue;
+    float sum = 0.f;
+    for (int u = t; u >= 0; u = nx[u]) sum += Rbar[(size_t)u * R + r];
+    Bbar[(int64_t)st[t] * R + r] -= sum;
+  }
+}
+
+// xbar = A_tau^T Rbar (MFMA as gemm_att_c_update); epilogue zbar += m_k . xbar and the
+// lambdabar partial of the block. grid = (ceil(n/64), R/64).
+__global__ __launch_bounds__(NTH) void gemm_att_adj(const float* __restrict__ A, int64_t ld, int64_t n,
+                                                    const int32_t* __restrict__ tau, int eta,
+                                                    const float* __restrict__ Rbar, int R, const float* __restrict__ Zk,
+                                                    float* __restrict__ zbar, float lambda,
+                                                    double* __restrict__ lam_part, const int* status) {
+  __shared__ float As[BK][BM];
+  __shared__ float Bs[BK][BN];
+  __shared__ double red[4];
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  if (status[0]) {
+    if (threadIdx.x == 0) lam_part[blk] = 0.0;
+    return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t j0 = (int64_t)blockIdx.x * BM;
+  const int r0 = blockIdx.y * BN;
+  const int lt = tid >> 4, lc = (tid & 15) * 4;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int t0 = 0; t0 < eta; t0 += BK) {
+    const int t = t0 + lt;
+    float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < eta && j0 + lc < n) av = *reinterpret_cast<const float4*>(A + (int64_t)tau[t] * ld + j0 + lc);
+    float4 cv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < eta && r0 + lc < R) cv = *reinterpret_cast<const float4*>(Rbar + (size_t)t * R + r0 + lc);
+    __syncthreads();
+    *reinterpret_cast<float4*>(&As[lt][lc]) = av;
+    *reinterpret_cast<float4*>(&Bs[lt][lc]) = cv;
+    __syncthreads();
+    mma_tile(As, Bs, wm, wn, lane, acc);
+  }
+  double lp = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t jj = j0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int r = r0 + wn * 32 + j * 16 + (lane & 15);
+        if (jj < n && r < R) {
+          const size_t o = (size_t)jj * R + r;
+          const float z = Zk[o];
+          if (fabsf(z) > lambda) {
+            const float xb = acc[i][j][v];
+            zbar[o] += xb;
+            lp -= (z > 0.f ? 1.0 : -1.0) * (double)xb;
+          }
+        }
+      }
+  const double t = block_sum_d(lp, red);
+  if (threadIdx.x == 0) lam_part[blk] = t;
+}
+
+// alpha_bar[k] = sum of the step's partials; lambda_bar = seed partials, then steps 0..K-1, each in order.
+__global__ __launch_bounds__(256) void adj_finish(const double* __restrict__ abar_part,
+                                                  const double* __restrict__ lam_part, int64_t K, int nblk_att,
+                                                  float* __restrict__ alpha_bar, double* __restrict__ lambda_bar,
+                                                  const int* status) {
+  __shared__ double red[256];
+  for (int64_t k = threadIdx.x; k < K; k += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < kAdjCoefBlocks; ++b) s += abar_part[k * kAdjCoefBlocks + b];
+    alpha_bar[k] = status[0] ? 0.f : (float)s;
+  }
+  // lam_part: [kAdjSeedBlocks] seed, then K x nblk_att
+  double s = 0.0;
+  const int64_t total = kAdjSeedBlocks + K * (int64_t)nblk_att;
+  const int64_t per = (total + blockDim.x - 1) / blockDim.x;
+  for (int64_t i = threadIdx.x * per; i < (threadIdx.x + 1) * per && i < total; ++i) s += lam_part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)blockDim.x; ++w) t += red[w];
+    *lambda_bar = status[0] ? 0.0 : t;
+  }
+}
+
+__global__ void fill_zero_f32(float* p, size_t total) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+    p[e] = 0.f;
+}
+
+size_t adjoint_lam_parts(int64_t n, int R, int64_t K) {
+  const int gr = (R + BN - 1) / BN;
+  const int gn = (int)((n + BM - 1) / BM);
+  return kAdjSeedBlocks + (size_t)K * gn * gr;
+}
+size_t adjoint_abar_parts(int64_t K) { return (size_t)(K > 0 ? K : 1) * kAdjCoefBlocks; }
+
+hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
+  const MultiRhsArgs& a = d.f;
+  const size_t total = (size_t)a.n * a.R;
+  const size_t etot = (size_t)a.eta_pad * a.R;
   const int gt = (a.eta + BM - 1) / BM;
   const int gr = (a.R + BN - 1) / BN;
   const int gn = (int)((a.n + BM - 1) / BM);
-  for (int64_t k = 0; k < a.K; ++k) {
-    const int32_t* tk = a.idx + k * (int64_t)a.eta;
-    hipLaunchKernelGGL(gemm_at_x, dim3(gt, gr, a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R, a.Y,
-                       a.eta_pad, a.kspan, a.status);
-    hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
-                       a.alpha, a.alpha_k, k, a.C, a.status);
-    hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
-                       a.x_star, a.x, a.lambda, a.status);
-    const int32_t* tn = (k + 1 < a.K) ? tk + a.eta : tk;
-    hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, tn, (k + 1 < a.K) ? a.eta : 0, a.m, a.status,
-                       k + 1);
+  const int nblk_att = gn * gr;
+  hipLaunchKernelGGL(fill_zero_f32, dim3(1024), dim3(256), 0, stream, d.Bbar, (size_t)a.m * a.R);
+  hipLaunchKernelGGL(adj_seed, dim3(kAdjSeedBlocks), dim3(256), 0, stream, d.zK, d.xbarK, total, a.lambda, d.zbar,
+                     d.lam_part, a.status);
+  const int64_t C = d.ckpt_every;
+  const int64_t nseg = (a.K + C - 1) / C;
+  MultiRhsArgs f = a;
+  for (int64_t s = nseg - 1; s >= 0; --s) {
+    const int64_t k0 = s * C, k1 = (k0 + C < a.K) ? k0 + C : a.K;
+    // recompute z_k0..z_k1 and r_k0..r_{k1-1} from the checkpoint
+    hipError_t e = hipMemcpyAsync(d.Zh, d.ckpt + (size_t)s * total, total * sizeof(float), hipMemcpyDeviceToDevice,
+                                  stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(init_multirhs, dim3(1024), dim3(256), 0, stream, d.Zh, a.x, total, a.lambda, 1);
+    // the segment's first indices are range-checked before any kernel reads A with them
+    hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, a.idx + k0 * (int64_t)a.eta, a.eta, a.m, a.status,
+                       k0);
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t j = k - k0;
+      f.K = k1;  // the step check after the segment's last step is skipped
+      multirhs_step(f, k, d.Zh + (size_t)j * total, d.Zh + (size_t)(j + 1) * total, d.Rh + (size_t)j * etot, stream);
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const int64_t j = k - k0;
+      const int32_t* tk = a.idx + k * (int64_t)a.eta;
+      hipLaunchKernelGGL(gemm_at_x, dim3(gt, gr, a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, d.zbar, a.R,
+                         a.Y, a.eta_pad, a.kspan, a.status);
+      hipLaunchKernelGGL(adj_coef, dim3(kAdjCoefBlocks), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta,
+                         d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
+      hipLaunchKernelGGL(adj_bbar, dim3(1), dim3(1024), 0, stream, tk, a.eta, a.C, a.R, d.Bbar, a.status);
+      hipLaunchKernelGGL(gemm_att_adj, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
+                         d.Zh + (size_t)j * total, d.zbar, a.lambda,
+                         d.lam_part + kAdjSeedBlocks + (size_t)k * nblk_att, a.status);
+    }
   }
+  hipLaunchKernelGGL(adj_finish, dim3(1), dim3(256), 0, stream, d.abar_part, d.lam_part, a.K, nblk_att, d.alpha_bar,
+                     d.lambda_bar, a.status);
   return hipGetLastError();
 }
 

@@ -236,8 +236,13 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
                    index_stream: torch.Tensor, stream_offset: int = 0, alpha_k: Optional[torch.Tensor] = None,
                    rownorm2_t: Optional[torch.Tensor] = None, X_star: Optional[torch.Tensor] = None,
                    warm_start: bool = False, workspace: Optional[torch.Tensor] = None,
+                   ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
                    check: bool = True) -> SolveResult:
-    """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major)."""
+    """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major).
+
+    With ``ckpt`` (ceil(K/ckpt_every) x n x R float32) the x* checkpoints the
+    adjoint recomputes from are written as well.
+    """
     m, n = A.shape
     if B.dim() != 2 or B.shape[0] != m:
         raise ValueError("B must be m x R")
@@ -263,8 +268,17 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
         raise RskError(st, "rsk_workspace_size_multirhs")
     if workspace is None or workspace.numel() < nbytes.value:
         workspace = _workspace(nbytes.value, A.device)
-    st = _lib().rsk_avg_solve_multirhs(ctypes.byref(d), B.data_ptr(), R, ctypes.byref(params), X_star.data_ptr(),
-                                       X.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    if ckpt is not None:
+        if ckpt_every < 1:
+            raise ValueError("ckpt needs ckpt_every >= 1")
+        _dev(ckpt, "ckpt", dt, max(1, -(-K // ckpt_every)) * n * R)
+        st = _lib().rsk_avg_solve_multirhs_ckpt(ctypes.byref(d), B.data_ptr(), R, ctypes.byref(params),
+                                                int(ckpt_every), X_star.data_ptr(), X.data_ptr(), ckpt.data_ptr(),
+                                                workspace.data_ptr(), workspace.numel(), _stream())
+    else:
+        st = _lib().rsk_avg_solve_multirhs(ctypes.byref(d), B.data_ptr(), R, ctypes.byref(params),
+                                           X_star.data_ptr(), X.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                           _stream())
     if st:
         raise RskError(st, "rsk_avg_solve_multirhs")
     status = k_done = None
@@ -274,6 +288,54 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
         if status:
             raise RskError(status, "rsk_avg_solve_multirhs (device)")
     return SolveResult(X_star, X, status, k_done, None, status_dev)
+
+
+@dataclass
+class AdjointResult:
+    Bbar: torch.Tensor
+    lambda_bar: torch.Tensor
+    alpha_bar: torch.Tensor
+    status_dev: torch.Tensor
+
+
+def adjoint_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, alpha_k: torch.Tensor, K: int,
+                     index_stream: torch.Tensor, ckpt: torch.Tensor, ckpt_every: int, X_star_K: torch.Tensor,
+                     Xbar_K: torch.Tensor, stream_offset: int = 0, rownorm2_t: Optional[torch.Tensor] = None,
+                     workspace: Optional[torch.Tensor] = None, check: bool = True) -> AdjointResult:
+    """dL/dB, dL/dlambda, dL/dalpha_k of K unrolled multi-RHS steps, given Xbar_K = dL/dx_K."""
+    m, n = A.shape
+    R = B.shape[1]
+    dt = A.dtype
+    _dev(B, "B", dt, m * R)
+    _dev(X_star_K, "X_star_K", dt, n * R)
+    _dev(Xbar_K, "Xbar_K", dt, n * R)
+    _dev(alpha_k, "alpha_k", dt, K)
+    if rownorm2_t is None:
+        rownorm2_t = rownorm2(A)
+    status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
+    params = make_params(lam=lam, eta=eta, alpha=1.0, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
+                         status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, dtype=dt)
+    d = dense_desc(A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_adjoint(ctypes.byref(d), R, ctypes.byref(params), int(ckpt_every),
+                                           ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_adjoint")
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = _workspace(nbytes.value, A.device)
+    Bbar = torch.empty((m, R), dtype=dt, device=A.device)
+    lbar = torch.zeros(1, dtype=torch.float64, device=A.device)
+    abar = torch.zeros(max(K, 1), dtype=dt, device=A.device)
+    st = _lib().rsk_avg_adjoint(ctypes.byref(d), B.data_ptr(), R, ctypes.byref(params), int(ckpt_every),
+                                ckpt.data_ptr(), X_star_K.data_ptr(), Xbar_K.data_ptr(), Bbar.data_ptr(),
+                                lbar.data_ptr(), abar.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_avg_adjoint")
+    if check:
+        s = int(status_dev[0].item())
+        if s:
+            raise RskError(s, "rsk_avg_adjoint (device)")
+    return AdjointResult(Bbar, lbar, abar[:K], status_dev)
 
 
 # ---------------------------------------------------------------------------
