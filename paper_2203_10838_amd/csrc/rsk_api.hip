@@ -143,7 +143,7 @@ int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
     pl->tile_cache = ((size_t)p->eta * pl->wq_max * pl->vec * s) <= kTileCacheBytes;
     pl->two_hop = ((int64_t)G * p->eta * pl->W) > kOneHopWords;
     size_t lds = 0;
-    const int64_t xr = pl->two_hop ? 0 : (int64_t)G * p->eta;
+    const int64_t xr = pl->two_hop ? 0 : rsk::onehop_lds_elems(G, p->eta);
     int maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, pl->tile_cache, xr, &lds);
     if (maxg == 0 && pl->tile_cache) {
       pl->tile_cache = 0;

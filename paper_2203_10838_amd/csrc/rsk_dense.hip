@@ -98,7 +98,7 @@ template <typename T>
 hipError_t launch_dense(DenseArgs<T>& a, int vec, hipStream_t stream, int* max_grid_out) {
   size_t lds = 0;
   const int maxg = dense_max_grid<T>(vec, a.eta, a.wq_max, a.tile_cache,
-                                     a.two_hop ? 0 : (int64_t)a.G * a.eta, &lds);
+                                     a.two_hop ? 0 : onehop_lds_elems(a.G, a.eta), &lds);
   if (max_grid_out) *max_grid_out = maxg;
   if (maxg < a.G) return hipErrorCooperativeLaunchTooLarge;
   void* fn = dense_kernel_for<T>(vec);

@@ -133,7 +133,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
   const bool solo = G == 1;
   const bool pf_regs = eta <= PF * NT;
 
-  DenseSmem L(sizeof(T), VEC, a.wq_max, eta, NT, a.tile_cache, a.two_hop ? 0 : (int64_t)G * eta);
+  DenseSmem L(sizeof(T), VEC, a.wq_max, eta, NT, a.tile_cache, a.two_hop ? 0 : onehop_lds_elems(G, eta));
   T* xs = reinterpret_cast<T*>(smem + L.xs);
   T* xv = reinterpret_cast<T*>(smem + L.xv);
   T* cs = reinterpret_cast<T*>(smem + L.cs);
@@ -208,47 +208,77 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
     // 2. partial dots over the own columns: every lane issues the loads of
     //    U rows x QU chunks before it uses any (rows past eta load a valid
     //    row and are discarded), so a batch costs one memory round trip
-    for (int tb = wave * rpw; tb < eta; tb += rstride * U) {
-      T acc[U];
-      const T* rowp[U];
+    if (eta <= rstride) {
+      // at most one row per lane group: keep 8 chunks of that row in flight instead
+      constexpr int QC = 8;
+      const int t = wave * rpw + rs;
+      if (t < eta) {
+        const T* rowp = a.A + (int64_t)tau[t] * a.ld + c0;
+        T acc = T(0);
+        for (int qb = cl; qb < wq; qb += lpr * QC) {
+          V v[QC];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        acc[u] = T(0);
-        const int t = tb + u * rstride + rs;
-        rowp[u] = a.A + (int64_t)tau[t < eta ? t : eta - 1] * a.ld + c0;
-      }
-      for (int qb = cl; qb < wq; qb += lpr * QU) {
-        V v[QU][U];
+          for (int h = 0; h < QC; ++h) {
+            const int q = qb + h * lpr < wq ? qb + h * lpr : wq - 1;
+            v[h] = load_vec<T, VEC>(rowp, (int64_t)q * VEC, a.n - c0);
+          }
 #pragma unroll
-        for (int h = 0; h < QU; ++h) {
-          const int q = qb + h * lpr < wq ? qb + h * lpr : wq - 1;
+          for (int h = 0; h < QC; ++h) {
+            const int q = qb + h * lpr;
+            if (q < wq) {
+              if (a.tile_cache) tile[(size_t)t * wq + q] = v[h];
+              const V xx = reinterpret_cast<const V*>(xv)[q];
 #pragma unroll
-          for (int u = 0; u < U; ++u) v[h][u] = load_vec<T, VEC>(rowp[u], (int64_t)q * VEC, a.n - c0);
+              for (int e = 0; e < VEC; ++e) acc += v[h].v[e] * xx.v[e];
+            }
+          }
         }
+        acc = group_sum(acc, lpr);
+        if (cl == 0) cs[t] = acc;
+      }
+    } else {
+      for (int tb = wave * rpw; tb < eta; tb += rstride * U) {
+        T acc[U];
+        const T* rowp[U];
 #pragma unroll
-        for (int h = 0; h < QU; ++h) {
-          const int q = qb + h * lpr;
-          if (q < wq) {
-            const V xx = reinterpret_cast<const V*>(xv)[q];
+        for (int u = 0; u < U; ++u) {
+          acc[u] = T(0);
+          const int t = tb + u * rstride + rs;
+          rowp[u] = a.A + (int64_t)tau[t < eta ? t : eta - 1] * a.ld + c0;
+        }
+        for (int qb = cl; qb < wq; qb += lpr * QU) {
+          V v[QU][U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int t = tb + u * rstride + rs;
-              if (t < eta) {
-                if (a.tile_cache) tile[(size_t)t * wq + q] = v[h][u];
+          for (int h = 0; h < QU; ++h) {
+            const int q = qb + h * lpr < wq ? qb + h * lpr : wq - 1;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[u] += v[h][u].v[e] * xx.v[e];
+            for (int u = 0; u < U; ++u) v[h][u] = load_vec<T, VEC>(rowp[u], (int64_t)q * VEC, a.n - c0);
+          }
+#pragma unroll
+          for (int h = 0; h < QU; ++h) {
+            const int q = qb + h * lpr;
+            if (q < wq) {
+              const V xx = reinterpret_cast<const V*>(xv)[q];
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                const int t = tb + u * rstride + rs;
+                if (t < eta) {
+                  if (a.tile_cache) tile[(size_t)t * wq + q] = v[h][u];
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) acc[u] += v[h][u].v[e] * xx.v[e];
+                }
               }
             }
           }
         }
-      }
-      T sum[U];
+        T sum[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) sum[u] = group_sum(acc[u], lpr);
+        for (int u = 0; u < U; ++u) sum[u] = group_sum(acc[u], lpr);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int t = tb + u * rstride + rs;
-        if (t < eta && cl == 0) cs[t] = sum[u];
+        for (int u = 0; u < U; ++u) {
+          const int t = tb + u * rstride + rs;
+          if (t < eta && cl == 0) cs[t] = sum[u];
+        }
       }
     }
     // publish the partials in one coalesced pass: on this architecture a
@@ -282,12 +312,35 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
       for (int t = tid; t < eta; t += NT) cs[t] = coef_of(cs[t], bq[t], rq[t], ak, eta, zero_row);
     } else if (!a.two_hop) {
       // every workgroup gathers all G*eta partials in one round, then sums
-      // each row over q = 0..G-1 in order
+      // each row in a fixed order: segments of kOneHopSeg workgroups in
+      // ascending q (loads unrolled), then the segment sums in ascending order
       poll_flat<T>(xP, G * eta, tid, NT, tag, xr, lerr);
+      __syncthreads();
+      constexpr int SG = kOneHopSeg;
+      const int nseg = (G + SG - 1) / SG;
+      T* part = xr + G * eta;
+      for (int p = tid; p < eta * nseg; p += NT) {
+        const int t = p % eta, q0 = (p / eta) * SG;
+        T v[SG];
+#pragma unroll
+        for (int u = 0; u < SG; ++u) v[u] = q0 + u < G ? xr[(q0 + u) * eta + t] : T(0);
+        T sum = T(0);
+#pragma unroll
+        for (int u = 0; u < SG; ++u)
+          if (q0 + u < G) sum += v[u];
+        part[p] = sum;
+      }
       __syncthreads();
       for (int t = tid; t < eta; t += NT) {
         T sum = T(0);
-        for (int q = 0; q < G; ++q) sum += xr[q * eta + t];
+        for (int j0 = 0; j0 < nseg; j0 += SG) {
+          T v[SG];
+#pragma unroll
+          for (int u = 0; u < SG; ++u) v[u] = j0 + u < nseg ? part[(j0 + u) * eta + t] : T(0);
+#pragma unroll
+          for (int u = 0; u < SG; ++u)
+            if (j0 + u < nseg) sum += v[u];
+        }
         cs[t] = coef_of(sum, bq[t], rq[t], ak, eta, zero_row);
       }
     } else {

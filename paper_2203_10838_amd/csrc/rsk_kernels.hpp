@@ -68,6 +68,13 @@ struct DenseSmem {
   }
 };
 
+// LDS values of the one-hop gather: the G*eta partials and the per-row sums
+// of their segments of kOneHopSeg workgroups.
+constexpr int kOneHopSeg = 16;
+__host__ __device__ inline int64_t onehop_lds_elems(int64_t G, int64_t eta) {
+  return G * eta + (G + kOneHopSeg - 1) / kOneHopSeg * eta;
+}
+
 // Exchange words per step (G*eta*words per value) at or below which every
 // workgroup gathers all partials (one flat poll of at most 16 words per
 // thread of a 256-thread workgroup, then per-row sums in LDS).
@@ -175,7 +182,7 @@ __host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int 
   if (G > gmax) G = gmax;
   for (;;) {
     const int wq = (int)((nchunks + G - 1) / G);
-    const int64_t xr = G * eta * (esize / 4) > kOneHopWords ? 0 : G * eta;
+    const int64_t xr = G * eta * (esize / 4) > kOneHopWords ? 0 : onehop_lds_elems(G, eta);
     const DenseSmem with_tile(esize, vec, wq, eta, kDenseThreads, 1, xr);
     const DenseSmem no_tile(esize, vec, wq, eta, kDenseThreads, 0, xr);
     if (with_tile.total <= kBatchLdsCap || no_tile.total <= kBatchLdsCap) {

@@ -323,37 +323,61 @@ __global__ __launch_bounds__(256) void adj_coef(const float* __restrict__ Y, int
 }
 
 // Bbar[tau_t][r] -= rbar[t][r]; rows repeated within the step are summed in
-// ascending t by the first occurrence (no two threads touch one element).
+// ascending t by their first occurrence (no two threads touch one element).
+// Every workgroup builds an LDS hash table of the step's rows (first
+// occurrence and count per row), then takes one (t, r) element per thread,
+// so all read-modify-writes are in flight at once; only a repeated row scans
+// for its later occurrences. grid = ceil(eta * R / 256); dynamic LDS
+// adj_bbar_lds(eta) bytes (table size H = the power of two >= 2 eta).
 constexpr int kAdjMaxEta = 4096;
-__global__ __launch_bounds__(1024) void adj_bbar(const int32_t* __restrict__ tau, int eta,
-                                                 const float* __restrict__ Rbar, int R, float* __restrict__ Bbar,
-                                                 const int* status) {
-  __shared__ int st[kAdjMaxEta];
-  __shared__ int nx[kAdjMaxEta];
-  __shared__ unsigned char first[kAdjMaxEta];
+__host__ __device__ inline int adj_hash_size(int eta) {
+  int h = 16;
+  while (h < 2 * eta) h <<= 1;
+  return h;
+}
+size_t adj_bbar_lds(int eta) { return (size_t)adj_hash_size(eta) * 12 + (size_t)eta * 4; }
+
+__global__ __launch_bounds__(256) void adj_bbar(const int32_t* __restrict__ tau, int eta,
+                                                const float* __restrict__ Rbar, int R, float* __restrict__ Bbar,
+                                                const int* status) {
+  extern __shared__ int hsm[];
   if (status[0]) return;
-  for (int t = threadIdx.x; t < eta; t += blockDim.x) {
-    st[t] = tau[t];
-    first[t] = 1;
+  const int H = adj_hash_size(eta);
+  int* hkey = hsm;
+  int* hmin = hsm + H;
+  int* hcnt = hsm + 2 * H;
+  int* st = hsm + 3 * H;
+  for (int i = threadIdx.x; i < H; i += blockDim.x) {
+    hkey[i] = -1;
+    hmin[i] = INT_MAX;
+    hcnt[i] = 0;
   }
+  for (int t = threadIdx.x; t < eta; t += blockDim.x) st[t] = tau[t];
   __syncthreads();
   for (int t = threadIdx.x; t < eta; t += blockDim.x) {
-    int nt = -1;
+    const int key = st[t];
+    int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
+    for (;;) {  // at most eta distinct keys in a table of H >= 2 eta slots: a free or matching slot exists
+      const int prev = atomicCAS(&hkey[h], -1, key);
+      if (prev == -1 || prev == key) break;
+      h = (h + 1) & (H - 1);
+    }
+    atomicMin(&hmin[h], t);
+    atomicAdd(&hcnt[h], 1);
+  }
+  __syncthreads();
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= (size_t)eta * R) return;
+  const int t = (int)(e / R), r = (int)(e % R);
+  const int key = st[t];
+  int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
+  while (hkey[h] != key) h = (h + 1) & (H - 1);
+  if (hmin[h] != t) return;
+  float sum = Rbar[(size_t)t * R + r];
+  if (hcnt[h] > 1)
     for (int u = t + 1; u < eta; ++u)
-      if (st[u] == st[t]) { nt = u; break; }
-    nx[t] = nt;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < eta; t += blockDim.x)
-    if (nx[t] >= 0) first[nx[t]] = 0;
-  __syncthreads();
-  for (size_t e = threadIdx.x; e < (size_t)eta * R; e += blockDim.x) {
-    const int t = (int)(e / R), r = (int)(e % R);
-    if (!first[t]) continue;
-    float sum = 0.f;
-    for (int u = t; u >= 0; u = nx[u]) sum += Rbar[(size_t)u * R + r];
-    Bbar[(int64_t)st[t] * R + r] -= sum;
-  }
+      if (st[u] == key) sum += Rbar[(size_t)u * R + r];
+  Bbar[(int64_t)key * R + r] -= sum;
 }
 
 // xbar = A_tau^T Rbar (MFMA as gemm_att_c_update); epilogue zbar += m_k . xbar and the
@@ -461,6 +485,9 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
   const int gr = (a.R + BN - 1) / BN;
   const int gn = (int)((a.n + BM - 1) / BM);
   const int nblk_att = gn * gr;
+  if (hipFuncSetAttribute((const void*)&adj_bbar, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)adj_bbar_lds(a.eta)) != hipSuccess)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(fill_zero_f32, dim3(1024), dim3(256), 0, stream, d.Bbar, (size_t)a.m * a.R);
   hipLaunchKernelGGL(adj_seed, dim3(kAdjSeedBlocks), dim3(256), 0, stream, d.zK, d.xbarK, total, a.lambda, d.zbar,
                      d.lam_part, a.status);
@@ -489,7 +516,8 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
                          a.Y, a.eta_pad, a.kspan, a.status);
       hipLaunchKernelGGL(adj_coef, dim3(kAdjCoefBlocks), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta,
                          d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
-      hipLaunchKernelGGL(adj_bbar, dim3(1), dim3(1024), 0, stream, tk, a.eta, a.C, a.R, d.Bbar, a.status);
+      hipLaunchKernelGGL(adj_bbar, dim3((unsigned)(((size_t)a.eta * a.R + 255) / 256)), dim3(256),
+                         adj_bbar_lds(a.eta), stream, tk, a.eta, a.C, a.R, d.Bbar, a.status);
       hipLaunchKernelGGL(gemm_att_adj, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
                          d.Zh + (size_t)j * total, d.zbar, a.lambda,
                          d.lam_part + kAdjSeedBlocks + (size_t)k * nblk_att, a.status);
