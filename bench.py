@@ -55,6 +55,17 @@ def spectral_norm_sq(A, iters=40):
     return lam
 
 
+def device_info(dev):
+    """Name, compute units and clocks of the GPU the run used (runs on different boxes vary)."""
+    import torch
+    p = torch.cuda.get_device_properties(dev)
+    out = {"name": p.name, "gcn_arch": getattr(p, "gcnArchName", None), "cus": p.multi_processor_count}
+    for k in ("clock_rate", "memory_clock_rate"):
+        if hasattr(p, k):
+            out[k + "_khz"] = getattr(p, k)
+    return out
+
+
 def step_bytes(eta, n):
     return eta * (n * 4 + 12)
 
@@ -214,6 +225,7 @@ def main():
                                f"eta={eta}, alpha=alpha*, {iters} iterations per step",
                    "m": M, "n": N, "eta": eta, "iters_per_step": iters},
         "us_per_iteration": round(launch_ms * 1e3 / iters, 3),
+        "device": device_info(dev),
     }
     traffic = traffic_from_profile(bytes_launch)
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -62,6 +62,60 @@ __device__ __forceinline__ void poll_flat(const u64* xP, int n_slots, int tid, i
   }
 }
 
+// Butterfly sums within aligned groups of `width` lanes (a power of two <= 64)
+// without the LDS crossbar: DPP quad permutes for offsets 1 and 2, the row
+// half-mirror and row mirror for 4 and 8 (each pairs a lane with one of the
+// other, already uniform, half-group), and the gfx950 permlane16/32 swaps for
+// 16 and 32 (the two swapped outputs are the lane's own and its partner's
+// value). Every lane of a group ends with the same, fixed-order sum.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ float swap16_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ float swap32_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ double join_d(int lo, int hi) {
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ double swap16_sum(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  return join_d(l[0], h[0]) + join_d(l[1], h[1]);
+}
+__device__ __forceinline__ double swap32_sum(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  return join_d(l[0], h[0]) + join_d(l[1], h[1]);
+}
+template <typename T>
+__device__ __forceinline__ T lane_sum(T v, int width) {
+  if (width > 1) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (width > 2) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (width > 4) v += dpp_move<0x141>(v);  // row_half_mirror
+  if (width > 8) v += dpp_move<0x140>(v);  // row_mirror
+  if (width > 16) v = swap16_sum(v);
+  if (width > 32) v = swap32_sum(v);
+  return v;
+}
+
 // c_t = (alpha_k/eta) (r_t - b_t) / ||a_t||^2 from the row's prefetched b and norm.
 template <typename T>
 __device__ __forceinline__ T coef_of(T s, T bt, T rn, T ak, int eta, int& zero_row) {
@@ -233,7 +287,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
             }
           }
         }
-        acc = group_sum(acc, lpr);
+        acc = lane_sum(acc, lpr);
         if (cl == 0) cs[t] = acc;
       }
     } else {
@@ -273,7 +327,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
         }
         T sum[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) sum[u] = group_sum(acc[u], lpr);
+        for (int u = 0; u < U; ++u) sum[u] = lane_sum(acc[u], lpr);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int t = tb + u * rstride + rs;
@@ -356,7 +410,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
         }
 #pragma unroll
         for (int u = 0; u < UR; ++u) {
-          const T sum = wave_sum(part[u]);
+          const T sum = lane_sum(part[u], 64);
           const int t = tb + u * NW * G;
           if (lane == 0 && t < eta) {
             const T c = coef_of(sum, bq[t], rq[t], ak, eta, zero_row);
@@ -495,8 +549,8 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
           r2s += rf * rf;
         }
       }
-      e2 = wave_sum(e2);
-      r2s = wave_sum(r2s);
+      e2 = lane_sum(e2, 64);
+      r2s = lane_sum(r2s, 64);
       if (lane == 0) { mon[2 * wave] = e2; mon[2 * wave + 1] = r2s; }
       __syncthreads();
       if (solo) {
@@ -521,8 +575,8 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
             se += wait_tagged<double>(&a.xM[(size_t)q * 4], mtag, lerr);
             sr += wait_tagged<double>(&a.xM[(size_t)q * 4 + 2], mtag, lerr);
           }
-          se = wave_sum(se);
-          sr = wave_sum(sr);
+          se = lane_sum(se, 64);
+          sr = lane_sum(sr, 64);
           if (lane == 0) {
             const double err = sr > 0.0 ? sqrt(se / sr) : sqrt(se);
             if (g == 0 && a.err_hist) a.err_hist[mtag - 1] = err;
