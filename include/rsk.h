@@ -153,12 +153,16 @@ int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
 
 /*
  * The same iteration with A in CSR form (eq. (rska) with sparse rows).
- * Runs as one persistent workgroup: a sparse step moves a few hundred KB
- * and is bound by latency, which a single CU minimises (no cross-CU exchange).
- * Columns hit by several sampled rows of a step are summed in int64 fixed
- * point with a per-step power-of-two quantum (2^-41 of the step's largest
- * contribution), so results are bitwise reproducible. eta <= 4096.
- * Workspace: n int64 accumulators (rsk_workspace_size_csr), zeroed by the call.
+ * A sparse step moves a few hundred KB and is bound by latency. p->kernel
+ * selects the kernel: 1 = one persistent workgroup (no cross-CU exchange),
+ * 2 = the multi-workgroup kernel (one lane per nonzero, p->grid workgroups or
+ * eta/8 up to the CU count, three grid barriers per step), 0 = 2 when
+ * eta >= 64, else 1. Columns hit by several sampled rows of a step are summed
+ * in int64 fixed point with a per-step power-of-two quantum (2^-41 of the
+ * step's largest contribution), so results are bitwise reproducible for a
+ * given kernel. eta <= 4096.
+ * Workspace: n + 1 int64 accumulators plus the grid kernel's barrier and
+ * monitor words (rsk_workspace_size_csr), zeroed by the call.
  * A column index outside [0, n) in a sampled row is RSK_ERR_INDEX_RANGE.
  */
 int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, void *x_star, void *x,

@@ -204,13 +204,47 @@ int32_t check_csr(const rsk_csr* A) {
   return RSK_OK;
 }
 
-// n column accumulators plus one spare slot for empty lanes
-size_t csr_ws_bytes(const rsk_csr* A) { return align256((size_t)(A->n + 1) * sizeof(long long)); }
+// CSR plan: one workgroup (small steps) or the multi-workgroup kernel.
+// Workspace: n + 1 int64 column accumulators (the last a spare slot), then for
+// the grid kernel the barrier counter, the step-parity exponent words and the
+// monitor words.
+struct CsrPlan {
+  int kernel, G;
+  size_t offBar, offEmax, offM, bytes;
+};
+
+template <typename T>
+int32_t plan_csr(const rsk_csr* A, const rsk_params* p, CsrPlan* pl) {
+  const int cus = device_cus() > 0 ? device_cus() : 1;
+  const int rpp = rsk::kCsrGridRowsPerPass;
+  const bool grid = p->kernel == 2 || (p->kernel == 0 && p->eta >= 64);
+  pl->kernel = grid ? 2 : 1;
+  pl->G = 1;
+  size_t o = align256((size_t)(A->n + 1) * sizeof(long long));
+  pl->offBar = pl->offEmax = pl->offM = o;
+  if (grid) {
+    int G = p->grid > 0 ? p->grid : (p->eta + rpp - 1) / rpp;
+    if (p->grid <= 0 && G > cus) G = cus;
+    const int maxres = rsk::csr_grid_max_resident<T>();
+    if (G < 1 || (maxres > 0 && G > maxres)) return RSK_ERR_UNSUPPORTED;
+    if ((p->eta + rpp * G - 1) / (rpp * G) > rsk::kCsrGridMaxPasses) return RSK_ERR_UNSUPPORTED;
+    pl->G = G;
+    pl->offBar = o; o += 64;
+    pl->offEmax = o; o += 64;
+    pl->offM = o; o = align256(o + (size_t)G * 4 * sizeof(u64));
+  }
+  pl->bytes = o;
+  return RSK_OK;
+}
 
 template <typename T>
 int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* x_star, void* x, void* ws,
                     size_t ws_bytes, hipStream_t stream) {
-  if (!ws || ws_bytes < csr_ws_bytes(A) || ((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  CsrPlan pl;
+  int32_t st = plan_csr<T>(A, p, &pl);
+  if (st) return st;
+  if (!ws || ws_bytes < pl.bytes || ((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  unsigned char* w = (unsigned char*)ws;
   rsk::CsrArgs<T> a;
   a.row_ptr = A->row_ptr; a.col = A->col; a.val = (const T*)A->val; a.m = A->m; a.n = A->n;
   a.b = (const T*)b; a.r2 = (const T*)p->rownorm2;
@@ -222,10 +256,14 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
   a.xref = (const T*)p->x_ref; a.check_every = p->x_ref ? p->check_every : 0; a.tol = p->tol;
   a.err_hist = p->err_hist; a.status = p->status_dev;
   a.acc = (long long*)ws;
-  if (rsk::launch_zero_words((u64*)ws, (size_t)A->n + 1, stream) != hipSuccess) return RSK_ERR_HIP;
+  a.G = pl.G;
+  a.bar = (u64*)(w + pl.offBar);
+  a.emax = (int*)(w + pl.offEmax);
+  a.xM = (u64*)(w + pl.offM);
+  if (rsk::launch_zero_words((u64*)ws, pl.bytes / sizeof(u64), stream) != hipSuccess) return RSK_ERR_HIP;
   if (rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
-  if (rsk::launch_csr<T>(a, stream) != hipSuccess) return RSK_ERR_HIP;
-  return RSK_OK;
+  const hipError_t e = pl.kernel == 2 ? rsk::launch_csr_grid<T>(a, stream) : rsk::launch_csr<T>(a, stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
 }
 
 struct MultiPlan {
@@ -506,7 +544,10 @@ int32_t rsk_workspace_size_csr(const rsk_csr* A, const rsk_params* p, size_t* by
   st = check_params(p, A->m);
   if (st) return st;
   if (p->eta > rsk::kCsrMaxEta) return RSK_ERR_UNSUPPORTED;
-  *bytes = csr_ws_bytes(A);
+  CsrPlan pl;
+  st = A->dtype == RSK_F64 ? plan_csr<double>(A, p, &pl) : plan_csr<float>(A, p, &pl);
+  if (st) return st;
+  *bytes = pl.bytes;
   return RSK_OK;
 }
 

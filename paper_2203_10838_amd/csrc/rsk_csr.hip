@@ -239,4 +239,272 @@ hipError_t launch_csr(CsrArgs<T>& a, hipStream_t stream) {
 template hipError_t launch_csr<float>(CsrArgs<float>&, hipStream_t);
 template hipError_t launch_csr<double>(CsrArgs<double>&, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Multi-workgroup CSR kernel.
+//
+// One sampled row per 32 lanes, one nonzero per lane (longer rows loop), so a
+// step's 16K nonzeros spread over G workgroups instead of one CU's request
+// queue. x*, x and the column accumulators are shared by all workgroups, so
+// every access to them is an agent-scope atomic (coherent across the XCDs
+// without cache maintenance). Per step, three grid barriers on one monotonic
+// counter (each workgroup first waits for all of its own memory operations):
+//   A. dots r_t (x gathered), c_t, contributions c_t a_{t,j}; the largest
+//      exponent goes to a step-parity word by atomicMax;      barrier
+//   B. int64 fixed-point accumulation with the step's quantum 2^(e-40)
+//      (integer adds commute: the totals do not depend on atomic order);  barrier
+//   C. every touched column applied once, by the lane that swaps its nonzero
+//      total out of the accumulator: x*_j -= total q, x_j = S_lambda(x*_j); barrier
+// The result is bitwise reproducible (the dots use a fixed lane order).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kGridThreads = 256;
+constexpr int kEBias = 4096;  // biased exponent stored in emax (0 = no contribution)
+
+template <typename T>
+__device__ __forceinline__ T ld_ag(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_ag(T* p, T v) {
+  // an exchange returns, so the write is complete before the workgroup arrives at the next barrier
+  (void)__hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) { return __int_as_float(dpp32<CTRL>(__float_as_int(v))); }
+template <int CTRL>
+__device__ __forceinline__ double dppf(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp32<CTRL>((int)b), hi = dpp32<CTRL>((int)(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ float swap16f(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ double swap16f(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  return __longlong_as_double((long long)(unsigned)l[0] | ((long long)h[0] << 32)) +
+         __longlong_as_double((long long)(unsigned)l[1] | ((long long)h[1] << 32));
+}
+// Sum over an aligned group of 32 lanes (DPP within 16 lanes, then the 16-lane swap).
+template <typename T>
+__device__ __forceinline__ T sum32(T v) {
+  v += dppf<0xB1>(v);
+  v += dppf<0x4E>(v);
+  v += dppf<0x141>(v);
+  v += dppf<0x140>(v);
+  return swap16f(v);
+}
+
+// Arrive at the grid barrier and wait for the counter to reach `target`.
+// Returns false if the bounded wait expired.
+__device__ __forceinline__ bool grid_sync(u64* bar, u64 target) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's memory operations are complete
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    int good = 1;
+    while (xload(bar) < target) {
+      if (++spins > kSpinLimit) { good = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
+  constexpr int RPP = kCsrGridRowsPerPass;
+  __shared__ T cl[kCsrGridMaxPasses * RPP];
+  __shared__ int il[kCsrGridMaxPasses * RPP];
+  __shared__ double wmax[kGridThreads / 64];
+  __shared__ double mon[2 * (kGridThreads / 64) + 2];
+  const int g = blockIdx.x, G = a.G, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int hw = tid >> 5, p = tid & 31;
+  const int eta = a.eta;
+  const int passes = (eta + RPP * G - 1) / (RPP * G);
+  u64 nbar = 0;
+  int stop_code = 0;
+
+  // x*_0, x_0 over this workgroup's column block
+  const int64_t j0 = (int64_t)g * a.n / G, j1 = (int64_t)(g + 1) * a.n / G;
+  for (int64_t j = j0 + tid; j < j1; j += kGridThreads) {
+    const T z = a.warm ? ld_ag(a.x_star + j) : T(0);
+    if (!a.warm) st_ag(a.x_star + j, z);
+    st_ag(a.x + j, shrink(z, a.lambda));
+  }
+  if (!grid_sync(a.bar, (u64)G * ++nbar)) stop_code = ST_ABORTED;
+
+  int64_t k_done = 0;
+  for (int64_t k = 0; k < a.K && !stop_code; ++k) {
+    const T ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
+    const int32_t* tk = a.idx + k * (int64_t)eta;
+    int lerr = 0;
+    double vmax = 0.0;
+
+    // A. residuals, coefficients, largest contribution
+    for (int ps = 0; ps < passes; ++ps) {
+      const int t = ps * RPP * G + g * RPP + hw;
+      if (t < eta) {
+        int i = tk[t];
+        if (i < 0 || (int64_t)i >= a.m) { lerr = ST_INDEX; i = -1; }
+        T dot = T(0);
+        int64_t r0 = 0, r1 = 0;
+        if (i >= 0) { r0 = a.row_ptr[i]; r1 = a.row_ptr[i + 1]; }
+        for (int64_t q = r0 + p; q < r1; q += 32) {
+          const int j = a.col[q];
+          const T v = a.val[q];
+          if (j < 0 || (int64_t)j >= a.n) { lerr = ST_INDEX; continue; }
+          dot += v * ld_ag(a.x + j);
+        }
+        dot = sum32(dot);
+        T c = T(0);
+        if (i >= 0) {
+          const T rn = a.r2[i];
+          if (rn == T(0)) { lerr = ST_ZERO_ROW; c = T(NAN); }
+          else c = (ak / T(eta)) * (dot - a.b[i]) / rn;
+          if (!isfinite(c) && !lerr) lerr = ST_NONFINITE;
+        }
+        for (int64_t q = r0 + p; q < r1; q += 32) vmax = fmax(vmax, fabs((double)(c * a.val[q])));
+        if (p == 0) { cl[ps * RPP + hw] = c; il[ps * RPP + hw] = i; }
+      }
+    }
+    if (lerr) set_status(a.status, lerr);
+    for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+    if (lane == 0) wmax[wave] = vmax;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int w = 0; w < kGridThreads / 64; ++w) m = fmax(m, wmax[w]);
+      if (m > 0.0 && isfinite(m))
+        __hip_atomic_fetch_max(a.emax + (k & 1), ilogb(m) + kEBias, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!grid_sync(a.bar, (u64)G * ++nbar)) { stop_code = ST_ABORTED; break; }
+    if (ld_ag(a.status)) { stop_code = -1; break; }  // the fault was recorded by the workgroup that saw it
+    const int eb = ld_ag(a.emax + (k & 1));
+    if (g == 0 && tid == 0) st_ag(a.emax + ((k + 1) & 1), 0);  // read by everyone two barriers ago
+
+    if (eb > 0) {
+      const int e = eb - kEBias;
+      // B. integer accumulation
+      for (int ps = 0; ps < passes; ++ps) {
+        const int t = ps * RPP * G + g * RPP + hw;
+        if (t < eta) {
+          const int i = il[ps * RPP + hw];
+          const T c = cl[ps * RPP + hw];
+          const int64_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+          for (int64_t q = r0 + p; q < r1; q += 32) {
+            const long long v = (long long)llrint(ldexp((double)(c * a.val[q]), 40 - e));
+            __hip_atomic_fetch_add(a.acc + a.col[q], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+      if (!grid_sync(a.bar, (u64)G * ++nbar)) { stop_code = ST_ABORTED; break; }
+      // C. apply each touched column once
+      for (int ps = 0; ps < passes; ++ps) {
+        const int t = ps * RPP * G + g * RPP + hw;
+        if (t < eta) {
+          const int i = il[ps * RPP + hw];
+          const int64_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+          for (int64_t q = r0 + p; q < r1; q += 32) {
+            const int j = a.col[q];
+            const long long tot = __hip_atomic_exchange(a.acc + j, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tot != 0) {
+              const T z = (T)((double)ld_ag(a.x_star + j) - ldexp((double)tot, e - 40));
+              st_ag(a.x_star + j, z);
+              st_ag(a.x + j, shrink(z, a.lambda));
+            }
+          }
+          if (a.y && p == 0) atomicAdd(&a.y[i], -cl[ps * RPP + hw]);
+        }
+      }
+    } else {
+      ++nbar;  // keep the barrier count of the skipped accumulation phase
+      if (!grid_sync(a.bar, (u64)G * nbar)) { stop_code = ST_ABORTED; break; }
+    }
+    if (!grid_sync(a.bar, (u64)G * ++nbar)) { stop_code = ST_ABORTED; break; }
+    k_done = k + 1;
+
+    if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
+      const unsigned mtag = (unsigned)((k + 1) / a.check_every);
+      double e2 = 0.0, r2s = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += kGridThreads) {
+        const double rf = (double)a.xref[j];
+        const double d = (double)ld_ag(a.x + j) - rf;
+        e2 += d * d;
+        r2s += rf * rf;
+      }
+      e2 = wave_sum(e2);
+      r2s = wave_sum(r2s);
+      if (lane == 0) { mon[2 * wave] = e2; mon[2 * wave + 1] = r2s; }
+      __syncthreads();
+      if (tid == 0) {
+        double se = 0.0, sr = 0.0;
+        for (int w = 0; w < kGridThreads / 64; ++w) { se += mon[2 * w]; sr += mon[2 * w + 1]; }
+        put_tagged(&a.xM[(size_t)g * 4], se, mtag);
+        put_tagged(&a.xM[(size_t)g * 4 + 2], sr, mtag);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        double se = 0.0, sr = 0.0;
+        for (int q = lane; q < G; q += 64) {
+          se += wait_tagged<double>(&a.xM[(size_t)q * 4], mtag, lerr);
+          sr += wait_tagged<double>(&a.xM[(size_t)q * 4 + 2], mtag, lerr);
+        }
+        se = wave_sum(se);
+        sr = wave_sum(sr);
+        if (lane == 0) {
+          const double err = sr > 0.0 ? sqrt(se / sr) : sqrt(se);
+          if (g == 0 && a.err_hist) a.err_hist[mtag - 1] = err;
+          mon[2 * (kGridThreads / 64)] = err;
+        }
+      }
+      if (lerr) set_status(a.status, lerr);
+      if (__syncthreads_or(lerr)) { stop_code = ST_ABORTED; break; }
+      if (a.tol > 0.0 && mon[2 * (kGridThreads / 64)] <= a.tol) break;
+    }
+  }
+  if (stop_code > 0 && tid == 0) set_status(a.status, stop_code);
+  if (g == 0 && tid == 0) a.status[1] = (int)k_done;
+}
+
+template <typename T>
+int csr_grid_max_resident() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&rska_csr_grid<T>, kGridThreads, 0) !=
+      hipSuccess)
+    return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+template <typename T>
+hipError_t launch_csr_grid(CsrArgs<T>& a, hipStream_t stream) {
+  if (a.G < 1 || a.G > csr_grid_max_resident<T>()) return hipErrorCooperativeLaunchTooLarge;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)&rska_csr_grid<T>, dim3(a.G), dim3(kGridThreads), args, 0, stream);
+}
+
+template int csr_grid_max_resident<float>();
+template int csr_grid_max_resident<double>();
+template hipError_t launch_csr_grid<float>(CsrArgs<float>&, hipStream_t);
+template hipError_t launch_csr_grid<double>(CsrArgs<double>&, hipStream_t);
+
 }  // namespace rsk

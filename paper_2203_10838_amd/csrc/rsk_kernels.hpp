@@ -105,10 +105,22 @@ struct CsrArgs {
   double* err_hist;
   int* status;
   long long* acc;         // n + 1 int64 accumulators (the last a spare), zero on entry and on exit
+  // grid kernel only
+  int G;                  // workgroups
+  u64* bar;               // grid barrier counter (zero on entry)
+  int* emax;              // [2] biased max exponent of a step's contributions (zero on entry)
+  u64* xM;                // monitor words [G][4]
 };
 
 template <typename T>
 hipError_t launch_csr(CsrArgs<T>& a, hipStream_t stream);
+// Multi-workgroup CSR kernel (one lane per nonzero, three grid barriers per step).
+constexpr int kCsrGridRowsPerPass = 8;   // rows per workgroup and pass (256 threads, 32 lanes a row)
+constexpr int kCsrGridMaxPasses = 8;
+template <typename T>
+int csr_grid_max_resident();
+template <typename T>
+hipError_t launch_csr_grid(CsrArgs<T>& a, hipStream_t stream);
 
 // Multi-RHS (shared A and stream), float32 MFMA GEMMs per step.
 struct MultiRhsArgs {

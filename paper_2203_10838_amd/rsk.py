@@ -187,8 +187,9 @@ def solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: in
               alpha_k: Optional[torch.Tensor] = None, rownorm2_t: Optional[torch.Tensor] = None,
               x_star: Optional[torch.Tensor] = None, warm_start: bool = False, x_ref: Optional[torch.Tensor] = None,
               check_every: int = 0, tol: float = 0.0, y_out: Optional[torch.Tensor] = None,
-              workspace: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
-    """K steps of RSKA on a CSR system (one persistent workgroup)."""
+              grid: int = 0, kernel: int = 0, workspace: Optional[torch.Tensor] = None,
+              check: bool = True) -> SolveResult:
+    """K steps of RSKA on a CSR system (kernel 1: one workgroup, 2: multi-workgroup, 0: by eta)."""
     d = csr_desc(row_ptr, col, val, n)
     dt = val.dtype
     dev = val.device
@@ -206,7 +207,8 @@ def solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: in
     err_hist = torch.full((max(nh, 1),), float("nan"), dtype=torch.float64, device=dev) if nh else None
     params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
                          status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, warm_start=warm_start,
-                         x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist, y_out=y_out, dtype=dt)
+                         x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist, y_out=y_out, grid=grid,
+                         kernel=kernel, dtype=dt)
     if y_out is not None:
         _dev(y_out, "y_out", dt, d.m)
     nbytes = ctypes.c_size_t(0)
