@@ -212,7 +212,7 @@ int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item 
  *   B       device, m x R row-major.
  *   X_star  device, n x R row-major, in/out (read when warm_start = 1).
  *   X       device, n x R row-major, out.
- * Requires R % 4 == 0, n % 4 == 0, ld % 4 == 0, A 16-byte aligned; the
+ * Requires R % 4 == 0, n % 4 == 0, ld % 4 == 0, eta <= 4096, A 16-byte aligned; the
  * monitor and y_out are not supported here (RSK_ERR_UNSUPPORTED).
  * Device faults and status_dev follow the single-RHS conventions; steps are
  * queued as kernels on `stream` (four per step).

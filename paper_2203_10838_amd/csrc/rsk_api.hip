@@ -277,6 +277,7 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   if (R <= 0) return RSK_ERR_INVALID_ARG;
   if ((R % 4) || (A->n % 4) || (A->ld % 4) || (((uintptr_t)A->val) % 16)) return RSK_ERR_UNSUPPORTED;
   if (p->x_ref || p->y_out || p->check_every) return RSK_ERR_UNSUPPORTED;
+  if (p->eta > 4096) return RSK_ERR_UNSUPPORTED;  // the sampled rows of a step are staged in LDS
   pl->eta_pad = (p->eta + 63) / 64 * 64;
   const int tiles = (pl->eta_pad / 64) * ((R + 63) / 64);
   const int cus = device_cus() > 0 ? device_cus() : 256;

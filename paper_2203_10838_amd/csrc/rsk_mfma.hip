@@ -23,7 +23,7 @@ namespace rsk {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NTH = 256;
+constexpr int BM = 64, BN = 64, NTH = 256;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -31,12 +31,22 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Inner product of the workgroup's LDS tiles: As[k][m] (BK x BM), Bs[k][n] (BK x BN).
-__device__ __forceinline__ void mma_tile(const float (*As)[BM], const float (*Bs)[BN], int wm, int wn, int lane,
-                                         f4 (&acc)[2][2]) {
+// Pipelined main loop. K advances SK = 64 per stage through LDS tiles stored
+// k-major (rows padded to BM + 4 floats); every thread moves four float4 of
+// each operand per stage, and the next stage's loads are issued before the
+// current stage's MFMAs, so one memory latency overlaps one stage of compute.
+constexpr int SK = 64, LDP = BM + 4;
+constexpr int kMaxTauLds = 4096;  // sampled rows staged in LDS by the A^T GEMMs
+
+struct Stage {
+  float4 a[4], b[4];
+};
+
+__device__ __forceinline__ void mma_stage(const float (*As)[LDP], const float (*Bs)[LDP], int wm, int wn, int lane,
+                                          f4 (&acc)[2][2]) {
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int k0 = 0; k0 < BK; k0 += 4) {
+  for (int k0 = 0; k0 < SK; k0 += 4) {
     float a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) a[i] = As[k0 + lk][wm * 32 + i * 16 + li];
@@ -49,6 +59,46 @@ __device__ __forceinline__ void mma_tile(const float (*As)[BM], const float (*Bs
   }
 }
 
+// acc = A_tau[:, k-range]^T-free product for the A^T GEMMs: acc(m = column j0 + m, n = r0 + n) =
+// sum_t A[tau_t, j0 + m] C[t, r0 + n] over t < eta, tau staged in LDS.
+__device__ __forceinline__ void att_mainloop(const float* __restrict__ A, int64_t ld, int64_t n,
+                                             const int* taus, int eta, const float* __restrict__ C, int R,
+                                             int64_t j0, int r0, float (*As)[LDP], float (*Bs)[LDP],
+                                             f4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = tid >> 4, lc = (tid & 15) * 4;
+  const bool colok = j0 + lc < n, rok = r0 + lc < R;
+  auto load = [&](int tb, Stage& st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int t = tb + lr + 16 * i;
+      const bool ok = t < eta;
+      st.a[i] = (ok && colok) ? *reinterpret_cast<const float4*>(A + (int64_t)taus[ok ? t : 0] * ld + j0 + lc)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      st.b[i] = (ok && rok) ? *reinterpret_cast<const float4*>(C + (size_t)t * R + r0 + lc)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  Stage st;
+  load(0, st);
+  for (int tb = 0; tb < eta; tb += SK) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      *reinterpret_cast<float4*>(&As[lr + 16 * i][lc]) = st.a[i];
+      *reinterpret_cast<float4*>(&Bs[lr + 16 * i][lc]) = st.b[i];
+    }
+    __syncthreads();
+    if (tb + SK < eta) load(tb + SK, st);
+    mma_stage(As, Bs, wm, wn, lane, acc);
+  }
+}
+
+__device__ __forceinline__ void stage_tau(const int32_t* __restrict__ tau, int eta, int* taus) {
+  for (int t = threadIdx.x; t < eta; t += blockDim.x) taus[t] = tau[t];
+}
+
 }  // namespace
 
 // Y[s][t][r] = sum_{j in split s} A[tau_t, j] X[j, r]. grid = (ceil(eta/64), R/64, S).
@@ -57,8 +107,8 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
                                                   int R, float* __restrict__ Y, int eta_pad, int64_t kspan,
                                                   const int* status) {
   if (status[0]) return;
-  __shared__ float As[BK][BM];
-  __shared__ float Bs[BK][BN];
+  __shared__ __align__(16) float As[SK][LDP];
+  __shared__ __align__(16) float Bs[SK][LDP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int t0 = blockIdx.x * BM, r0 = blockIdx.y * BN, s = blockIdx.z;
@@ -66,12 +116,27 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
   int64_t j_end = j_begin + kspan;
   if (j_end > n) j_end = n;
 
-  // A tile loader: thread -> row t0 + tid/4, 4 consecutive columns
-  const int at = tid >> 2, ac = (tid & 3) * 4;
-  const int trow = t0 + at;
-  const float* arow = A + (int64_t)(trow < eta ? tau[trow] : 0) * ld;
-  // X tile loader: thread -> row k = tid/16, columns r0 + 4*(tid%16)
-  const int xk = tid >> 4, xc = (tid & 15) * 4;
+  // thread -> rows t0 + lr + 16 i of A_tau (4 columns at lc), rows jb + lr + 16 i of X (4 columns at lc)
+  const int lr = tid >> 4, lc = (tid & 15) * 4;
+  const float* arow[4];
+  bool aok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int t = t0 + lr + 16 * i;
+    aok[i] = t < eta;
+    arow[i] = A + (int64_t)(aok[i] ? tau[t] : 0) * ld;
+  }
+  const bool rok = r0 + lc < R;
+  auto load = [&](int64_t jb, Stage& st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t c = jb + lc;
+      st.a[i] = (aok[i] && c < j_end) ? *reinterpret_cast<const float4*>(arow[i] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int64_t jj = jb + lr + 16 * i;
+      st.b[i] = (jj < j_end && rok) ? *reinterpret_cast<const float4*>(X + jj * R + r0 + lc)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
 
   f4 acc[2][2];
 #pragma unroll
@@ -79,19 +144,22 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t j0 = j_begin; j0 < j_end; j0 += BK) {
-    float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (trow < eta && j0 + ac < j_end) av = *reinterpret_cast<const float4*>(arow + j0 + ac);
-    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (j0 + xk < j_end && r0 + xc < R) xv = *reinterpret_cast<const float4*>(X + (j0 + xk) * R + r0 + xc);
+  Stage st;
+  load(j_begin, st);
+  for (int64_t jb = j_begin; jb < j_end; jb += SK) {
     __syncthreads();
-    As[ac + 0][at] = av.x;
-    As[ac + 1][at] = av.y;
-    As[ac + 2][at] = av.z;
-    As[ac + 3][at] = av.w;
-    *reinterpret_cast<float4*>(&Bs[xk][xc]) = xv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = lr + 16 * i;
+      As[lc + 0][m] = st.a[i].x;
+      As[lc + 1][m] = st.a[i].y;
+      As[lc + 2][m] = st.a[i].z;
+      As[lc + 3][m] = st.a[i].w;
+      *reinterpret_cast<float4*>(&Bs[m][lc]) = st.b[i];
+    }
     __syncthreads();
-    mma_tile(As, Bs, wm, wn, lane, acc);
+    if (jb + SK < j_end) load(jb + SK, st);
+    mma_stage(As, Bs, wm, wn, lane, acc);
   }
   // D layout: column lane%16, rows 4*(lane/16) + v
   float* Ys = Y + (size_t)s * eta_pad * R;
@@ -158,32 +226,21 @@ __global__ __launch_bounds__(NTH) void gemm_att_c_update(const float* __restrict
                                                          float* Zout, float* __restrict__ X, float lambda,
                                                          const int* status) {
   if (status[0]) return;
-  __shared__ float As[BK][BM];
-  __shared__ float Bs[BK][BN];
+  __shared__ __align__(16) float As[SK][LDP];
+  __shared__ __align__(16) float Bs[SK][LDP];
+  __shared__ int taus[kMaxTauLds];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t j0 = (int64_t)blockIdx.x * BM;
   const int r0 = blockIdx.y * BN;
-  // A^T tile loader: thread -> sampled row t0 + tid/16, columns j0 + 4*(tid%16)
-  const int lt = tid >> 4, lc = (tid & 15) * 4;
+  stage_tau(tau, eta, taus);
+  __syncthreads();
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-  for (int t0 = 0; t0 < eta; t0 += BK) {
-    const int t = t0 + lt;
-    float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < eta && j0 + lc < n) av = *reinterpret_cast<const float4*>(A + (int64_t)tau[t] * ld + j0 + lc);
-    float4 cv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < eta && r0 + lc < R) cv = *reinterpret_cast<const float4*>(C + (size_t)t * R + r0 + lc);
-    __syncthreads();
-    *reinterpret_cast<float4*>(&As[lt][lc]) = av;
-    *reinterpret_cast<float4*>(&Bs[lt][lc]) = cv;
-    __syncthreads();
-    mma_tile(As, Bs, wm, wn, lane, acc);
-  }
+  att_mainloop(A, ld, n, taus, eta, C, R, j0, r0, As, Bs, acc);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -387,8 +444,9 @@ __global__ __launch_bounds__(NTH) void gemm_att_adj(const float* __restrict__ A,
                                                     const float* __restrict__ Rbar, int R, const float* __restrict__ Zk,
                                                     float* __restrict__ zbar, float lambda,
                                                     double* __restrict__ lam_part, const int* status) {
-  __shared__ float As[BK][BM];
-  __shared__ float Bs[BK][BN];
+  __shared__ __align__(16) float As[SK][LDP];
+  __shared__ __align__(16) float Bs[SK][LDP];
+  __shared__ int taus[kMaxTauLds];
   __shared__ double red[4];
   const int blk = blockIdx.y * gridDim.x + blockIdx.x;
   if (status[0]) {
@@ -399,24 +457,14 @@ __global__ __launch_bounds__(NTH) void gemm_att_adj(const float* __restrict__ A,
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t j0 = (int64_t)blockIdx.x * BM;
   const int r0 = blockIdx.y * BN;
-  const int lt = tid >> 4, lc = (tid & 15) * 4;
+  stage_tau(tau, eta, taus);
+  __syncthreads();
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int t0 = 0; t0 < eta; t0 += BK) {
-    const int t = t0 + lt;
-    float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < eta && j0 + lc < n) av = *reinterpret_cast<const float4*>(A + (int64_t)tau[t] * ld + j0 + lc);
-    float4 cv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < eta && r0 + lc < R) cv = *reinterpret_cast<const float4*>(Rbar + (size_t)t * R + r0 + lc);
-    __syncthreads();
-    *reinterpret_cast<float4*>(&As[lt][lc]) = av;
-    *reinterpret_cast<float4*>(&Bs[lt][lc]) = cv;
-    __syncthreads();
-    mma_tile(As, Bs, wm, wn, lane, acc);
-  }
+  att_mainloop(A, ld, n, taus, eta, Rbar, R, j0, r0, As, Bs, acc);
   double lp = 0.0;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
