@@ -255,6 +255,7 @@ def main():
         out["time_to_plateau"] = plateau_runs(solve, inputs, weights, xhat, dev, stream)
 
     if not args.no_sweep:
+        out["sampler"] = sampler_run(A, dev, stream)
         out["csr"] = csr_run(dev, stream)
         out["batched"] = batched_run(dev, stream)
         torch.cuda.empty_cache()
@@ -469,6 +470,30 @@ def adjoint_run(dev, stream):
                           "alpha": float(adj.alpha_bar.norm())}}
     log(f"[bench] adjoint: {out}")
     return out
+
+
+def sampler_run(A, dev, stream, K=8000, eta=1024):
+    """Device row sampler on the large dense matrix: the FP64 cdf of the row norms (one pass over A)
+    and a stream of K x eta indices from Philox4x32-10 and the inverse CDF (the stream the
+    eta = 1024 plateau run needs), against drawing the same number of indices on the host."""
+    import torch
+    from paper_2203_10838_amd import inputs, rsk
+    cdf = rsk.sampling_cdf(A)
+    out = torch.empty(K * eta, dtype=torch.int32, device=dev)
+    rsk.sample_stream(cdf, seed=SEED + 1, K=K, eta=eta, out=out)
+    t_cdf = _median_ms(lambda: rsk.sampling_cdf(A), stream)
+    t_s = _median_ms(lambda: rsk.sample_stream(cdf, seed=SEED + 1, K=K, eta=eta, out=out), stream)
+    w = cdf.cpu().numpy()
+    w = np.diff(np.concatenate([[0.0], w]))
+    t0 = time.perf_counter()
+    inputs.index_stream(w, K, eta, SEED + 1)
+    t_host = (time.perf_counter() - t0) * 1e3
+    out_d = {"workload": f"cdf of the {A.shape[0]}x{A.shape[1]} float32 matrix; {K}x{eta} indices",
+             "cdf_ms": round(t_cdf, 3), "cdf_GBps": round(A.numel() * 4 / (t_cdf * 1e-3) / 1e9, 1),
+             "stream_ms": round(t_s, 3), "Gsamples_per_s": round(K * eta / (t_s * 1e-3) / 1e9, 2),
+             "host_numpy_stream_ms": round(t_host, 1)}
+    log(f"[bench] sampler: {out_d}")
+    return out_d
 
 
 def csr_run(dev, stream, K=20000):

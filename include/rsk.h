@@ -122,6 +122,30 @@ typedef struct {
   int32_t *status_dev;         /* int32[2]: status, steps completed */
 } rsk_batch_item;
 
+/*
+ * Row sampler (the index stream of Sec. 1.1 generated on the device).
+ *
+ * rsk_sampling_cdf_dense: cdf_i = sum_{j <= i} ||a_j||^2 in double (device,
+ * m entries), row norms accumulated in double, running sums by a three-pass
+ * scan (chunk sums, a fixed-order scan of the chunk sums, chunk-local scans):
+ * equal to a sequential running sum up to rounding order, the same bits on
+ * every run. Workspace: rsk_workspace_size_sampling_cdf(m).
+ *
+ * rsk_sample_stream: out[(k - k0) * eta + t] for k0 <= k < k0 + K, t < eta
+ * (device int32, step-major, the layout every solve takes as index_stream):
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) of the counter
+ * (t, k mod 2^32, k div 2^32, 0) under the key (seed mod 2^32, seed div 2^32)
+ * gives words w0, w1; u = ((w0 >> 5) 2^26 + (w1 >> 6)) / 2^53 in [0, 1); the
+ * index is the first i with cdf[i] > u * cdf[m-1] (at most m-1), i.e. rows
+ * are drawn with replacement with P(i) = ||a_i||^2 / ||A||_F^2. The result is
+ * a function of (cdf, seed, k, t) only. cdf must be non-decreasing with a
+ * positive finite last entry (otherwise every index is m-1). m <= 2^31 - 1.
+ */
+int32_t rsk_workspace_size_sampling_cdf(int64_t m, size_t *bytes);
+int32_t rsk_sampling_cdf_dense(const rsk_dense *A, double *cdf, void *workspace, size_t ws_bytes, void *stream);
+int32_t rsk_sample_stream(const double *cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int32_t eta,
+                          int32_t *out, void *stream);
+
 /* Version of this ABI (RSK_ABI_VERSION). */
 int32_t rsk_abi_version(void);
 

@@ -16,6 +16,9 @@ What is here (each function cites the passage it follows):
   one stream per system).
 * ``rska_dense_adjoint`` -- reverse mode of K unrolled steps, every iterate
   stored (no checkpointing).
+* ``philox4x32_10``, ``sampling_cdf``, ``sample_stream`` -- the row sampler
+  (p_i proportional to ||a_i||^2, Sec. 1.1) driven by the counter-based
+  generator Philox4x32-10 of Salmon et al. (SC'11) and an inverse-CDF search;
 * numpy helpers for the closed forms of Sec. 2 and Sec. 4: ``soft_threshold``
   (Sec. 1.1), ``f_value`` / ``f_conjugate`` (Example exmp:f),
   ``bregman_distance`` (Example exmp:D), ``optimal_alpha`` and
@@ -78,8 +81,13 @@ def _load():
                                             vp, vp, vp, i64, vp, vp, vp]
             lib.oracle_rska_dense_adjoint.argtypes = [i64, i64, i64, vp, vp, dbl, i32, vp, i64, vp, i64,
                                                       vp, vp, vp, vp]
+            lib.oracle_philox4x32_10.argtypes = [vp, vp, vp]
+            lib.oracle_philox4x32_10.restype = None
+            lib.oracle_sampling_cdf.argtypes = [i64, vp, vp]
+            lib.oracle_sample_stream.argtypes = [i64, vp, ctypes.c_uint64, i64, i64, i32, vp]
             for f in (lib.oracle_rownorm2_dense, lib.oracle_rownorm2_csr, lib.oracle_rska_dense,
-                      lib.oracle_rska_csr, lib.oracle_rska_dense_adjoint):
+                      lib.oracle_rska_csr, lib.oracle_rska_dense_adjoint, lib.oracle_sampling_cdf,
+                      lib.oracle_sample_stream):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -279,3 +287,37 @@ def rska_dense_adjoint(A, b, lam, eta, alpha_k, K, idx, xbar_K, *, off=0):
     if st:
         raise OracleError(st, "rska_dense_adjoint")
     return bbar, float(lbar[0]), abar[:K]
+
+
+# ---------------------------------------------------------------------------
+# Row sampler (counter-based generator + inverse CDF)
+# ---------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) of a 4-word counter under a 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def sampling_cdf(weights):
+    """Running sums of the sampling weights ||a_i||^2 (i ascending)."""
+    w = _f64(weights)
+    cdf = np.zeros_like(w)
+    st = _load().oracle_sampling_cdf(len(w), _p(w), _p(cdf))
+    if st:
+        raise OracleError(st, "sampling_cdf")
+    return cdf
+
+
+def sample_stream(cdf, seed, K, eta, k0=0):
+    """K*eta row indices (steps k0 .. k0+K-1, step-major) drawn with Philox4x32-10 and the inverse CDF."""
+    c = _f64(cdf)
+    out = np.zeros(max(int(K) * int(eta), 1), dtype=np.int32)
+    st = _load().oracle_sample_stream(len(c), _p(c), ctypes.c_uint64(int(seed)), int(k0), int(K), int(eta), _p(out))
+    if st:
+        raise OracleError(st, "sample_stream")
+    return out[:int(K) * int(eta)]
+

@@ -298,3 +298,81 @@ done:
   free(Z); free(xk); free(zbar); free(xbar); free(r); free(r2); free(cbar);
   return st;
 }
+
+/*
+ * Row sampler (the index stream of Sec. 1.1 drawn from a counter-based
+ * generator instead of being handed in).
+ *
+ * Philox4x32-10 as defined by Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3" (SC'11): the 128-bit counter passes through ten
+ * rounds; a round multiplies words 0 and 2 by M0 = 0xD2511F53 and
+ * M1 = 0xCD9E8D57 into 64-bit products and outputs
+ *   (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0));
+ * between rounds the key is advanced by the Weyl constants W0 = 0x9E3779B9,
+ * W1 = 0xBB67AE85 (the first round uses the key as given).
+ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    const uint32_t n3 = (uint32_t)p0;
+    c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+  }
+  out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+/* cdf_i = w_0 + ... + w_i, i ascending (sampling weights w_i = ||a_i||^2). */
+int oracle_sampling_cdf(int64_t m, const double *w, double *cdf) {
+  if (m <= 0 || !w || !cdf) return 1;
+  double s = 0.0;
+  for (int64_t i = 0; i < m; ++i) {
+    if (!(w[i] >= 0.0)) return 1;
+    s += w[i];
+    cdf[i] = s;
+  }
+  return 0;
+}
+
+/*
+ * Index t of step k (k0 <= k < k0 + K, 0 <= t < eta): Philox4x32-10 of the
+ * counter (t, k mod 2^32, k div 2^32, 0) under the key (seed mod 2^32,
+ * seed div 2^32) gives words w0, w1; u = ((w0 >> 5) 2^26 + (w1 >> 6)) / 2^53
+ * in [0, 1); the row is the first i with cdf_i > u cdf_{m-1} (at most m-1),
+ * so P(i) = w_i / sum_j w_j (sampling with replacement, p_i proportional to
+ * ||a_i||^2). out[(k - k0) eta + t], step-major.
+ */
+int oracle_sample_stream(int64_t m, const double *cdf, uint64_t seed, int64_t k0, int64_t K, int32_t eta,
+                         int32_t *out) {
+  if (m <= 0 || !cdf || K < 0 || k0 < 0 || eta < 1 || (K > 0 && !out)) return 1;
+  const double total = cdf[m - 1];
+  if (!(total > 0.0) || !isfinite(total)) return 1;
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int64_t k = k0; k < k0 + K; ++k) {
+    for (int32_t t = 0; t < eta; ++t) {
+      const uint32_t ctr[4] = {(uint32_t)t, (uint32_t)k, (uint32_t)((uint64_t)k >> 32), 0u};
+      uint32_t w[4];
+      oracle_philox4x32_10(ctr, key, w);
+      const uint64_t bits = ((uint64_t)(w[0] >> 5) << 26) | (uint64_t)(w[1] >> 6);
+      const double u = (double)bits * (1.0 / 9007199254740992.0);
+      const double target = u * total;
+      /* first i with cdf[i] > target */
+      int64_t lo = 0, hi = m;
+      while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > target) hi = mid;
+        else lo = mid + 1;
+      }
+      out[(k - k0) * eta + t] = (int32_t)(lo < m ? lo : m - 1);
+    }
+  }
+  return 0;
+}

@@ -56,6 +56,9 @@ SIGNATURES = {
                                            ctypes.POINTER(c_sz)]),
     "rsk_avg_adjoint": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_i32, c_vp, c_vp,
                                 c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "rsk_workspace_size_sampling_cdf": (c_i32, [c_i64, ctypes.POINTER(c_sz)]),
+    "rsk_sampling_cdf_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_vp, c_sz, c_vp]),
+    "rsk_sample_stream": (c_i32, [c_vp, c_i64, ctypes.c_uint64, c_i64, c_i64, c_i32, c_vp, c_vp]),
     "rsk_workspace_size_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_batched": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),

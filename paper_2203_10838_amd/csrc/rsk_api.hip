@@ -566,6 +566,31 @@ int32_t rsk_avg_solve_csr(const rsk_csr* A, const void* b, const rsk_params* p, 
 }
 
 
+int32_t rsk_workspace_size_sampling_cdf(int64_t m, size_t* bytes) {
+  if (m <= 0 || !bytes) return RSK_ERR_INVALID_ARG;
+  *bytes = rsk::sampling_cdf_ws_bytes(m);
+  return RSK_OK;
+}
+
+int32_t rsk_sampling_cdf_dense(const rsk_dense* A, double* cdf, void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!cdf) return RSK_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < rsk::sampling_cdf_ws_bytes(A->m) || ((uintptr_t)workspace) % 256)
+    return RSK_ERR_WORKSPACE;
+  const hipError_t e = A->dtype == RSK_F64
+      ? rsk::launch_sampling_cdf<double>((const double*)A->val, A->m, A->n, A->ld, cdf, workspace, (hipStream_t)stream)
+      : rsk::launch_sampling_cdf<float>((const float*)A->val, A->m, A->n, A->ld, cdf, workspace, (hipStream_t)stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_sample_stream(const double* cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int32_t eta,
+                          int32_t* out, void* stream) {
+  if (!cdf || m <= 0 || m > INT32_MAX || k0 < 0 || K < 0 || eta < 1 || (K > 0 && !out)) return RSK_ERR_INVALID_ARG;
+  const hipError_t e = rsk::launch_sample_stream(cdf, m, seed, k0, K, eta, out, (hipStream_t)stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
 int32_t rsk_abi_version(void) { return RSK_ABI_VERSION; }
 
 const char* rsk_status_string(int32_t s) {

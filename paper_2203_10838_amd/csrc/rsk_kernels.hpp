@@ -251,6 +251,14 @@ hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, hipStre
 constexpr int kRtMaxEta = 1024, kRtMaxCPL = 5, kRtOwnMax = 4;
 hipError_t launch_zero_status(int* status, hipStream_t stream);
 
+// Row sampler (Philox4x32-10 + inverse CDF) and the FP64 cdf of the row norms.
+size_t sampling_cdf_ws_bytes(int64_t m);
+template <typename T>
+hipError_t launch_sampling_cdf(const T* A, int64_t m, int64_t n, int64_t ld, double* cdf, void* ws,
+                               hipStream_t stream);
+hipError_t launch_sample_stream(const double* cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int eta,
+                                int32_t* out, hipStream_t stream);
+
 // Largest co-resident grid for the dense kernel with these sizes (0 if none).
 template <typename T>
 int dense_max_grid(int vec, int eta, int wq_max, int tile_cache, int64_t xr_elems, size_t* lds_bytes);

@@ -341,6 +341,40 @@ def adjoint_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, 
 
 
 # ---------------------------------------------------------------------------
+# Row sampler
+# ---------------------------------------------------------------------------
+
+def sampling_cdf(A: torch.Tensor) -> torch.Tensor:
+    """Running sums of the FP64 row norms ||a_i||^2 on the device (m doubles)."""
+    d = dense_desc(A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_sampling_cdf(d.m, ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_sampling_cdf")
+    ws = _workspace(nbytes.value, A.device)
+    cdf = torch.empty(A.shape[0], dtype=torch.float64, device=A.device)
+    st = _lib().rsk_sampling_cdf_dense(ctypes.byref(d), cdf.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_sampling_cdf_dense")
+    return cdf
+
+
+def sample_stream(cdf: torch.Tensor, *, seed: int, K: int, eta: int, k0: int = 0,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K*eta row indices (steps k0 .. k0+K-1) from Philox4x32-10 and the inverse CDF, on the device."""
+    _dev(cdf, "cdf", torch.float64)
+    m = cdf.numel()
+    if out is None:
+        out = torch.empty(max(K * eta, 1), dtype=torch.int32, device=cdf.device)
+    _dev(out, "out", torch.int32, K * eta)
+    st = _lib().rsk_sample_stream(cdf.data_ptr(), m, int(seed) & ((1 << 64) - 1), int(k0), int(K), int(eta),
+                                  out.data_ptr(), _stream())
+    if st:
+        raise RskError(st, "rsk_sample_stream")
+    return out[:K * eta]
+
+
+# ---------------------------------------------------------------------------
 # Batched independent systems
 # ---------------------------------------------------------------------------
 

@@ -419,3 +419,56 @@ def test_paper_experiment_rska_beats_rsk_on_average():
         err_rsk.append(_rel(r1["x"], xh))
         err_rska.append(_rel(r2["x"], xh))
     assert np.mean(err_rska) < np.mean(err_rsk)
+
+
+# ---------------------------------------------------------------------------
+# Row sampler: Philox4x32-10 known answers, the distribution p_i = w_i / sum w
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answer_vectors():
+    spec = json.load(open(os.path.join(HERE, "golden", "philox4x32_10_kat.json")))
+    for v in spec["vectors"]:
+        ctr = [int(x, 16) for x in v["ctr"]]
+        key = [int(x, 16) for x in v["key"]]
+        assert [int(x) for x in oracle.philox4x32_10(ctr, key)] == [int(x, 16) for x in v["out"]]
+
+
+def test_sampling_cdf_is_the_running_sum():
+    w = np.random.default_rng(1).random(1000) * 3.0
+    assert np.array_equal(oracle.sampling_cdf(w), np.cumsum(w))
+
+
+def test_sampler_distribution_chi_square():
+    """200000 draws over 16 rows: counts agree with p_i = w_i / sum w (Sec. 1.1, sampling with replacement)."""
+    from scipy.stats import chisquare
+    w = np.array([0.5, 1.0, 2.0, 0.1, 4.0, 1.5, 0.25, 3.0, 1.0, 0.75, 2.5, 0.05, 1.25, 0.6, 2.2, 0.9])
+    idx = oracle.sample_stream(oracle.sampling_cdf(w), seed=20310838, K=2000, eta=100)
+    counts = np.bincount(idx, minlength=len(w))
+    p = w / w.sum()
+    assert chisquare(counts, p * len(idx)).pvalue > 1e-3
+    # a plausible bias (off-by-one in the search) would show at once
+    assert abs(counts[11] / len(idx) - p[11]) < 5 * np.sqrt(p[11] / len(idx))
+
+
+def test_sampler_zero_weights_and_single_row():
+    w = np.array([0.0, 0.0, 3.0, 0.0, 1.0, 0.0])
+    idx = oracle.sample_stream(oracle.sampling_cdf(w), seed=7, K=500, eta=20)
+    assert set(np.unique(idx)) <= {2, 4}
+    assert oracle.sample_stream(oracle.sampling_cdf([2.5]), seed=3, K=10, eta=7).tolist() == [0] * 70
+
+
+def test_sampler_inverse_cdf_against_linear_search_and_offsets():
+    """Each index is the first row whose running weight exceeds u * total, u built from the
+    first two Philox words of the counter (t, k, 0, 0); a stream started at k0 is the tail of a
+    stream started at 0."""
+    w = np.random.default_rng(2).random(37) + 0.01
+    cdf = oracle.sampling_cdf(w)
+    seed, K, eta = (1 << 40) + 12345, 12, 9
+    full = oracle.sample_stream(cdf, seed, K, eta)
+    for k in range(K):
+        for t in range(eta):
+            o = oracle.philox4x32_10([t, k, 0, 0], [seed & 0xFFFFFFFF, seed >> 32])
+            u = ((int(o[0]) >> 5) * 2.0 ** 26 + (int(o[1]) >> 6)) / 2.0 ** 53
+            lin = next(i for i in range(len(w)) if cdf[i] > u * cdf[-1])
+            assert full[k * eta + t] == lin
+    assert np.array_equal(oracle.sample_stream(cdf, seed, K - 5, eta, k0=5), full[5 * eta:])
