@@ -16,6 +16,8 @@ What is here (each function cites the passage it follows):
   one stream per system).
 * ``rska_dense_adjoint`` -- reverse mode of K unrolled steps, every iterate
   stored (no checkpointing).
+* ``lb_dense`` / ``power_ata`` -- the full-batch linearized Bregman comparator
+  (the remark on its rate in Sec. 4) and sigma_max(A)^2 by power iteration;
 * ``philox4x32_10``, ``sampling_cdf``, ``sample_stream`` -- the row sampler
   (p_i proportional to ||a_i||^2, Sec. 1.1) driven by the counter-based
   generator Philox4x32-10 of Salmon et al. (SC'11) and an inverse-CDF search;
@@ -85,9 +87,11 @@ def _load():
             lib.oracle_philox4x32_10.restype = None
             lib.oracle_sampling_cdf.argtypes = [i64, vp, vp]
             lib.oracle_sample_stream.argtypes = [i64, vp, ctypes.c_uint64, i64, i64, i32, vp]
+            lib.oracle_lb_dense.argtypes = [i64, i64, i64, vp, vp, dbl, dbl, i64, vp, vp, i64, vp, vp, vp]
+            lib.oracle_power_ata.argtypes = [i64, i64, i64, vp, i64, vp, vp]
             for f in (lib.oracle_rownorm2_dense, lib.oracle_rownorm2_csr, lib.oracle_rska_dense,
                       lib.oracle_rska_csr, lib.oracle_rska_dense_adjoint, lib.oracle_sampling_cdf,
-                      lib.oracle_sample_stream):
+                      lib.oracle_sample_stream, lib.oracle_lb_dense, lib.oracle_power_ata):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -320,4 +324,38 @@ def sample_stream(cdf, seed, K, eta, k0=0):
     if st:
         raise OracleError(st, "sample_stream")
     return out[:int(K) * int(eta)]
+
+
+# ---------------------------------------------------------------------------
+# Linearized Bregman (full batch) and power iteration
+# ---------------------------------------------------------------------------
+
+def lb_dense(A, b, lam, step, K, *, check_every=0, xref=None):
+    """K linearized Bregman steps x* -= step A^T(Ax - b), x = S_lambda(x*). Returns dict(z, x, res, hist)."""
+    A = _f64(A)
+    b = _f64(b)
+    m, n = A.shape
+    z = np.zeros(n)
+    x = np.zeros(n)
+    res = np.zeros(max(int(K), 1))
+    nh = (int(K) // check_every) if (xref is not None and check_every > 0) else 0
+    hist = np.full(max(nh, 1), np.nan)
+    xr = None if xref is None else _f64(xref)
+    st = _load().oracle_lb_dense(m, n, n, _p(A), _p(b), float(lam), float(step), int(K), _p(z), _p(x),
+                                 int(check_every) if xr is not None else 0, _p(xr), _p(hist), _p(res))
+    if st:
+        raise OracleError(st, "lb_dense")
+    return {"z": z, "x": x, "res": res[:int(K)], "hist": hist[:nh]}
+
+
+def power_ata(A, iters, v0=None):
+    """sigma_max(A)^2 by power iteration on A^T A (v0 defaults to v_j = 1 + (j mod 7) / 7)."""
+    A = _f64(A)
+    m, n = A.shape
+    v = _f64(v0) if v0 is not None else 1.0 + (np.arange(n) % 7) / 7.0
+    est = np.zeros(1)
+    st = _load().oracle_power_ata(m, n, n, _p(A), int(iters), _p(v), _p(est))
+    if st:
+        raise OracleError(st, "power_ata")
+    return float(est[0])
 

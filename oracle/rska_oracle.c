@@ -376,3 +376,81 @@ int oracle_sample_stream(int64_t m, const double *cdf, uint64_t seed, int64_t k0
   }
   return 0;
 }
+
+/*
+ * Linearized Bregman method (full-batch comparator; the remark on its
+ * convergence rate in Sec. 4, and eq. (bsk) with tau_k = all rows):
+ *   x*_{k+1} = x*_k - s A^T (A x_k - b),  x_{k+1} = S_lambda(x*_{k+1}),
+ * with step s (1/||A||_2^2 in the paper). r = A x - b is formed first, then
+ * A^T r (j ascending, i ascending). Optional monitor as in oracle_rska_dense,
+ * and the residual norm ||A x_k - b|| of every step in res_hist (nullable).
+ */
+int oracle_lb_dense(int64_t m, int64_t n, int64_t ld, const double *A, const double *b, double lambda, double step,
+                    int64_t K, double *z, double *x, int64_t check_every, const double *xref, double *err_hist,
+                    double *res_hist) {
+  if (m <= 0 || n <= 0 || ld < n || !A || !b || !z || !x || K < 0 || !(lambda >= 0.0) || !(step > 0.0)) return 1;
+  double *r = (double *)malloc(sizeof(double) * (size_t)m);
+  double *g = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!r || !g) { free(r); free(g); return 1; }
+  for (int64_t j = 0; j < n; ++j) { z[j] = 0.0; x[j] = 0.0; }
+  int code = 0;
+  for (int64_t k = 0; k < K; ++k) {
+    double rr = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int64_t j = 0; j < n; ++j) s += A[i * ld + j] * x[j];
+      r[i] = s - b[i];
+      rr += r[i] * r[i];
+    }
+    if (res_hist) res_hist[k] = sqrt(rr);
+    for (int64_t j = 0; j < n; ++j) g[j] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j < n; ++j) g[j] += A[i * ld + j] * r[i];
+    for (int64_t j = 0; j < n; ++j) {
+      z[j] -= step * g[j];
+      x[j] = shrink(z[j], lambda);
+      if (!isfinite(z[j])) code = 7;
+    }
+    if (code) break;
+    if (xref && check_every > 0 && (k + 1) % check_every == 0 && err_hist)
+      err_hist[(k + 1) / check_every - 1] = rel_err(n, x, xref);
+  }
+  free(r);
+  free(g);
+  return code;
+}
+
+/* sigma_max(A)^2 by `iters` steps of power iteration on A^T A from v0 (n):
+   w = A^T (A v), estimate = <v, w> with ||v|| = 1, then v = w / ||w||. */
+int oracle_power_ata(int64_t m, int64_t n, int64_t ld, const double *A, int64_t iters, const double *v0,
+                     double *est) {
+  if (m <= 0 || n <= 0 || ld < n || !A || !v0 || !est || iters < 1) return 1;
+  double *v = (double *)malloc(sizeof(double) * (size_t)n);
+  double *w = (double *)malloc(sizeof(double) * (size_t)n);
+  double *u = (double *)malloc(sizeof(double) * (size_t)m);
+  if (!v || !w || !u) { free(v); free(w); free(u); return 1; }
+  double nv = 0.0;
+  for (int64_t j = 0; j < n; ++j) nv += v0[j] * v0[j];
+  nv = sqrt(nv);
+  for (int64_t j = 0; j < n; ++j) v[j] = v0[j] / nv;
+  double lam = 0.0;
+  for (int64_t it = 0; it < iters; ++it) {
+    for (int64_t i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int64_t j = 0; j < n; ++j) s += A[i * ld + j] * v[j];
+      u[i] = s;
+    }
+    for (int64_t j = 0; j < n; ++j) w[j] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j < n; ++j) w[j] += A[i * ld + j] * u[i];
+    double vw = 0.0, ww = 0.0;
+    for (int64_t j = 0; j < n; ++j) { vw += v[j] * w[j]; ww += w[j] * w[j]; }
+    lam = vw;
+    ww = sqrt(ww);
+    if (!(ww > 0.0)) break;
+    for (int64_t j = 0; j < n; ++j) v[j] = w[j] / ww;
+  }
+  *est = lam;
+  free(v); free(w); free(u);
+  return 0;
+}

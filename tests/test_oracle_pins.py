@@ -472,3 +472,42 @@ def test_sampler_inverse_cdf_against_linear_search_and_offsets():
             lin = next(i for i in range(len(w)) if cdf[i] > u * cdf[-1])
             assert full[k * eta + t] == lin
     assert np.array_equal(oracle.sample_stream(cdf, seed, K - 5, eta, k0=5), full[5 * eta:])
+
+
+# ---------------------------------------------------------------------------
+# Linearized Bregman (full-batch comparator) and power iteration
+# ---------------------------------------------------------------------------
+
+def test_power_iteration_matches_svd():
+    A = inputs.dense_system(120, 40, 3, dtype="f64", seed=41)["A"]
+    s = np.linalg.svd(A, compute_uv=False)
+    assert abs(oracle.power_ata(A, 300) - s[0] ** 2) <= 1e-8 * s[0] ** 2
+
+
+def test_lb_consistent_limit_and_rate_bound():
+    """Consistent overdetermined system: LB with step 1/||A||_2^2 converges to x_hat, and every iterate
+    obeys ||x_k - x_hat||^2 <= 2 (1 - 1/(2 gamma ||A||_2^2))^k f(x_hat) (the remark's rate, gamma of Lemma Gamma)."""
+    sysd = inputs.dense_system(40, 8, 3, dtype="f64", seed=31)
+    A, b, xh = sysd["A"], sysd["b"], sysd["xhat"]
+    lam = 0.5
+    s2 = float(np.linalg.svd(A, compute_uv=False)[0] ** 2)
+    st = _sigma_tilde_min(A)
+    xmin = np.min(np.abs(xh[xh != 0]))
+    gamma = (xmin + 2 * lam) / (xmin * st ** 2)
+    q = 1 - 1 / (2 * gamma * s2)
+    for k in (1, 5, 20, 80, 300):
+        r = oracle.lb_dense(A, b, lam, 1.0 / s2, k)
+        assert np.sum((r["x"] - xh) ** 2) <= 2 * q ** k * oracle.f_value(xh, lam)
+    r = oracle.lb_dense(A, b, lam, 1.0 / s2, 4000)
+    assert np.linalg.norm(r["x"] - xh) <= 1e-9 * np.linalg.norm(xh)
+    assert r["res"][-1] <= 1e-9 * np.linalg.norm(b)
+
+
+def test_lb_lambda0_underdetermined_gives_min_norm_solution():
+    """lambda = 0 from x_0 = 0: the Landweber iteration stays in range(A^T) and converges to pinv(A) b."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((12, 30))
+    b = rng.standard_normal(12)
+    s2 = float(np.linalg.svd(A, compute_uv=False)[0] ** 2)
+    r = oracle.lb_dense(A, b, 0.0, 1.0 / s2, 6000)
+    assert np.linalg.norm(r["x"] - np.linalg.pinv(A) @ b) <= 1e-8 * np.linalg.norm(np.linalg.pinv(A) @ b)
