@@ -146,6 +146,46 @@ int32_t rsk_sampling_cdf_dense(const rsk_dense *A, double *cdf, void *workspace,
 int32_t rsk_sample_stream(const double *cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int32_t eta,
                           int32_t *out, void *stream);
 
+/*
+ * Linearized Bregman method: the full-batch comparator of Sec. 4 (the block
+ * step of eq. (bsk) with every row in the block and the step 1/||A||_2^2 of
+ * the remark on its linear rate; the paper cites Cai, Osher and Shen and Yin
+ * for it). From x*_0 = 0, x_0 = 0 (or the x* passed in, with x_0 = S_lambda(x*_0)):
+ *   x*_{k+1} = x*_k - step A^T (A x_k - b),   x_{k+1} = S_lambda(x*_{k+1}).
+ * One iteration reads A once (a row-blocked pass forming A x_k - b and
+ * A^T (A x_k - b) together) and n-sized vectors a few times. All sums are in
+ * fixed orders: the results are the same bits on every run.
+ *
+ * rsk_workspace_size_lb_dense: device workspace bytes for A (256-byte aligned).
+ * rsk_lb_solve_dense: A device row-major (rsk_dense), b device (m), x_star and
+ *   x device (n, dtype of A): x_star in (warm_start) and out, x out. Fails with
+ *   RSK_ERR_UNSUPPORTED for n > 6144 * (16 / sizeof element) (n > 6144 when A
+ *   is not 16-byte aligned or ld is not a multiple of 16 / sizeof element).
+ *   Device status as in rsk_params (RSK_ERR_NONFINITE when x* leaves the
+ *   finite range; status_dev[1] = iterations run).
+ * rsk_spectral_norm2_dense: sigma_max(A)^2 by `iters` >= 1 steps of power
+ *   iteration on A^T A from v_j = 1 + (j mod 7)/7 (normalised): w = A^T A v,
+ *   est = <v, w>, v = w / ||w||. est: device double; v: device (n, dtype of
+ *   A), out: the last unit vector. Same workspace as rsk_lb_solve_dense.
+ */
+typedef struct {
+  double lambda;       /* >= 0 */
+  double step;         /* > 0; the paper's choice is 1 / sigma_max(A)^2 (rsk_spectral_norm2_dense) */
+  int64_t K;           /* >= 0 iterations */
+  int32_t warm_start;  /* 1: start from the x_star passed in */
+  const void *x_ref;   /* nullable device vector (n): monitor target */
+  int64_t check_every; /* > 0 with x_ref: every check_every iterations record ||x - x_ref||/||x_ref|| */
+  double *err_hist;    /* nullable device array, K/check_every entries */
+  double *res_hist;    /* nullable device array, K entries: ||A x_k - b|| of the iterate step k starts from */
+  int32_t *status_dev; /* device int32[2]: [0] status, [1] iterations run. Required. */
+} rsk_lb_params;
+
+int32_t rsk_workspace_size_lb_dense(const rsk_dense *A, size_t *bytes);
+int32_t rsk_lb_solve_dense(const rsk_dense *A, const void *b, const rsk_lb_params *p, void *x_star, void *x,
+                           void *workspace, size_t ws_bytes, void *stream);
+int32_t rsk_spectral_norm2_dense(const rsk_dense *A, int64_t iters, void *v, double *est, void *workspace,
+                                 size_t ws_bytes, void *stream);
+
 /* Version of this ABI (RSK_ABI_VERSION). */
 int32_t rsk_abi_version(void);
 

@@ -40,6 +40,11 @@ class RskBatchItem(ctypes.Structure):
                 ("tol", c_dbl), ("err_hist", c_vp), ("status_dev", c_vp)]
 
 
+class RskLbParams(ctypes.Structure):
+    _fields_ = [("lambda_", c_dbl), ("step", c_dbl), ("K", c_i64), ("warm_start", c_i32), ("x_ref", c_vp),
+                ("check_every", c_i64), ("err_hist", c_vp), ("res_hist", c_vp), ("status_dev", c_vp)]
+
+
 # name -> (restype, argtypes); every symbol include/rsk.h declares
 SIGNATURES = {
     "rsk_abi_version": (c_i32, []),
@@ -59,6 +64,10 @@ SIGNATURES = {
     "rsk_workspace_size_sampling_cdf": (c_i32, [c_i64, ctypes.POINTER(c_sz)]),
     "rsk_sampling_cdf_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_vp, c_sz, c_vp]),
     "rsk_sample_stream": (c_i32, [c_vp, c_i64, ctypes.c_uint64, c_i64, c_i64, c_i32, c_vp, c_vp]),
+    "rsk_workspace_size_lb_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(c_sz)]),
+    "rsk_lb_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskLbParams), c_vp, c_vp, c_vp, c_sz,
+                                   c_vp]),
+    "rsk_spectral_norm2_dense": (c_i32, [ctypes.POINTER(RskDense), c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_batched": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),

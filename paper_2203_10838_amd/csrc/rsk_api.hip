@@ -383,6 +383,64 @@ int32_t adj_layout(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t c
   return RSK_OK;
 }
 
+struct LbLayout {
+  int vec, cpt, G;
+  size_t lds, bytes, offPart, offR;
+  int64_t nstride;
+};
+
+template <typename T>
+int32_t lb_layout(const rsk_dense* A, LbLayout* L) {
+  constexpr int V = rsk::kLbVec<T>;
+  L->vec = (((uintptr_t)A->val) % 16 == 0 && A->ld % V == 0) ? V : 1;
+  if (!rsk::lb_plan<T>(A->n, L->vec, &L->cpt, &L->lds, &L->G, &L->nstride)) return RSK_ERR_UNSUPPORTED;
+  L->offPart = 0;
+  L->offR = align256((size_t)L->G * L->nstride * sizeof(T));
+  L->bytes = L->offR + align256((size_t)L->G * sizeof(double));
+  return RSK_OK;
+}
+
+template <typename T>
+rsk::LbArgs<T> lb_args(const rsk_dense* A, const LbLayout& L, void* ws) {
+  rsk::LbArgs<T> a{};
+  a.A = (const T*)A->val;
+  a.m = A->m;
+  a.n = A->n;
+  a.ld = A->ld;
+  a.part = (T*)((char*)ws + L.offPart);
+  a.rpart = (double*)((char*)ws + L.offR);
+  a.nstride = L.nstride;
+  a.G = L.G;
+  a.vec = L.vec;
+  a.cpt = L.cpt;
+  a.lds = L.lds;
+  return a;
+}
+
+template <typename T>
+int32_t lb_solve_t(const rsk_dense* A, const void* b, const rsk_lb_params* p, void* x_star, void* x, void* ws,
+                   size_t ws_bytes, hipStream_t s) {
+  LbLayout L;
+  int32_t st = lb_layout<T>(A, &L);
+  if (st) return st;
+  if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  rsk::LbArgs<T> a = lb_args<T>(A, L, ws);
+  a.b = (const T*)b;
+  a.lambda = (T)p->lambda;
+  a.step = (T)p->step;
+  a.K = p->K;
+  a.z = (T*)x_star;
+  a.x = (T*)x;
+  a.warm = p->warm_start ? 1 : 0;
+  a.xref = (const T*)p->x_ref;
+  a.check_every = p->check_every;
+  a.err_hist = p->err_hist;
+  a.res_hist = p->res_hist;
+  a.status = p->status_dev;
+  if (rsk::launch_zero_status(p->status_dev, s) != hipSuccess) return RSK_ERR_HIP;
+  return rsk::launch_lb<T>(a, s) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -588,6 +646,45 @@ int32_t rsk_sample_stream(const double* cdf, int64_t m, uint64_t seed, int64_t k
                           int32_t* out, void* stream) {
   if (!cdf || m <= 0 || m > INT32_MAX || k0 < 0 || K < 0 || eta < 1 || (K > 0 && !out)) return RSK_ERR_INVALID_ARG;
   const hipError_t e = rsk::launch_sample_stream(cdf, m, seed, k0, K, eta, out, (hipStream_t)stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_workspace_size_lb_dense(const rsk_dense* A, size_t* bytes) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  LbLayout L;
+  st = A->dtype == RSK_F64 ? lb_layout<double>(A, &L) : lb_layout<float>(A, &L);
+  if (st) return st;
+  *bytes = L.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_lb_solve_dense(const rsk_dense* A, const void* b, const rsk_lb_params* p, void* x_star, void* x,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!p || !b || !x_star || !x || !p->status_dev || p->K < 0 || p->K >= (int64_t(1) << 31)) return RSK_ERR_INVALID_ARG;
+  if (!(p->lambda >= 0.0) || !isfinite(p->lambda) || !finite_pos(p->step)) return RSK_ERR_INVALID_ARG;
+  if (p->check_every < 0 || (p->x_ref && p->check_every > 0 && !p->err_hist)) return RSK_ERR_INVALID_ARG;
+  return A->dtype == RSK_F64 ? lb_solve_t<double>(A, b, p, x_star, x, workspace, ws_bytes, (hipStream_t)stream)
+                             : lb_solve_t<float>(A, b, p, x_star, x, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t rsk_spectral_norm2_dense(const rsk_dense* A, int64_t iters, void* v, double* est, void* workspace,
+                                 size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (iters < 1 || !v || !est) return RSK_ERR_INVALID_ARG;
+  LbLayout L;
+  st = A->dtype == RSK_F64 ? lb_layout<double>(A, &L) : lb_layout<float>(A, &L);
+  if (st) return st;
+  if (!workspace || ws_bytes < L.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
+  hipError_t e;
+  if (A->dtype == RSK_F64)
+    e = rsk::launch_power<double>(lb_args<double>(A, L, workspace), iters, (double*)v, est, (hipStream_t)stream);
+  else
+    e = rsk::launch_power<float>(lb_args<float>(A, L, workspace), iters, (float*)v, est, (hipStream_t)stream);
   return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
 }
 

@@ -251,6 +251,41 @@ hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, hipStre
 constexpr int kRtMaxEta = 1024, kRtMaxCPL = 5, kRtOwnMax = 4;
 hipError_t launch_zero_status(int* status, hipStream_t stream);
 
+// Linearized Bregman (full batch) and power iteration on A^T A. One pass reads A once with
+// kLbThreads threads a workgroup, chunks of vec elements (16 bytes, or 1 element when A is not
+// 16-byte aligned or ld not a multiple of kLbVec), at most 12 chunks a thread: n <= 6144 vec.
+constexpr int kLbThreads = 512;
+template <typename T>
+constexpr int kLbVec = 16 / (int)sizeof(T);
+constexpr int kLbMaxChunksPerThread = 12;
+template <typename T>
+struct LbArgs {
+  const T* A;
+  int64_t m, n, ld;
+  const T* b;
+  T lambda, step;
+  int64_t K;
+  T* z;                   // x*: in when warm, out
+  T* x;                   // out (in when warm: S_lambda(z))
+  int warm;
+  const T* xref;
+  int64_t check_every;
+  double* err_hist;
+  double* res_hist;       // ||A x_k - b|| before step k (nullable)
+  int* status;
+  T* part;                // [G][nstride] per-workgroup partial A^T r
+  double* rpart;          // [G] per-workgroup sum of r_i^2
+  int64_t nstride;        // nchunks * vec
+  int G, vec, cpt;
+  size_t lds;
+};
+template <typename T>
+int lb_plan(int64_t n, int vec, int* cpt, size_t* lds, int* grid, int64_t* nstride);
+template <typename T>
+hipError_t launch_lb(const LbArgs<T>& a, hipStream_t stream);
+template <typename T>
+hipError_t launch_power(const LbArgs<T>& a, int64_t iters, T* v, double* est, hipStream_t stream);
+
 // Row sampler (Philox4x32-10 + inverse CDF) and the FP64 cdf of the row norms.
 size_t sampling_cdf_ws_bytes(int64_t m);
 template <typename T>

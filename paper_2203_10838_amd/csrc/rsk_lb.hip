@@ -1,0 +1,322 @@
+// Linearized Bregman method (the full-batch comparator of RSKA: the remark on
+// its convergence rate in Sec. 4, eq. (bsk) with every row in the block):
+//   x*_{k+1} = x*_k - s A^T (A x_k - b),  x_{k+1} = S_lambda(x*_{k+1}),
+// s = 1/||A||_2^2 in the paper, and sigma_max(A)^2 by power iteration on A^T A.
+//
+// One iteration reads A once. lb_pass: each persistent workgroup takes a block
+// of whole rows; x (n) sits in LDS and the thread's share of the partial
+// A^T r (chunks q = tid + NT c) in registers. Per row: the dot from the row
+// chunks in registers (the next row's chunks are already in flight), a
+// fixed-order block reduction (DPP sums in each wave, then the waves in
+// order), r_i = dot - b_i, and the row's contribution r_i a_i to the partial.
+// lb_update sums the workgroups' partials in workgroup order and applies the
+// step with S_lambda fused. All sums have fixed orders: runs are bitwise
+// reproducible.
+#include "rsk_dense_run.hpp"
+
+namespace rsk {
+
+namespace {
+
+constexpr int kLbWaves = kLbThreads / 64;
+
+}  // namespace
+
+template <typename T, int VEC, int CPT>
+__global__ __launch_bounds__(kLbThreads) void lb_pass(const T* __restrict__ A, int64_t m, int64_t n, int64_t ld,
+                                                      const T* __restrict__ x, const T* __restrict__ b,
+                                                      T* __restrict__ part, double* __restrict__ rpart,
+                                                      const int* status) {
+  using V = Vec<T, VEC>;
+  extern __shared__ __align__(16) unsigned char lsm[];
+  __shared__ T red[2][kLbWaves];
+  if (status && status[0]) return;
+  V* xs = reinterpret_cast<V*>(lsm);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = blockIdx.x, G = gridDim.x;
+  const int64_t nch = (n + VEC - 1) / VEC;
+  for (int64_t q = tid; q < nch; q += kLbThreads) {
+    V v;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v.v[e] = q * VEC + e < n ? x[q * VEC + e] : T(0);
+    xs[q] = v;
+  }
+  __syncthreads();
+  const int64_t i0 = (int64_t)g * m / G, i1 = (int64_t)(g + 1) * m / G;
+  V acc[CPT], cur[CPT], nxt[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[c].v[e] = T(0);
+  auto load_row = [&](int64_t i, V (&dst)[CPT]) {
+    const T* rowp = A + i * ld;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int64_t q = tid + (int64_t)kLbThreads * c;
+      dst[c] = q < nch ? load_vec<T, VEC>(rowp, q * VEC, n) : V{};
+    }
+  };
+  double rr = 0.0;
+  if (i0 < i1) load_row(i0, cur);
+  for (int64_t i = i0; i < i1; ++i) {
+    const bool more = i + 1 < i1;
+    if (more) load_row(i + 1, nxt);
+    const T bi = b ? b[i] : T(0);
+    T dot = T(0);
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int64_t q = tid + (int64_t)kLbThreads * c;
+      if (q < nch) {
+        const V xv = xs[q];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) dot += cur[c].v[e] * xv.v[e];
+      }
+    }
+    dot = lane_sum(dot, 64);
+    const int par = (int)(i & 1);
+    if (lane == 0) red[par][wave] = dot;
+    __syncthreads();  // red[par] is rewritten two rows later, after the next barrier
+    T s = T(0);
+#pragma unroll
+    for (int w = 0; w < kLbWaves; ++w) s += red[par][w];
+    const T r = s - bi;
+    rr += (double)r * (double)r;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[c].v[e] += r * cur[c].v[e];
+    if (more) {
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) cur[c] = nxt[c];
+    }
+  }
+  T* pg = part + (size_t)g * nch * VEC;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int64_t q = tid + (int64_t)kLbThreads * c;
+    if (q < nch) *reinterpret_cast<V*>(pg + q * VEC) = acc[c];
+  }
+  if (tid == 0) rpart[g] = rr;  // every thread of the block holds the same sum of r_i^2
+}
+
+// g_j = sum over workgroups (in order) of part[.][j]; z_j -= s g_j, x_j = S_lambda(z_j).
+template <typename T>
+__global__ void lb_update(const T* __restrict__ part, int G, int64_t n, int64_t nstride, T* __restrict__ z,
+                          T* __restrict__ x, T step, T lambda, const double* __restrict__ rpart,
+                          double* res_out, int* status, int64_t k) {
+  if (status[0]) return;
+  int bad = 0;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    T gj = T(0);
+    for (int q = 0; q < G; ++q) gj += part[(size_t)q * nstride + j];
+    const T zj = z[j] - step * gj;
+    z[j] = zj;
+    x[j] = shrink(zj, lambda);
+    bad |= !isfinite(zj);
+  }
+  if (bad) set_status(status, ST_NONFINITE);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    status[1] = (int)(k + 1);  // steps started; the nonfinite check marks a failed one
+    if (res_out) {
+      double s = 0.0;
+      for (int q = 0; q < G; ++q) s += rpart[q];
+      *res_out = sqrt(s);
+    }
+  }
+}
+
+// Start: x* = 0 and x = 0, or (warm) x = S_lambda(x*) from the given x*.
+template <typename T>
+__global__ void lb_init(T* z, T* x, int64_t n, T lambda, int warm) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    if (warm) {
+      x[j] = shrink(z[j], lambda);
+    } else {
+      z[j] = T(0);
+      x[j] = T(0);
+    }
+  }
+}
+
+// One workgroup: ||x - xref|| / ||xref|| into err (fixed order).
+template <typename T>
+__global__ __launch_bounds__(1024) void lb_err(const T* __restrict__ x, const T* __restrict__ xref, int64_t n,
+                                               double* err, const int* status) {
+  __shared__ double red[2][16];
+  if (status[0]) return;
+  double e2 = 0.0, r2 = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const double rf = (double)xref[j], d = (double)x[j] - rf;
+    e2 += d * d;
+    r2 += rf * rf;
+  }
+  e2 = wave_sum(e2);
+  r2 = wave_sum(r2);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = e2; red[1][threadIdx.x >> 6] = r2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double se = 0.0, sr = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { se += red[0][w]; sr += red[1][w]; }
+    *err = sr > 0.0 ? sqrt(se / sr) : sqrt(se);
+  }
+}
+
+// Power iteration: w_j = sum over workgroups (in order) of part[.][j], written over part[0][j]
+// (each j is read and written by one thread).
+template <typename T>
+__global__ void pw_sum(T* __restrict__ part, int G, int64_t n, int64_t nstride) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    T gj = T(0);
+    for (int q = 0; q < G; ++q) gj += part[(size_t)q * nstride + j];
+    part[j] = gj;
+  }
+}
+
+// est = <v, w> (||v|| = 1), then v = w / ||w||.
+template <typename T>
+__global__ __launch_bounds__(1024) void pw_finish(const T* __restrict__ w, int64_t n, T* __restrict__ v,
+                                                  double* est) {
+  __shared__ double red[2][16];
+  __shared__ double scale;
+  double vw = 0.0, ww = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const double wj = (double)w[j];
+    vw += (double)v[j] * wj;
+    ww += wj * wj;
+  }
+  vw = wave_sum(vw);
+  ww = wave_sum(ww);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = vw; red[1][threadIdx.x >> 6] = ww; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += red[0][k]; c += red[1][k]; }
+    *est = a;
+    scale = c > 0.0 ? 1.0 / sqrt(c) : 0.0;
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) v[j] = (T)((double)w[j] * scale);
+}
+
+// v_j = (1 + (j mod 7)/7) / ||.||
+template <typename T>
+__global__ __launch_bounds__(1024) void pw_start(T* v, int64_t n) {
+  __shared__ double red[16];
+  __shared__ double sc;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const double a = 1.0 + (double)(j % 7) / 7.0;
+    s += a * a;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    sc = 1.0 / sqrt(t);
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) v[j] = (T)((1.0 + (double)(j % 7) / 7.0) * sc);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <typename T, int V>
+static void* lb_pass_fn_v(int cpt) {
+  switch (cpt) {
+    case 1: return (void*)&lb_pass<T, V, 1>;
+    case 2: return (void*)&lb_pass<T, V, 2>;
+    case 4: return (void*)&lb_pass<T, V, 4>;
+    case 6: return (void*)&lb_pass<T, V, 6>;
+    case 8: return (void*)&lb_pass<T, V, 8>;
+    case 10: return (void*)&lb_pass<T, V, 10>;
+    case 12: return (void*)&lb_pass<T, V, 12>;
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+static void* lb_pass_fn(int vec, int cpt) {
+  return vec == 1 ? lb_pass_fn_v<T, 1>(cpt) : lb_pass_fn_v<T, kLbVec<T>>(cpt);
+}
+
+// vec: kLbVec<T> (A 16-byte aligned, ld a multiple of kLbVec) or 1.
+template <typename T>
+int lb_plan(int64_t n, int vec, int* cpt, size_t* lds, int* grid, int64_t* nstride) {
+  const int64_t nch = (n + vec - 1) / vec;
+  const int64_t need = (nch + kLbThreads - 1) / kLbThreads;
+  *cpt = 0;
+  for (int c : {1, 2, 4, 6, 8, 10, 12})
+    if (need <= c) { *cpt = c; break; }
+  if (n < 1 || !*cpt || (vec != 1 && vec != kLbVec<T>)) return 0;
+  *nstride = nch * vec;
+  *lds = (size_t)nch * vec * sizeof(T);
+  void* fn = lb_pass_fn<T>(vec, *cpt);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)*lds) != hipSuccess) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLbThreads, *lds) != hipSuccess || per_cu < 1)
+    return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  *grid = per_cu * cus;
+  return 1;
+}
+
+template <typename T>
+static hipError_t lb_pass_launch(const LbArgs<T>& a, const T* x, const T* b, hipStream_t s) {
+  void* fn = lb_pass_fn<T>(a.vec, a.cpt);
+  if (!fn) return hipErrorInvalidValue;
+  const T* Ap = a.A;
+  int64_t m = a.m, n = a.n, ld = a.ld;
+  T* part = a.part;
+  double* rpart = a.rpart;
+  const int* status = a.status;
+  void* args[] = {&Ap, &m, &n, &ld, &x, &b, &part, &rpart, &status};
+  return hipLaunchKernel(fn, dim3(a.G), dim3(kLbThreads), args, a.lds, s);
+}
+
+static int lb_update_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 1024 ? b : 1024);
+}
+
+template <typename T>
+hipError_t launch_lb(const LbArgs<T>& a, hipStream_t s) {
+  const int ub = lb_update_blocks(a.n);
+  hipLaunchKernelGGL(lb_init<T>, dim3(ub), dim3(256), 0, s, a.z, a.x, a.n, a.lambda, a.warm);
+  for (int64_t k = 0; k < a.K; ++k) {
+    hipError_t e = lb_pass_launch(a, a.x, a.b, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lb_update<T>, dim3(ub), dim3(256), 0, s, a.part, a.G, a.n, a.nstride, a.z, a.x, a.step,
+                       a.lambda, a.rpart, a.res_hist ? a.res_hist + k : nullptr, a.status, k);
+    if (a.xref && a.check_every > 0 && a.err_hist && (k + 1) % a.check_every == 0)
+      hipLaunchKernelGGL(lb_err<T>, dim3(1), dim3(1024), 0, s, a.x, a.xref, a.n,
+                         a.err_hist + (k + 1) / a.check_every - 1, a.status);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_power(const LbArgs<T>& a, int64_t iters, T* v, double* est, hipStream_t s) {
+  const int ub = lb_update_blocks(a.n);
+  hipLaunchKernelGGL(pw_start<T>, dim3(1), dim3(1024), 0, s, v, a.n);
+  for (int64_t it = 0; it < iters; ++it) {
+    hipError_t e = lb_pass_launch(a, v, (const T*)nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pw_sum<T>, dim3(ub), dim3(256), 0, s, a.part, a.G, a.n, a.nstride);
+    hipLaunchKernelGGL(pw_finish<T>, dim3(1), dim3(1024), 0, s, a.part, a.n, v, est);
+  }
+  return hipGetLastError();
+}
+
+template int lb_plan<float>(int64_t, int, int*, size_t*, int*, int64_t*);
+template int lb_plan<double>(int64_t, int, int*, size_t*, int*, int64_t*);
+template hipError_t launch_lb<float>(const LbArgs<float>&, hipStream_t);
+template hipError_t launch_lb<double>(const LbArgs<double>&, hipStream_t);
+template hipError_t launch_power<float>(const LbArgs<float>&, int64_t, float*, double*, hipStream_t);
+template hipError_t launch_power<double>(const LbArgs<double>&, int64_t, double*, double*, hipStream_t);
+
+}  // namespace rsk

@@ -375,6 +375,83 @@ def sample_stream(cdf: torch.Tensor, *, seed: int, K: int, eta: int, k0: int = 0
 
 
 # ---------------------------------------------------------------------------
+# Linearized Bregman (full-batch comparator) and sigma_max(A)^2
+# ---------------------------------------------------------------------------
+
+def _lb_workspace(A: torch.Tensor, workspace: Optional[torch.Tensor]) -> torch.Tensor:
+    d = dense_desc(A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_lb_dense(ctypes.byref(d), ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_lb_dense")
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = _workspace(nbytes.value, A.device)
+    return workspace
+
+
+def spectral_norm2(A: torch.Tensor, iters: int = 100, *, v: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None) -> float:
+    """sigma_max(A)^2 by power iteration on A^T A (on the device); ``v`` receives the last unit vector."""
+    d = dense_desc(A)
+    ws = _lb_workspace(A, workspace)
+    if v is None:
+        v = torch.empty(A.shape[1], dtype=A.dtype, device=A.device)
+    _dev(v, "v", A.dtype, A.shape[1])
+    est = torch.empty(1, dtype=torch.float64, device=A.device)
+    st = _lib().rsk_spectral_norm2_dense(ctypes.byref(d), int(iters), v.data_ptr(), est.data_ptr(), ws.data_ptr(),
+                                         ws.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_spectral_norm2_dense")
+    return float(est.item())
+
+
+@dataclass
+class LbResult:
+    x_star: torch.Tensor
+    x: torch.Tensor
+    status: Optional[int]
+    k_done: Optional[int]
+    err_hist: Optional[torch.Tensor]
+    res_hist: Optional[torch.Tensor]
+
+
+def lb_solve(A: torch.Tensor, b: torch.Tensor, *, lam: float, step: float, K: int,
+             x_star: Optional[torch.Tensor] = None, warm_start: bool = False, x_ref: Optional[torch.Tensor] = None,
+             check_every: int = 0, residuals: bool = False, workspace: Optional[torch.Tensor] = None,
+             check: bool = True) -> LbResult:
+    """K linearized Bregman iterations x* -= step A^T(Ax - b), x = S_lambda(x*), each reading A once."""
+    m, n = A.shape
+    dt = A.dtype
+    _dev(b, "b", dt, m)
+    if x_star is None:
+        if warm_start:
+            raise ValueError("warm_start needs x_star")
+        x_star = torch.empty(n, dtype=dt, device=A.device)
+    _dev(x_star, "x_star", dt, n)
+    x = torch.empty(n, dtype=dt, device=A.device)
+    status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
+    nh = (K // check_every) if (x_ref is not None and check_every > 0) else 0
+    err_hist = torch.full((max(nh, 1),), float("nan"), dtype=torch.float64, device=A.device) if nh else None
+    res_hist = torch.full((max(K, 1),), float("nan"), dtype=torch.float64, device=A.device) if residuals else None
+    p = _abi.RskLbParams(float(lam), float(step), int(K), 1 if warm_start else 0, _dev(x_ref, "x_ref", dt, n),
+                         int(check_every), _dev(err_hist, "err_hist"), _dev(res_hist, "res_hist"),
+                         status_dev.data_ptr())
+    d = dense_desc(A)
+    ws = _lb_workspace(A, workspace)
+    st = _lib().rsk_lb_solve_dense(ctypes.byref(d), b.data_ptr(), ctypes.byref(p), x_star.data_ptr(), x.data_ptr(),
+                                   ws.data_ptr(), ws.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_lb_solve_dense")
+    status = k_done = None
+    if check:
+        s = status_dev.cpu().tolist()
+        status, k_done = int(s[0]), int(s[1])
+        if status:
+            raise RskError(status, "rsk_lb_solve_dense (device)")
+    return LbResult(x_star, x, status, k_done, err_hist, None if res_hist is None else res_hist[:K])
+
+
+# ---------------------------------------------------------------------------
 # Batched independent systems
 # ---------------------------------------------------------------------------
 
