@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr"], default=None,
+    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb"], default=None,
                     help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
@@ -145,6 +145,13 @@ def main():
     from paper_2203_10838_amd import inputs, params, rsk
 
     dev = torch.device("cuda:0")
+    if args.only == "lb":
+        stream = torch.cuda.current_stream()
+        sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
+        b = torch.from_numpy(sysd["b"]).to(dev)
+        xhat = torch.from_numpy(sysd["xhat"]).to(dev)
+        print(json.dumps({"lb": lb_run(sysd["A"], b, xhat, dev, stream)}), flush=True)
+        return
     if args.only:
         stream = torch.cuda.current_stream()
         fn = {"batched": batched_run, "multirhs": multirhs_run, "adjoint": adjoint_run, "csr": csr_run}[args.only]
@@ -253,6 +260,7 @@ def main():
             log(f"[bench] sweep eta={e}: {sweep[-1]}")
         out["eta_sweep"] = sweep
         out["time_to_plateau"] = plateau_runs(solve, inputs, weights, xhat, dev, stream)
+        out["lb"] = lb_run(A, b, xhat, dev, stream)
 
     if not args.no_sweep:
         out["sampler"] = sampler_run(A, dev, stream)
@@ -524,6 +532,47 @@ def csr_run(dev, stream, K=20000):
            "GB/s": round(K * step_b / (ms * 1e-3) / 1e9, 3),
            "rel_err_at_K": float(res.err_hist.cpu().numpy()[-1]), "status": res.status_dev.cpu().tolist()}
     log(f"[bench] csr: {out}")
+    return out
+
+
+def lb_run(A, b, xhat, dev, stream, Kmax=800, C=5, K_rate=40):
+    """Full-batch comparator on the headline system: linearized Bregman with s = 1/sigma_max^2
+    (power iteration on the device, timed), its error plateau and the time to reach it, and the
+    HBM rate of one iteration (A read once: m n 4 bytes)."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    m, n = A.shape
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        r = fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return r, a0.elapsed_time(a1)
+
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    rsk.spectral_norm2(A, 2, workspace=ws)
+    s2, ms_power = timed(lambda: rsk.spectral_norm2(A, 100, workspace=ws))
+    step = 1.0 / s2
+    rsk.lb_solve(A, b, lam=LAM, step=step, K=2, workspace=ws)
+    _, ms_rate = timed(lambda: rsk.lb_solve(A, b, lam=LAM, step=step, K=K_rate, workspace=ws, check=False))
+    cal = rsk.lb_solve(A, b, lam=LAM, step=step, K=Kmax, x_ref=xhat, check_every=C, workspace=ws)
+    h = cal.err_hist.cpu().numpy()
+    plateau = float(np.median(h[int(len(h) * 0.8):]))
+    kstar = (int(np.argmax(h <= 1.05 * plateau)) + 1) * C
+    _, ms_plateau = timed(lambda: rsk.lb_solve(A, b, lam=LAM, step=step, K=kstar, workspace=ws, check=False))
+    it_bytes = m * n * 4
+    out = {"workload": f"linearized Bregman, dense {m}x{n} float32, lambda={LAM}, s=1/sigma_max^2",
+           "sigma_max2": s2, "ms_power_100": round(ms_power, 3),
+           "us_per_iteration": round(ms_rate * 1e3 / K_rate, 2),
+           "GB/s": round(K_rate * it_bytes / (ms_rate * 1e-3) / 1e9, 1),
+           "frac_hbm_peak": round(K_rate * it_bytes / (ms_rate * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+           "plateau_rel_err": plateau, "iterations_to_plateau": kstar, "ms_to_plateau": round(ms_plateau, 3),
+           "max_iterations_run": Kmax}
+    log(f"[bench] lb: {out}")
     return out
 
 

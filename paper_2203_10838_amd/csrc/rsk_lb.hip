@@ -42,52 +42,64 @@ __global__ __launch_bounds__(kLbThreads) void lb_pass(const T* __restrict__ A, i
   }
   __syncthreads();
   const int64_t i0 = (int64_t)g * m / G, i1 = (int64_t)(g + 1) * m / G;
-  V acc[CPT], cur[CPT], nxt[CPT];
+  V acc[CPT], ra[CPT], rb[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[c].v[e] = T(0);
+  // Which loaded elements lie in the row (the rest, past n or past the last chunk, is masked
+  // out of the dot; their products in acc land past n and are never read).
+  unsigned long long inrow = 0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t q = tid + (int64_t)kLbThreads * c;
+      if (q < nch && q * VEC + e < n) inrow |= 1ull << (c * VEC + e);
+    }
+  // Raw 16-byte (or element) loads of row i, the chunk index clamped into the row: no select
+  // touches the loaded registers before their use, so the loads stay in flight.
   auto load_row = [&](int64_t i, V (&dst)[CPT]) {
     const T* rowp = A + i * ld;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int64_t q = tid + (int64_t)kLbThreads * c;
-      dst[c] = q < nch ? load_vec<T, VEC>(rowp, q * VEC, n) : V{};
+      dst[c] = *reinterpret_cast<const V*>(rowp + (q < nch ? q : nch - 1) * VEC);
     }
   };
   double rr = 0.0;
-  if (i0 < i1) load_row(i0, cur);
-  for (int64_t i = i0; i < i1; ++i) {
-    const bool more = i + 1 < i1;
-    if (more) load_row(i + 1, nxt);
+  auto row_step = [&](int64_t i, const V (&cur)[CPT]) {
     const T bi = b ? b[i] : T(0);
     T dot = T(0);
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int64_t q = tid + (int64_t)kLbThreads * c;
-      if (q < nch) {
-        const V xv = xs[q];
+      const V xv = xs[q < nch ? q : nch - 1];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) dot += cur[c].v[e] * xv.v[e];
-      }
+      for (int e = 0; e < VEC; ++e) dot += ((inrow >> (c * VEC + e)) & 1 ? cur[c].v[e] : T(0)) * xv.v[e];
     }
     dot = lane_sum(dot, 64);
     const int par = (int)(i & 1);
     if (lane == 0) red[par][wave] = dot;
     __syncthreads();  // red[par] is rewritten two rows later, after the next barrier
-    T s = T(0);
+    T sum = T(0);
 #pragma unroll
-    for (int w = 0; w < kLbWaves; ++w) s += red[par][w];
-    const T r = s - bi;
+    for (int w = 0; w < kLbWaves; ++w) sum += red[par][w];
+    const T r = sum - bi;
     rr += (double)r * (double)r;
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[c].v[e] += r * cur[c].v[e];
-    if (more) {
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) cur[c] = nxt[c];
-    }
+  };
+  // Rows in pairs through two register buffers: row i+1 (i+2) loads while row i (i+1) is
+  // reduced. Past the block's last row the clamped index reloads that row (never used).
+  if (i0 < i1) load_row(i0, ra);
+  for (int64_t i = i0; i < i1; i += 2) {
+    load_row(i + 1 < i1 ? i + 1 : i1 - 1, rb);
+    row_step(i, ra);
+    load_row(i + 2 < i1 ? i + 2 : i1 - 1, ra);
+    if (i + 1 < i1) row_step(i + 1, rb);
   }
   T* pg = part + (size_t)g * nch * VEC;
 #pragma unroll
