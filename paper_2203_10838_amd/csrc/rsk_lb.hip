@@ -9,8 +9,8 @@
 // chunks in registers (the next row's chunks are already in flight), a
 // fixed-order block reduction (DPP sums in each wave, then the waves in
 // order), r_i = dot - b_i, and the row's contribution r_i a_i to the partial.
-// lb_update sums the workgroups' partials in workgroup order and applies the
-// step with S_lambda fused. All sums have fixed orders: runs are bitwise
+// lb_reduce sums the workgroups' partials in a fixed segmented order and applies
+// the step with S_lambda fused. All sums have fixed orders: runs are bitwise
 // reproducible.
 #include "rsk_dense_run.hpp"
 
@@ -22,7 +22,7 @@ constexpr int kLbWaves = kLbThreads / 64;
 
 }  // namespace
 
-template <typename T, int VEC, int CPT>
+template <typename T, int VEC, int CPT, int NB>
 __global__ __launch_bounds__(kLbThreads) void lb_pass(const T* __restrict__ A, int64_t m, int64_t n, int64_t ld,
                                                       const T* __restrict__ x, const T* __restrict__ b,
                                                       T* __restrict__ part, double* __restrict__ rpart,
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kLbThreads) void lb_pass(const T* __restrict__ A, i
   }
   __syncthreads();
   const int64_t i0 = (int64_t)g * m / G, i1 = (int64_t)(g + 1) * m / G;
-  V acc[CPT], ra[CPT], rb[CPT];
+  V acc[CPT], buf[NB][CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
@@ -92,14 +92,19 @@ __global__ __launch_bounds__(kLbThreads) void lb_pass(const T* __restrict__ A, i
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[c].v[e] += r * cur[c].v[e];
   };
-  // Rows in pairs through two register buffers: row i+1 (i+2) loads while row i (i+1) is
-  // reduced. Past the block's last row the clamped index reloads that row (never used).
-  if (i0 < i1) load_row(i0, ra);
-  for (int64_t i = i0; i < i1; i += 2) {
-    load_row(i + 1 < i1 ? i + 1 : i1 - 1, rb);
-    row_step(i, ra);
-    load_row(i + 2 < i1 ? i + 2 : i1 - 1, ra);
-    if (i + 1 < i1) row_step(i + 1, rb);
+  // Rows through NB register buffers used in turn: while row i is reduced, rows i+1 .. i+NB-1
+  // are in flight. Past the block's last row the clamped index reloads that row (never used).
+  if (i0 < i1) {
+#pragma unroll
+    for (int u = 0; u < NB - 1; ++u) load_row(i0 + u < i1 ? i0 + u : i1 - 1, buf[u]);
+    for (int64_t i = i0; i < i1; i += NB) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int64_t ahead = i + u + NB - 1;
+        load_row(ahead < i1 ? ahead : i1 - 1, buf[(u + NB - 1) % NB]);
+        if (i + u < i1) row_step(i + u, buf[u]);
+      }
+    }
   }
   T* pg = part + (size_t)g * nch * VEC;
 #pragma unroll
@@ -110,28 +115,70 @@ __global__ __launch_bounds__(kLbThreads) void lb_pass(const T* __restrict__ A, i
   if (tid == 0) rpart[g] = rr;  // every thread of the block holds the same sum of r_i^2
 }
 
-// g_j = sum over workgroups (in order) of part[.][j]; z_j -= s g_j, x_j = S_lambda(z_j).
-template <typename T>
-__global__ void lb_update(const T* __restrict__ part, int G, int64_t n, int64_t nstride, T* __restrict__ z,
-                          T* __restrict__ x, T step, T lambda, const double* __restrict__ rpart,
-                          double* res_out, int* status, int64_t k) {
-  if (status[0]) return;
-  int bad = 0;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    T gj = T(0);
-    for (int q = 0; q < G; ++q) gj += part[(size_t)q * nstride + j];
-    const T zj = z[j] - step * gj;
-    z[j] = zj;
-    x[j] = shrink(zj, lambda);
-    bad |= !isfinite(zj);
+// g_j = sum over the workgroups' partials part[q][j], in a fixed order: kSumSeg segments of
+// consecutive workgroups, each summed in order, then the segment sums in order. A block
+// covers kSumCols chunks of columns; all of its partial loads are independent.
+//   mode 0 (LB): x*_j -= step g_j, x_j = S_lambda(x*_j); residual norm and step count.
+//   mode 1 (power iteration): w_j = g_j written over part[0][j] (read by this thread only).
+constexpr int kSumSeg = 16, kSumCols = 16;
+template <typename T, int VEC>
+__global__ __launch_bounds__(kSumSeg * kSumCols) void lb_reduce(T* __restrict__ part, int G, int64_t n,
+                                                                int64_t nstride, int mode, T* __restrict__ z,
+                                                                T* __restrict__ x, T step, T lambda,
+                                                                const double* __restrict__ rpart, double* res_out,
+                                                                int* status, int64_t k) {
+  using V = Vec<T, VEC>;
+  __shared__ V red[kSumSeg][kSumCols];
+  if (status && status[0]) return;
+  const int col = threadIdx.x % kSumCols, seg = threadIdx.x / kSumCols;
+  const int64_t nch = (n + VEC - 1) / VEC;
+  const int64_t qc = blockIdx.x * (int64_t)kSumCols + col;
+  const int g0 = seg * G / kSumSeg, g1 = (seg + 1) * G / kSumSeg;
+  V acc;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc.v[e] = T(0);
+  if (qc < nch) {
+    const T* p = part + qc * VEC;
+#pragma unroll 8
+    for (int q = g0; q < g1; ++q) {
+      const V t = *reinterpret_cast<const V*>(p + (size_t)q * nstride);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc.v[e] += t.v[e];
+    }
   }
-  if (bad) set_status(status, ST_NONFINITE);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    status[1] = (int)(k + 1);  // steps started; the nonfinite check marks a failed one
-    if (res_out) {
-      double s = 0.0;
-      for (int q = 0; q < G; ++q) s += rpart[q];
-      *res_out = sqrt(s);
+  red[seg][col] = acc;
+  __syncthreads();
+  int bad = 0;
+  if (seg == 0 && qc < nch) {
+    V t = red[0][col];
+#pragma unroll
+    for (int sg = 1; sg < kSumSeg; ++sg)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) t.v[e] += red[sg][col].v[e];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t j = qc * VEC + e;
+      if (j >= n) break;
+      if (mode == 0) {
+        const T zj = z[j] - step * t.v[e];
+        z[j] = zj;
+        x[j] = shrink(zj, lambda);
+        bad |= !isfinite(zj);
+      } else {
+        part[j] = t.v[e];
+      }
+    }
+  }
+  if (mode == 0) {
+    if (bad) set_status(status, ST_NONFINITE);
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+      double r2 = 0.0;
+      for (int q = threadIdx.x; q < G; q += 64) r2 += rpart[q];
+      r2 = wave_sum(r2);
+      if (threadIdx.x == 0) {
+        status[1] = (int)(k + 1);  // iterations started; the nonfinite check marks a failed one
+        if (res_out) *res_out = sqrt(r2);
+      }
     }
   }
 }
@@ -169,17 +216,6 @@ __global__ __launch_bounds__(1024) void lb_err(const T* __restrict__ x, const T*
     double se = 0.0, sr = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { se += red[0][w]; sr += red[1][w]; }
     *err = sr > 0.0 ? sqrt(se / sr) : sqrt(se);
-  }
-}
-
-// Power iteration: w_j = sum over workgroups (in order) of part[.][j], written over part[0][j]
-// (each j is read and written by one thread).
-template <typename T>
-__global__ void pw_sum(T* __restrict__ part, int G, int64_t n, int64_t nstride) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    T gj = T(0);
-    for (int q = 0; q < G; ++q) gj += part[(size_t)q * nstride + j];
-    part[j] = gj;
   }
 }
 
@@ -235,16 +271,20 @@ __global__ __launch_bounds__(1024) void pw_start(T* v, int64_t n) {
 // host side
 // ---------------------------------------------------------------------------
 
+// Three row buffers where they fit in the registers of two waves per SIMD, else two.
+template <typename T, int V, int CPT>
+constexpr int kLbBuffers = CPT * V * (int)sizeof(T) <= 160 ? 3 : 2;
+
 template <typename T, int V>
 static void* lb_pass_fn_v(int cpt) {
   switch (cpt) {
-    case 1: return (void*)&lb_pass<T, V, 1>;
-    case 2: return (void*)&lb_pass<T, V, 2>;
-    case 4: return (void*)&lb_pass<T, V, 4>;
-    case 6: return (void*)&lb_pass<T, V, 6>;
-    case 8: return (void*)&lb_pass<T, V, 8>;
-    case 10: return (void*)&lb_pass<T, V, 10>;
-    case 12: return (void*)&lb_pass<T, V, 12>;
+    case 1: return (void*)&lb_pass<T, V, 1, kLbBuffers<T, V, 1>>;
+    case 2: return (void*)&lb_pass<T, V, 2, kLbBuffers<T, V, 2>>;
+    case 4: return (void*)&lb_pass<T, V, 4, kLbBuffers<T, V, 4>>;
+    case 6: return (void*)&lb_pass<T, V, 6, kLbBuffers<T, V, 6>>;
+    case 8: return (void*)&lb_pass<T, V, 8, kLbBuffers<T, V, 8>>;
+    case 10: return (void*)&lb_pass<T, V, 10, kLbBuffers<T, V, 10>>;
+    case 12: return (void*)&lb_pass<T, V, 12, kLbBuffers<T, V, 12>>;
     default: return nullptr;
   }
 }
@@ -290,20 +330,31 @@ static hipError_t lb_pass_launch(const LbArgs<T>& a, const T* x, const T* b, hip
   return hipLaunchKernel(fn, dim3(a.G), dim3(kLbThreads), args, a.lds, s);
 }
 
-static int lb_update_blocks(int64_t n) {
-  const int64_t b = (n + 255) / 256;
-  return (int)(b < 1024 ? b : 1024);
+template <typename T>
+static void lb_reduce_launch(const LbArgs<T>& a, int mode, int64_t k, hipStream_t s) {
+  const int64_t nch = (a.n + a.vec - 1) / a.vec;
+  const dim3 grid((unsigned)((nch + kSumCols - 1) / kSumCols)), block(kSumSeg * kSumCols);
+  T* z = mode == 0 ? a.z : nullptr;
+  T* x = mode == 0 ? a.x : nullptr;
+  int* st = mode == 0 ? a.status : nullptr;
+  double* res = mode == 0 && a.res_hist ? a.res_hist + k : nullptr;
+  if (a.vec == 1)
+    hipLaunchKernelGGL((lb_reduce<T, 1>), grid, block, 0, s, a.part, a.G, a.n, a.nstride, mode, z, x, a.step,
+                       a.lambda, a.rpart, res, st, k);
+  else
+    hipLaunchKernelGGL((lb_reduce<T, kLbVec<T>>), grid, block, 0, s, a.part, a.G, a.n, a.nstride, mode, z, x,
+                       a.step, a.lambda, a.rpart, res, st, k);
 }
 
 template <typename T>
 hipError_t launch_lb(const LbArgs<T>& a, hipStream_t s) {
-  const int ub = lb_update_blocks(a.n);
+  const int64_t ib = (a.n + 255) / 256;
+  const int ub = (int)(ib < 1024 ? ib : 1024);
   hipLaunchKernelGGL(lb_init<T>, dim3(ub), dim3(256), 0, s, a.z, a.x, a.n, a.lambda, a.warm);
   for (int64_t k = 0; k < a.K; ++k) {
     hipError_t e = lb_pass_launch(a, a.x, a.b, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(lb_update<T>, dim3(ub), dim3(256), 0, s, a.part, a.G, a.n, a.nstride, a.z, a.x, a.step,
-                       a.lambda, a.rpart, a.res_hist ? a.res_hist + k : nullptr, a.status, k);
+    lb_reduce_launch(a, 0, k, s);
     if (a.xref && a.check_every > 0 && a.err_hist && (k + 1) % a.check_every == 0)
       hipLaunchKernelGGL(lb_err<T>, dim3(1), dim3(1024), 0, s, a.x, a.xref, a.n,
                          a.err_hist + (k + 1) / a.check_every - 1, a.status);
@@ -313,12 +364,11 @@ hipError_t launch_lb(const LbArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_power(const LbArgs<T>& a, int64_t iters, T* v, double* est, hipStream_t s) {
-  const int ub = lb_update_blocks(a.n);
   hipLaunchKernelGGL(pw_start<T>, dim3(1), dim3(1024), 0, s, v, a.n);
   for (int64_t it = 0; it < iters; ++it) {
     hipError_t e = lb_pass_launch(a, v, (const T*)nullptr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pw_sum<T>, dim3(ub), dim3(256), 0, s, a.part, a.G, a.n, a.nstride);
+    lb_reduce_launch(a, 1, it, s);
     hipLaunchKernelGGL(pw_finish<T>, dim3(1), dim3(1024), 0, s, a.part, a.n, v, est);
   }
   return hipGetLastError();
