@@ -18,6 +18,9 @@ What is here (each function cites the passage it follows):
   stored (no checkpointing).
 * ``lb_dense`` / ``power_ata`` -- the full-batch linearized Bregman comparator
   (the remark on its rate in Sec. 4) and sigma_max(A)^2 by power iteration;
+* ``bsk_dense`` -- the block sparse Kaczmarz iteration, eq. (bsk) of Sec. 1.1,
+  on the rows an explicit index stream names, with ||A_tau||_2^2 taken as the
+  largest eigenvalue of the block's Gram matrix (numpy);
 * ``philox4x32_10``, ``sampling_cdf``, ``sample_stream`` -- the row sampler
   (p_i proportional to ||a_i||^2, Sec. 1.1) driven by the counter-based
   generator Philox4x32-10 of Salmon et al. (SC'11) and an inverse-CDF search;
@@ -358,4 +361,45 @@ def power_ata(A, iters, v0=None):
     if st:
         raise OracleError(st, "power_ata")
     return float(est[0])
+
+
+def bsk_dense(A, b, lam, w, K, idx, eta, *, off=0, z0=None, check_every=0, xref=None):
+    """Block sparse Kaczmarz, eq. (bsk) (Sec. 1.1): per step k the rows tau_k = idx[off + k eta ..
+    off + (k+1) eta) form A_tau (repeated indices give repeated rows), and
+
+        x*_{k+1} = x*_k - w A_tau^T (A_tau x_k - b_tau) / ||A_tau||_2^2,   x_{k+1} = S_lambda(x*_{k+1}),
+
+    from x*_0 = 0 (or z0), x_0 = S_lambda(x*_0). ||A_tau||_2^2 is the largest eigenvalue of
+    A_tau A_tau^T. Returns dict(z, x, s2 (per step), hist).
+    """
+    A = _f64(A)
+    b = _f64(b)
+    idx = np.asarray(idx, dtype=np.int64)
+    m, n = A.shape
+    if eta < 1 or K < 0 or lam < 0 or not (w > 0):
+        raise OracleError(INVALID, "bsk_dense")
+    if K > 0 and (idx.size < off + K * eta or idx[off:off + K * eta].min() < 0
+                  or idx[off:off + K * eta].max() >= m):
+        raise OracleError(INDEX_RANGE, "bsk_dense")
+    z = np.zeros(n) if z0 is None else _f64(z0).copy()
+    x = soft_threshold(z, lam)
+    s2 = np.zeros(int(K))
+    nh = (int(K) // check_every) if (xref is not None and check_every > 0) else 0
+    hist = np.full(nh, np.nan)
+    xr = None if xref is None else _f64(xref)
+    for k in range(int(K)):
+        tau = idx[off + k * eta: off + (k + 1) * eta]
+        At = A[tau]
+        r = At @ x - b[tau]
+        s2[k] = float(np.linalg.eigvalsh(At @ At.T)[-1])
+        if not s2[k] > 0:
+            raise OracleError(ZERO_ROW, "bsk_dense")
+        z = z - (w / s2[k]) * (At.T @ r)
+        x = soft_threshold(z, lam)
+        if not np.all(np.isfinite(z)):
+            raise OracleError(NONFINITE, "bsk_dense")
+        if nh and (k + 1) % check_every == 0:
+            nr = np.linalg.norm(xr)
+            hist[(k + 1) // check_every - 1] = np.linalg.norm(x - xr) / (nr if nr > 0 else 1.0)
+    return {"z": z, "x": x, "s2": s2, "hist": hist}
 

@@ -511,3 +511,64 @@ def test_lb_lambda0_underdetermined_gives_min_norm_solution():
     s2 = float(np.linalg.svd(A, compute_uv=False)[0] ** 2)
     r = oracle.lb_dense(A, b, 0.0, 1.0 / s2, 6000)
     assert np.linalg.norm(r["x"] - np.linalg.pinv(A) @ b) <= 1e-8 * np.linalg.norm(np.linalg.pinv(A) @ b)
+
+
+# ---------------------------------------------------------------------------
+# Block sparse Kaczmarz, eq. (bsk)
+# ---------------------------------------------------------------------------
+
+def test_bsk_all_rows_is_linearized_bregman():
+    """tau_k = every row once (eta = m): eq. (bsk) is the full-batch step w A^T(Ax-b)/||A||_2^2,
+    checked against the C linearized Bregman loop with step w / sigma_max^2 from the SVD."""
+    rng = np.random.default_rng(31)
+    m, n, K, w, lam = 30, 50, 25, 1.5, 0.4
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    idx = np.tile(np.arange(m), K)
+    got = oracle.bsk_dense(A, b, lam, w, K, idx, m)
+    s2 = np.linalg.svd(A, compute_uv=False)[0] ** 2
+    ref = oracle.lb_dense(A, b, lam, w / s2, K)
+    assert np.allclose(got["s2"], s2, rtol=1e-12)
+    assert np.allclose(got["z"], ref["z"], rtol=1e-10, atol=1e-12)
+
+
+def test_bsk_single_row_is_relaxed_rsk():
+    """eta = 1: ||a_i||_2^2 is the row norm and the step is relaxed RSK (eq. (rsk) with weight w),
+    checked against the C RSKA loop at eta = 1, alpha = w."""
+    c = inputs.dense_system(40, 25, 4, dtype="f64", seed=32)
+    K = 200
+    idx = inputs.index_stream(inputs.row_sampling_weights(c["A"]), K, 1, 33)
+    got = oracle.bsk_dense(c["A"], c["b"], 0.3, 0.7, K, idx, 1)
+    ref = oracle.rska_dense(c["A"], c["b"], 0.3, 1, 0.7, K, idx)
+    assert np.allclose(got["z"], ref["z"], rtol=1e-11, atol=1e-13)
+    assert np.allclose(got["s2"], np.sum(c["A"][idx[:K]] ** 2, axis=1), rtol=1e-12)
+
+
+def test_bsk_block_norm_closed_forms():
+    """Rows orthogonal with norms c_i: ||A_tau||^2 = max c_i^2 (not the Frobenius sum); a row
+    repeated r times in the block: ||A_tau||^2 = r ||a||^2."""
+    n = 12
+    Q, _ = np.linalg.qr(np.random.default_rng(34).standard_normal((n, n)))
+    cs = np.array([1.0, 3.0, 0.5, 2.0])
+    A = (Q[:4] * cs[:, None])
+    b = np.zeros(4)
+    got = oracle.bsk_dense(A, b, 0.0, 1.0, 1, np.array([0, 1, 2, 3]), 4)
+    assert got["s2"][0] == pytest.approx(9.0, rel=1e-12)
+    got = oracle.bsk_dense(A, b, 0.0, 1.0, 1, np.array([2, 2, 2, 0]), 4)
+    # rows 2 (norm 0.5, three times) and 0 (norm 1), orthogonal: max(3 * 0.25, 1)
+    assert got["s2"][0] == pytest.approx(1.0, rel=1e-12)
+    got = oracle.bsk_dense(A, b, 0.0, 1.0, 1, np.array([1, 1, 1]), 3)
+    assert got["s2"][0] == pytest.approx(27.0, rel=1e-12)
+
+
+def test_bsk_consistent_limit_matches_linearized_bregman_limit():
+    """Consistent system with sparse x_hat: block steps of eta = 8 sampled rows converge to the
+    same lambda-regularised solution as the full-batch method."""
+    c = inputs.dense_system(120, 60, 5, dtype="f64", seed=35)
+    K, eta, lam = 6000, 8, 1.0
+    idx = inputs.index_stream(inputs.row_sampling_weights(c["A"]), K, eta, 36)
+    got = oracle.bsk_dense(c["A"], c["b"], lam, 1.0, K, idx, eta)
+    s2 = np.linalg.svd(c["A"], compute_uv=False)[0] ** 2
+    lb = oracle.lb_dense(c["A"], c["b"], lam, 1.0 / s2, 6000)
+    assert np.linalg.norm(c["A"] @ got["x"] - c["b"]) <= 1e-8 * np.linalg.norm(c["b"])
+    assert np.allclose(got["x"], lb["x"], atol=1e-7)
