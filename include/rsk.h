@@ -186,6 +186,26 @@ int32_t rsk_lb_solve_dense(const rsk_dense *A, const void *b, const rsk_lb_param
 int32_t rsk_spectral_norm2_dense(const rsk_dense *A, int64_t iters, void *v, double *est, void *workspace,
                                  size_t ws_bytes, void *stream);
 
+/*
+ * Block sparse Kaczmarz, eq. (bsk) (Sec. 1.1): per step the eta rows tau_k of
+ * the index stream form A_tau (a repeated index is a repeated row) and
+ *   x*_{k+1} = x*_k - w A_tau^T (A_tau x_k - b_tau) / ||A_tau||_2^2,
+ *   x_{k+1} = S_lambda(x*_{k+1}),
+ * with w = p->alpha. ||A_tau||_2^2 is the largest eigenvalue of the block's
+ * Gram matrix A_tau A_tau^T, computed in double to rounding (Householder
+ * tridiagonalisation, then Sturm-count bisection). Takes the rsk_params of
+ * the RSKA solves: lambda, eta (1 <= eta <= 64), alpha (= w), K,
+ * index_stream, stream_offset, warm_start, x_ref / check_every / err_hist,
+ * status_dev; alpha_k, y_out and tol must be null/0, rownorm2, grid and kernel
+ * are ignored. block_norm2: nullable device double[K], ||A_tau_k||_2^2 of
+ * every step. Device status: RSK_ERR_INDEX_RANGE (stream index outside
+ * [0, m)), RSK_ERR_ZERO_ROW (a block of zero rows), RSK_ERR_NONFINITE.
+ * All sums run in fixed orders (bitwise reproducible).
+ */
+int32_t rsk_workspace_size_bsk_dense(const rsk_dense *A, const rsk_params *p, size_t *bytes);
+int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
+                            double *block_norm2, void *workspace, size_t ws_bytes, void *stream);
+
 /* Version of this ABI (RSK_ABI_VERSION). */
 int32_t rsk_abi_version(void);
 

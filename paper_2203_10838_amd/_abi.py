@@ -68,6 +68,10 @@ SIGNATURES = {
     "rsk_lb_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskLbParams), c_vp, c_vp, c_vp, c_sz,
                                    c_vp]),
     "rsk_spectral_norm2_dense": (c_i32, [ctypes.POINTER(RskDense), c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "rsk_workspace_size_bsk_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(RskParams),
+                                             ctypes.POINTER(c_sz)]),
+    "rsk_bsk_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp, c_vp,
+                                    c_vp, c_sz, c_vp]),
     "rsk_workspace_size_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_batched": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),

@@ -441,6 +441,71 @@ int32_t lb_solve_t(const rsk_dense* A, const void* b, const rsk_lb_params* p, vo
   return rsk::launch_lb<T>(a, s) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
 }
 
+struct BskLayout {
+  int Gb, vec;
+  size_t bytes, offPart, offSums, offCoef;
+};
+
+int32_t check_bsk(const rsk_dense* A, const rsk_params* p) {
+  if (!p || !p->status_dev) return RSK_ERR_INVALID_ARG;
+  if (p->eta < 1 || p->K < 0 || p->K >= (int64_t(1) << 31) || p->stream_offset < 0) return RSK_ERR_INVALID_ARG;
+  if (!(p->lambda >= 0.0) || !isfinite(p->lambda) || !finite_pos(p->alpha)) return RSK_ERR_INVALID_ARG;
+  if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
+  if (p->check_every < 0 || (p->x_ref && p->check_every > 0 && !p->err_hist)) return RSK_ERR_INVALID_ARG;
+  if (p->alpha_k || p->y_out || p->tol != 0.0) return RSK_ERR_UNSUPPORTED;
+  if (p->eta > rsk::kBskMaxEta || A->m > INT32_MAX) return RSK_ERR_UNSUPPORTED;
+  return RSK_OK;
+}
+
+template <typename T>
+int32_t bsk_layout(const rsk_dense* A, const rsk_params* p, BskLayout* L) {
+  constexpr int V = rsk::kLbVec<T>;
+  L->vec = (((uintptr_t)A->val) % 16 == 0 && A->ld % V == 0) ? V : 1;
+  size_t pb = 0;
+  if (!rsk::bsk_plan<T>(A->n, p->eta, &L->Gb, &pb)) return RSK_ERR_UNSUPPORTED;
+  const size_t cnt = (size_t)p->eta + (size_t)p->eta * p->eta;
+  L->offPart = 0;
+  L->offSums = align256(pb);
+  L->offCoef = L->offSums + align256(cnt * sizeof(double));
+  L->bytes = L->offCoef + align256((size_t)p->eta * sizeof(T));
+  return RSK_OK;
+}
+
+template <typename T>
+int32_t bsk_solve_t(const rsk_dense* A, const void* b, const rsk_params* p, void* x_star, void* x, double* norm2,
+                    void* ws, size_t ws_bytes, hipStream_t s) {
+  BskLayout L;
+  int32_t st = bsk_layout<T>(A, p, &L);
+  if (st) return st;
+  if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  rsk::BskArgs<T> a{};
+  a.A = (const T*)A->val;
+  a.m = A->m;
+  a.n = A->n;
+  a.ld = A->ld;
+  a.b = (const T*)b;
+  a.tau = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
+  a.eta = p->eta;
+  a.K = p->K;
+  a.w = p->alpha;
+  a.lambda = (T)p->lambda;
+  a.z = (T*)x_star;
+  a.x = (T*)x;
+  a.warm = p->warm_start ? 1 : 0;
+  a.xref = (const T*)p->x_ref;
+  a.check_every = p->check_every;
+  a.err_hist = p->err_hist;
+  a.norm2_hist = norm2;
+  a.status = p->status_dev;
+  a.part = (T*)((char*)ws + L.offPart);
+  a.sums = (double*)((char*)ws + L.offSums);
+  a.coef = (T*)((char*)ws + L.offCoef);
+  a.Gb = L.Gb;
+  a.vec = L.vec;
+  if (rsk::launch_zero_status(p->status_dev, s) != hipSuccess) return RSK_ERR_HIP;
+  return rsk::launch_bsk<T>(a, s) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -686,6 +751,31 @@ int32_t rsk_spectral_norm2_dense(const rsk_dense* A, int64_t iters, void* v, dou
   else
     e = rsk::launch_power<float>(lb_args<float>(A, L, workspace), iters, (float*)v, est, (hipStream_t)stream);
   return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_workspace_size_bsk_dense(const rsk_dense* A, const rsk_params* p, size_t* bytes) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!bytes) return RSK_ERR_INVALID_ARG;
+  st = check_bsk(A, p);
+  if (st) return st;
+  BskLayout L;
+  st = A->dtype == RSK_F64 ? bsk_layout<double>(A, p, &L) : bsk_layout<float>(A, p, &L);
+  if (st) return st;
+  *bytes = L.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_bsk_solve_dense(const rsk_dense* A, const void* b, const rsk_params* p, void* x_star, void* x,
+                            double* block_norm2, void* workspace, size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  st = check_bsk(A, p);
+  if (st) return st;
+  if (!b || !x_star || !x) return RSK_ERR_INVALID_ARG;
+  return A->dtype == RSK_F64
+      ? bsk_solve_t<double>(A, b, p, x_star, x, block_norm2, workspace, ws_bytes, (hipStream_t)stream)
+      : bsk_solve_t<float>(A, b, p, x_star, x, block_norm2, workspace, ws_bytes, (hipStream_t)stream);
 }
 
 int32_t rsk_abi_version(void) { return RSK_ABI_VERSION; }

@@ -451,6 +451,60 @@ def lb_solve(A: torch.Tensor, b: torch.Tensor, *, lam: float, step: float, K: in
     return LbResult(x_star, x, status, k_done, err_hist, None if res_hist is None else res_hist[:K])
 
 
+@dataclass
+class BskResult:
+    x_star: torch.Tensor
+    x: torch.Tensor
+    status: Optional[int]
+    k_done: Optional[int]
+    err_hist: Optional[torch.Tensor]
+    block_norm2: Optional[torch.Tensor]
+
+
+def bsk_solve(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, w: float, K: int,
+              index_stream: torch.Tensor, stream_offset: int = 0, x_star: Optional[torch.Tensor] = None,
+              warm_start: bool = False, x_ref: Optional[torch.Tensor] = None, check_every: int = 0,
+              block_norms: bool = False, workspace: Optional[torch.Tensor] = None, check: bool = True) -> BskResult:
+    """K block sparse Kaczmarz steps, eq. (bsk): x* -= w A_tau^T(A_tau x - b_tau)/||A_tau||_2^2, x = S_lambda(x*)."""
+    m, n = A.shape
+    dt = A.dtype
+    _dev(b, "b", dt, m)
+    if x_star is None:
+        if warm_start:
+            raise ValueError("warm_start needs x_star")
+        x_star = torch.empty(n, dtype=dt, device=A.device)
+    _dev(x_star, "x_star", dt, n)
+    x = torch.empty(n, dtype=dt, device=A.device)
+    status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
+    nh = (K // check_every) if (x_ref is not None and check_every > 0) else 0
+    err_hist = torch.full((max(nh, 1),), float("nan"), dtype=torch.float64, device=A.device) if nh else None
+    norms = torch.full((max(K, 1),), float("nan"), dtype=torch.float64, device=A.device) if block_norms else None
+    if K > 0:
+        _dev(index_stream, "index_stream", torch.int32, stream_offset + K * eta)
+    p = _abi.RskParams(float(lam), int(eta), float(w), None, int(K),
+                       _dev(index_stream, "index_stream") if index_stream is not None else None, int(stream_offset),
+                       None, 1 if warm_start else 0, _dev(x_ref, "x_ref", dt, n), int(check_every), 0.0,
+                       _dev(err_hist, "err_hist"), None, status_dev.data_ptr(), 0, 0)
+    d = dense_desc(A)
+    nbytes = ctypes.c_size_t(0)
+    st = _lib().rsk_workspace_size_bsk_dense(ctypes.byref(d), ctypes.byref(p), ctypes.byref(nbytes))
+    if st:
+        raise RskError(st, "rsk_workspace_size_bsk_dense")
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = _workspace(nbytes.value, A.device)
+    st = _lib().rsk_bsk_solve_dense(ctypes.byref(d), b.data_ptr(), ctypes.byref(p), x_star.data_ptr(), x.data_ptr(),
+                                    _dev(norms, "block_norm2"), workspace.data_ptr(), workspace.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_bsk_solve_dense")
+    status = k_done = None
+    if check:
+        s_ = status_dev.cpu().tolist()
+        status, k_done = int(s_[0]), int(s_[1])
+        if status:
+            raise RskError(status, "rsk_bsk_solve_dense (device)")
+    return BskResult(x_star, x, status, k_done, err_hist, None if norms is None else norms[:K])
+
+
 # ---------------------------------------------------------------------------
 # Batched independent systems
 # ---------------------------------------------------------------------------
