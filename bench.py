@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb"], default=None,
+    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb", "bsk"], default=None,
                     help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
@@ -145,12 +145,16 @@ def main():
     from paper_2203_10838_amd import inputs, params, rsk
 
     dev = torch.device("cuda:0")
-    if args.only == "lb":
+    if args.only in ("lb", "bsk"):
         stream = torch.cuda.current_stream()
         sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
         b = torch.from_numpy(sysd["b"]).to(dev)
         xhat = torch.from_numpy(sysd["xhat"]).to(dev)
-        print(json.dumps({"lb": lb_run(sysd["A"], b, xhat, dev, stream)}), flush=True)
+        if args.only == "lb":
+            out = lb_run(sysd["A"], b, xhat, dev, stream)
+        else:
+            out = bsk_run(sysd["A"], b, xhat, sysd["weights"], dev, stream)
+        print(json.dumps({args.only: out}), flush=True)
         return
     if args.only:
         stream = torch.cuda.current_stream()
@@ -261,6 +265,7 @@ def main():
         out["eta_sweep"] = sweep
         out["time_to_plateau"] = plateau_runs(solve, inputs, weights, xhat, dev, stream)
         out["lb"] = lb_run(A, b, xhat, dev, stream)
+        out["bsk"] = bsk_run(A, b, xhat, weights, dev, stream)
 
     if not args.no_sweep:
         out["sampler"] = sampler_run(A, dev, stream)
@@ -573,6 +578,46 @@ def lb_run(A, b, xhat, dev, stream, Kmax=800, C=5, K_rate=40):
            "plateau_rel_err": plateau, "iterations_to_plateau": kstar, "ms_to_plateau": round(ms_plateau, 3),
            "max_iterations_run": Kmax}
     log(f"[bench] lb: {out}")
+    return out
+
+
+def bsk_run(A, b, xhat, weights, dev, stream, eta=64, Kmax=30000, C=100, K_rate=400):
+    """Block sparse Kaczmarz (eq. (bsk)) on the headline system, eta = 64, w = 1: time per step,
+    the rate of reading the step's rows (eta n 4 bytes, read twice: once for the block dots and
+    Gram matrix, once for the update), the error plateau and the time to reach it."""
+    import torch
+    from paper_2203_10838_amd import inputs, rsk
+    m, n = A.shape
+    ix = torch.from_numpy(inputs.index_stream(weights, Kmax, eta, SEED + 5)).to(dev)
+    ws = torch.empty(16 << 20, dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        r = fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return r, a0.elapsed_time(a1)
+
+    rsk.bsk_solve(A, b, lam=LAM, eta=eta, w=1.0, K=4, index_stream=ix, workspace=ws)
+    _, ms_rate = timed(lambda: rsk.bsk_solve(A, b, lam=LAM, eta=eta, w=1.0, K=K_rate, index_stream=ix,
+                                             workspace=ws, check=False))
+    cal = rsk.bsk_solve(A, b, lam=LAM, eta=eta, w=1.0, K=Kmax, index_stream=ix, x_ref=xhat, check_every=C,
+                        workspace=ws)
+    h = cal.err_hist.cpu().numpy()
+    plateau = float(np.median(h[int(len(h) * 0.8):]))
+    kstar = (int(np.argmax(h <= 1.05 * plateau)) + 1) * C
+    _, ms_plateau = timed(lambda: rsk.bsk_solve(A, b, lam=LAM, eta=eta, w=1.0, K=kstar, index_stream=ix,
+                                                workspace=ws, check=False))
+    step_bytes_ = eta * n * 4
+    out = {"workload": f"block sparse Kaczmarz, dense {m}x{n} float32, lambda={LAM}, eta={eta}, w=1",
+           "us_per_step": round(ms_rate * 1e3 / K_rate, 2),
+           "GB/s_rows_once": round(K_rate * step_bytes_ / (ms_rate * 1e-3) / 1e9, 1),
+           "plateau_rel_err": plateau, "steps_to_plateau": kstar, "ms_to_plateau": round(ms_plateau, 3),
+           "max_steps_run": Kmax}
+    log(f"[bench] bsk: {out}")
     return out
 
 

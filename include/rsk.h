@@ -193,14 +193,15 @@ int32_t rsk_spectral_norm2_dense(const rsk_dense *A, int64_t iters, void *v, dou
  *   x_{k+1} = S_lambda(x*_{k+1}),
  * with w = p->alpha. ||A_tau||_2^2 is the largest eigenvalue of the block's
  * Gram matrix A_tau A_tau^T, computed in double to rounding (Householder
- * tridiagonalisation, then Sturm-count bisection). Takes the rsk_params of
- * the RSKA solves: lambda, eta (1 <= eta <= 64), alpha (= w), K,
- * index_stream, stream_offset, warm_start, x_ref / check_every / err_hist,
- * status_dev; alpha_k, y_out and tol must be null/0, rownorm2, grid and kernel
- * are ignored. block_norm2: nullable device double[K], ||A_tau_k||_2^2 of
- * every step. Device status: RSK_ERR_INDEX_RANGE (stream index outside
- * [0, m)), RSK_ERR_ZERO_ROW (a block of zero rows), RSK_ERR_NONFINITE.
- * All sums run in fixed orders (bitwise reproducible).
+ * tridiagonalisation, then Sturm-count bisection) for every step before the
+ * iteration starts (it does not depend on x); the iteration is the RSKA solve
+ * with unit row norms and per-step relaxation alpha_k = eta w / ||A_tau_k||^2.
+ * Takes the rsk_params of rsk_avg_solve_dense with 1 <= eta <= 64, alpha = w,
+ * alpha_k null; rownorm2 is ignored; y_out, the monitor, tol, grid and kernel
+ * mean what they mean there. block_norm2: nullable device double[K],
+ * ||A_tau_k||_2^2 of every step. Device status: RSK_ERR_INDEX_RANGE (stream
+ * index outside [0, m)), RSK_ERR_ZERO_ROW (a block of zero rows: that step
+ * leaves x* unchanged), RSK_ERR_NONFINITE. Bitwise reproducible.
  */
 int32_t rsk_workspace_size_bsk_dense(const rsk_dense *A, const rsk_params *p, size_t *bytes);
 int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,

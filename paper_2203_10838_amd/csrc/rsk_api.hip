@@ -164,7 +164,7 @@ int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
 
 template <typename T>
 int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, void* x_star, void* x,
-                      void* ws, size_t ws_bytes, hipStream_t stream) {
+                      void* ws, size_t ws_bytes, hipStream_t stream, bool zero_status = true) {
   DensePlan pl;
   int32_t st = plan_dense<T>(A, p, &pl);
   if (st) return st;
@@ -185,7 +185,7 @@ int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, vo
   a.G = pl.G; a.two_hop = pl.two_hop; a.tile_cache = pl.tile_cache;
   a.nchunks = pl.nchunks; a.wq_max = pl.wq_max; a.lpr = pl.lpr;
   if (rsk::launch_zero_words((u64*)w, pl.bytes / sizeof(u64), stream) != hipSuccess) return RSK_ERR_HIP;
-  if (rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
+  if (zero_status && rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
   if (pl.kernel == 2) {
     if (rsk::launch_dense_rt(*reinterpret_cast<rsk::DenseArgs<float>*>(&a), pl.nt, pl.rp, pl.cpl, stream) != hipSuccess)
       return RSK_ERR_HIP;
@@ -441,33 +441,35 @@ int32_t lb_solve_t(const rsk_dense* A, const void* b, const rsk_lb_params* p, vo
   return rsk::launch_lb<T>(a, s) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
 }
 
-struct BskLayout {
-  int Gb, vec;
-  size_t bytes, offPart, offSums, offCoef;
-};
-
 int32_t check_bsk(const rsk_dense* A, const rsk_params* p) {
   if (!p || !p->status_dev) return RSK_ERR_INVALID_ARG;
   if (p->eta < 1 || p->K < 0 || p->K >= (int64_t(1) << 31) || p->stream_offset < 0) return RSK_ERR_INVALID_ARG;
   if (!(p->lambda >= 0.0) || !isfinite(p->lambda) || !finite_pos(p->alpha)) return RSK_ERR_INVALID_ARG;
   if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
-  if (p->check_every < 0 || (p->x_ref && p->check_every > 0 && !p->err_hist)) return RSK_ERR_INVALID_ARG;
-  if (p->alpha_k || p->y_out || p->tol != 0.0) return RSK_ERR_UNSUPPORTED;
+  if (p->alpha_k) return RSK_ERR_UNSUPPORTED;
   if (p->eta > rsk::kBskMaxEta || A->m > INT32_MAX) return RSK_ERR_UNSUPPORTED;
   return RSK_OK;
 }
 
+// The bsk workspace: per-step relaxations [K], unit row norms [m], then the RSKA solve's own.
+struct BskLayout {
+  size_t offAlpha, offOnes, offSolve, bytes;
+  rsk_params p2;
+};
+
 template <typename T>
 int32_t bsk_layout(const rsk_dense* A, const rsk_params* p, BskLayout* L) {
-  constexpr int V = rsk::kLbVec<T>;
-  L->vec = (((uintptr_t)A->val) % 16 == 0 && A->ld % V == 0) ? V : 1;
-  size_t pb = 0;
-  if (!rsk::bsk_plan<T>(A->n, p->eta, &L->Gb, &pb)) return RSK_ERR_UNSUPPORTED;
-  const size_t cnt = (size_t)p->eta + (size_t)p->eta * p->eta;
-  L->offPart = 0;
-  L->offSums = align256(pb);
-  L->offCoef = L->offSums + align256(cnt * sizeof(double));
-  L->bytes = L->offCoef + align256((size_t)p->eta * sizeof(T));
+  L->offAlpha = 0;
+  L->offOnes = align256((size_t)(p->K > 0 ? p->K : 1) * sizeof(T));
+  L->offSolve = L->offOnes + align256((size_t)A->m * sizeof(T));
+  L->p2 = *p;
+  L->p2.alpha = 1.0;
+  L->p2.alpha_k = (const void*)1;  // placeholders with the solve's validity; set at launch
+  L->p2.rownorm2 = (const void*)1;
+  size_t solve_bytes = 0;
+  int32_t st = rsk_workspace_size_dense(A, &L->p2, &solve_bytes);
+  if (st) return st;
+  L->bytes = L->offSolve + solve_bytes;
   return RSK_OK;
 }
 
@@ -478,32 +480,26 @@ int32_t bsk_solve_t(const rsk_dense* A, const void* b, const rsk_params* p, void
   int32_t st = bsk_layout<T>(A, p, &L);
   if (st) return st;
   if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws) % 256) return RSK_ERR_WORKSPACE;
+  char* w = (char*)ws;
   rsk::BskArgs<T> a{};
   a.A = (const T*)A->val;
   a.m = A->m;
   a.n = A->n;
   a.ld = A->ld;
-  a.b = (const T*)b;
   a.tau = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
   a.eta = p->eta;
   a.K = p->K;
   a.w = p->alpha;
-  a.lambda = (T)p->lambda;
-  a.z = (T*)x_star;
-  a.x = (T*)x;
-  a.warm = p->warm_start ? 1 : 0;
-  a.xref = (const T*)p->x_ref;
-  a.check_every = p->check_every;
-  a.err_hist = p->err_hist;
+  a.alpha_k = (T*)(w + L.offAlpha);
+  a.ones = (T*)(w + L.offOnes);
   a.norm2_hist = norm2;
   a.status = p->status_dev;
-  a.part = (T*)((char*)ws + L.offPart);
-  a.sums = (double*)((char*)ws + L.offSums);
-  a.coef = (T*)((char*)ws + L.offCoef);
-  a.Gb = L.Gb;
-  a.vec = L.vec;
   if (rsk::launch_zero_status(p->status_dev, s) != hipSuccess) return RSK_ERR_HIP;
-  return rsk::launch_bsk<T>(a, s) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+  if (rsk::launch_bsk_norms<T>(a, s) != hipSuccess) return RSK_ERR_HIP;
+  L.p2.alpha_k = a.alpha_k;
+  L.p2.rownorm2 = a.ones;
+  // the status stays as the block norms left it: the first error wins
+  return solve_dense_t<T>(A, b, &L.p2, x_star, x, w + L.offSolve, ws_bytes - L.offSolve, s, false);
 }
 
 }  // namespace

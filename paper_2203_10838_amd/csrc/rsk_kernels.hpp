@@ -286,36 +286,25 @@ hipError_t launch_lb(const LbArgs<T>& a, hipStream_t stream);
 template <typename T>
 hipError_t launch_power(const LbArgs<T>& a, int64_t iters, T* v, double* est, hipStream_t stream);
 
-// Block sparse Kaczmarz, eq. (bsk): eta <= kBskMaxEta rows a step, four kernels a step.
+// Block sparse Kaczmarz, eq. (bsk): per-step block norms (eta <= kBskMaxEta) computed up front,
+// written as the relaxations alpha_k = eta w / ||A_tau_k||_2^2 of an RSKA solve with unit row norms.
 constexpr int kBskMaxEta = 64;
 constexpr int kBskThreads = 256;
 template <typename T>
 struct BskArgs {
   const T* A;
   int64_t m, n, ld;
-  const T* b;
   const int* tau;         // index stream at the first step (K * eta entries)
   int eta;
   int64_t K;
   double w;               // relaxation of eq. (bsk)
-  T lambda;
-  T* z;
-  T* x;
-  int warm;
-  const T* xref;
-  int64_t check_every;
-  double* err_hist;
+  T* alpha_k;             // out: K relaxations
+  T* ones;                // out: m unit row norms
   double* norm2_hist;     // nullable, K entries: ||A_tau_k||_2^2
   int* status;
-  T* part;                // [Gb][eta + eta^2]
-  double* sums;           // [eta + eta^2]
-  T* coef;                // [eta]
-  int Gb, vec;
 };
 template <typename T>
-int bsk_plan(int64_t n, int eta, int* Gb, size_t* part_bytes);
-template <typename T>
-hipError_t launch_bsk(const BskArgs<T>& a, hipStream_t stream);
+hipError_t launch_bsk_norms(const BskArgs<T>& a, hipStream_t stream);
 
 // Row sampler (Philox4x32-10 + inverse CDF) and the FP64 cdf of the row norms.
 size_t sampling_cdf_ws_bytes(int64_t m);

@@ -270,110 +270,24 @@ __global__ __launch_bounds__(1024) void pw_start(T* v, int64_t n) {
 // ---------------------------------------------------------------------------
 // Block sparse Kaczmarz, eq. (bsk) of Sec. 1.1 (eta <= kBskMaxEta rows a step):
 //   x*_{k+1} = x*_k - w A_tau^T (A_tau x_k - b_tau) / ||A_tau||_2^2,  x_{k+1} = S_lambda(x*_{k+1}).
-// Per step: bsk_partial (partial block dots and partial Gram A_tau A_tau^T over column
-// slices), bsk_sum (fixed-order sums in double), bsk_coef (one wave: ||A_tau||_2^2 as the
-// largest eigenvalue of the Gram matrix, then the coefficients), bsk_update (transposed
-// update with S_lambda fused). ||A_tau||_2^2 is computed to rounding: Householder
-// tridiagonalisation of the Gram matrix in double, then Sturm-count multisection of the
-// tridiagonal matrix over the wave's 64 lanes.
+// ||A_tau_k||_2^2 depends on the step's rows only, not on x, so bsk_norms computes it for
+// every step up front (persistent workgroups, one step at a time): the Gram matrix
+// A_tau A_tau^T over LDS tiles of the rows, then its largest eigenvalue to rounding
+// (Householder tridiagonalisation in double, Sturm-count multisection). It writes the
+// per-step relaxation alpha_k = eta w / ||A_tau_k||_2^2, with which the RSKA step with unit
+// row norms, (alpha_k / eta) sum_t (<a_t, x> - b_t) a_t, is the block step of eq. (bsk);
+// the iteration itself then runs in the persistent RSKA kernels.
 // ---------------------------------------------------------------------------
 
-constexpr int kBskTile = 64;  // columns per LDS tile of bsk_partial
+constexpr int kBskTile = 64;  // columns per LDS tile
+constexpr int kBskQ = kBskMaxEta / (kBskThreads / 64);  // columns of the Gram matrix a lane updates
 
-template <typename T>
-__global__ __launch_bounds__(kBskThreads) void bsk_partial(const T* __restrict__ A, int64_t m, int64_t n, int64_t ld,
-                                                           const int* __restrict__ tau, int eta,
-                                                           const T* __restrict__ x, T* __restrict__ part,
-                                                           int64_t pstride, int* status) {
-  __shared__ T tile[kBskMaxEta][kBskTile + 1];
-  __shared__ T xt[kBskTile];
-  __shared__ int rows[kBskMaxEta];
-  if (status[0]) return;
-  const int tid = threadIdx.x, g = blockIdx.x, G = gridDim.x;
-  const int eta4 = (eta + 3) & ~3;
-  if (tid < kBskMaxEta) {
-    int r = -1;
-    if (tid < eta) {
-      r = tau[tid];
-      if (r < 0 || r >= m) {
-        set_status(status, ST_INDEX);
-        r = -1;
-      }
-    }
-    rows[tid] = r;
-  }
-  __syncthreads();
-  const int64_t c0 = (int64_t)g * n / G, c1 = (int64_t)(g + 1) * n / G;
-  const int bi = tid / 16, bj = tid % 16;  // this thread's 4x4 block of the Gram matrix
-  const bool gb = 4 * bi < eta && 4 * bj < eta;
-  T acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-  T dacc = T(0);
-  for (int64_t cb = c0; cb < c1; cb += kBskTile) {
-    const int cw = (int)(c1 - cb < kBskTile ? c1 - cb : kBskTile);
-    for (int e = tid; e < eta4 * kBskTile; e += kBskThreads) {
-      const int t = e / kBskTile, j = e % kBskTile;
-      const int r = rows[t];
-      tile[t][j] = (j < cw && r >= 0) ? A[(int64_t)r * ld + cb + j] : T(0);
-    }
-    if (tid < kBskTile) xt[tid] = tid < cw ? x[cb + tid] : T(0);
-    __syncthreads();
-    if (tid < eta)
-      for (int j = 0; j < kBskTile; ++j) dacc += tile[tid][j] * xt[j];
-    if (gb) {
-      for (int j = 0; j < kBskTile; ++j) {
-        T a[4], c[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a[u] = tile[4 * bi + u][j];
-          c[u] = tile[4 * bj + u][j];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * c[v];
-      }
-    }
-    __syncthreads();
-  }
-  T* pg = part + (size_t)g * pstride;
-  if (tid < eta) pg[tid] = dacc;
-  if (gb) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (4 * bi + u < eta && 4 * bj + v < eta) pg[eta + (4 * bi + u) * eta + 4 * bj + v] = acc[u][v];
-  }
-}
-
-// sums[e] = sum over slices of part[.][e] in double: kSumSeg segments of consecutive
-// slices summed in order, then the segment sums in order.
-template <typename T>
-__global__ __launch_bounds__(kSumSeg * kSumCols) void bsk_sum(const T* __restrict__ part, int Gb, int64_t pstride,
-                                                              int cnt, double* __restrict__ sums,
-                                                              const int* status) {
-  __shared__ double red[kSumSeg][kSumCols];
-  if (status[0]) return;
-  const int col = threadIdx.x % kSumCols, seg = threadIdx.x / kSumCols;
-  const int e = blockIdx.x * kSumCols + col;
-  const int g0 = seg * Gb / kSumSeg, g1 = (seg + 1) * Gb / kSumSeg;
-  double a = 0.0;
-  if (e < cnt) {
-#pragma unroll 8
-    for (int q = g0; q < g1; ++q) a += (double)part[(size_t)q * pstride + e];
-  }
-  red[seg][col] = a;
-  __syncthreads();
-  if (seg == 0 && e < cnt) {
-    double t = red[0][col];
-    for (int sg = 1; sg < kSumSeg; ++sg) t += red[sg][col];
-    sums[e] = t;
-  }
-}
+struct BskEig {
+  double Gm[kBskMaxEta][kBskMaxEta + 1];
+  double vs[kBskMaxEta], ws[kBskMaxEta], dd[kBskMaxEta], ee[kBskMaxEta];
+  double pr[kBskThreads / 64][kBskMaxEta];
+  double bnd[2][kBskThreads / 64];
+};
 
 __device__ __forceinline__ double wave_max_d(double v) {
 #pragma unroll
@@ -381,147 +295,189 @@ __device__ __forceinline__ double wave_max_d(double v) {
   return v;
 }
 
-// One wave. Gram G (eta x eta, double) from sums[eta ..]; lane i owns row i.
-template <typename T>
-__global__ __launch_bounds__(64) void bsk_coef(const double* __restrict__ sums, const T* __restrict__ b,
-                                               const int* __restrict__ tau, int eta, double w,
-                                               T* __restrict__ coef, double* norm2_out, int* status) {
-  __shared__ double Gm[kBskMaxEta][kBskMaxEta + 1];
-  __shared__ double vs[kBskMaxEta], ws[kBskMaxEta], dd[kBskMaxEta], ee[kBskMaxEta];
-  if (status[0]) return;
-  const int i = threadIdx.x;
-  for (int e = i; e < eta * eta; e += 64) Gm[e / eta][e % eta] = sums[eta + e];
-  if (i < kBskMaxEta) { vs[i] = 0.0; ws[i] = 0.0; ee[i] = 0.0; }
+// Largest eigenvalue of the symmetric eta x eta matrix in L.Gm (destroyed), by the whole
+// workgroup. Lane i of wave q owns row i and columns kBskQ q .. kBskQ q + kBskQ - 1; the
+// scalars every wave needs are computed by every wave alike from the same data.
+__device__ double gram_lambda_max(BskEig& L, int eta) {
+  const int tid = threadIdx.x, i = tid & 63, q = tid >> 6, j0 = q * kBskQ;
+  if (tid < kBskMaxEta) { L.vs[tid] = 0.0; L.ws[tid] = 0.0; L.ee[tid] = 0.0; L.dd[tid] = 0.0; }
   __syncthreads();
-  // Householder reduction to tridiagonal form (reflector H = I - beta v v^T on rows/columns k+1..)
+  // Householder reduction to tridiagonal form: H = I - beta v v^T on rows/columns k+1..
   for (int k = 0; k + 2 < eta; ++k) {
     const bool own = i > k && i < eta;
-    const double xi = own ? Gm[i][k] : 0.0;
+    const double xi = own ? L.Gm[i][k] : 0.0;
     const double nx2 = lane_sum(xi * xi, 64);
     double alpha = 0.0;
     if (nx2 > 0.0) {
-      const double x0 = Gm[k + 1][k];
+      const double x0 = L.Gm[k + 1][k];
       alpha = x0 > 0.0 ? -sqrt(nx2) : sqrt(nx2);
       const double vi = own ? (i == k + 1 ? xi - alpha : xi) : 0.0;
       const double beta = 2.0 / lane_sum(vi * vi, 64);
-      vs[i] = vi;
+      if (q == 0) L.vs[i] = vi;
+      __syncthreads();
+      double pp = 0.0;
+#pragma unroll 4
+      for (int c = 0; c < kBskQ; ++c) {
+        const int j = j0 + c;
+        pp += (own && j > k && j < eta) ? L.Gm[i][j] * L.vs[j] : 0.0;
+      }
+      L.pr[q][i] = pp;
       __syncthreads();
       double pi = 0.0;
-      if (own)
-        for (int j = k + 1; j < eta; ++j) pi += Gm[i][j] * vs[j];
+#pragma unroll
+      for (int r = 0; r < kBskThreads / 64; ++r) pi += L.pr[r][i];
       pi *= beta;
       const double pv = lane_sum(own ? pi * vi : 0.0, 64);
       const double wi = pi - 0.5 * beta * pv * vi;
-      ws[i] = wi;
+      if (q == 0) L.ws[i] = wi;
       __syncthreads();
-      if (own)
-        for (int j = k + 1; j < eta; ++j) Gm[i][j] -= vi * ws[j] + wi * vs[j];
+#pragma unroll 4
+      for (int c = 0; c < kBskQ; ++c) {
+        const int j = j0 + c;
+        if (own && j > k && j < eta) L.Gm[i][j] -= vi * L.ws[j] + wi * L.vs[j];
+      }
       __syncthreads();
     }
-    if (i == 0) {
-      dd[k] = Gm[k][k];
-      ee[k] = alpha;
+    if (tid == 0) {
+      L.dd[k] = L.Gm[k][k];
+      L.ee[k] = alpha;
     }
   }
   __syncthreads();
-  if (i == 0) {
+  if (tid == 0) {
     if (eta >= 2) {
-      dd[eta - 2] = Gm[eta - 2][eta - 2];
-      ee[eta - 2] = Gm[eta - 1][eta - 2];
+      L.dd[eta - 2] = L.Gm[eta - 2][eta - 2];
+      L.ee[eta - 2] = L.Gm[eta - 1][eta - 2];
     }
-    dd[eta - 1] = Gm[eta - 1][eta - 1];
+    L.dd[eta - 1] = L.Gm[eta - 1][eta - 1];
   }
   __syncthreads();
-  // Sturm-count multisection for the largest eigenvalue of the tridiagonal (dd, ee):
-  // count(s) = #eigenvalues < s = #negative pivots of T - s I; lane l tests s_l.
-  const double di = i < eta ? dd[i] : -INFINITY;
-  const double ri = i < eta ? fabs(i > 0 ? ee[i - 1] : 0.0) + fabs(i + 1 < eta ? ee[i] : 0.0) : 0.0;
+  // count(s) = #eigenvalues < s = #negative pivots of T - s I; thread l tests shift s_l.
+  const double di = i < eta ? L.dd[i] : -INFINITY;
+  const double ri = i < eta ? fabs(i > 0 ? L.ee[i - 1] : 0.0) + fabs(i + 1 < eta ? L.ee[i] : 0.0) : 0.0;
   double lo = wave_max_d(di), hi = wave_max_d(i < eta ? di + ri : -INFINITY);
-  const double e2max = wave_max_d(i < eta ? ee[i] * ee[i] : 0.0);
+  const double e2max = wave_max_d(i < eta ? L.ee[i] * L.ee[i] : 0.0);
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
-  for (int round = 0; round < 12 && hi > lo; ++round) {
+  constexpr double kParts = kBskThreads + 1;
+  for (int round = 0; round < 10 && hi > lo; ++round) {
     const double width = hi - lo;
-    const double sg = lo + width * (double)(i + 1) / 65.0;
+    const double sg = lo + width * (double)(tid + 1) / kParts;
     int cnt = 0;
-    double q = dd[0] - sg;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
+    double qv = L.dd[0] - sg;
+    if (fabs(qv) < pivmin) qv = -pivmin;
+    cnt += qv < 0.0;
     for (int t = 1; t < eta; ++t) {
-      q = (dd[t] - sg) - ee[t - 1] * ee[t - 1] / q;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
+      qv = (L.dd[t] - sg) - L.ee[t - 1] * L.ee[t - 1] / qv;
+      if (fabs(qv) < pivmin) qv = -pivmin;
+      cnt += qv < 0.0;
     }
-    const unsigned long long below = __ballot(cnt < eta);  // lanes with s_l <= lambda_max
-    if (below == 0ull) {
-      hi = lo + width / 65.0;
+    // shifts at or below lambda_max have cnt < eta; they are a prefix of the threads
+    const unsigned long long below = __ballot(cnt < eta);
+    if (i == 0) L.bnd[round & 1][q] = (double)__popcll(below);
+    __syncthreads();
+    int nb = 0;
+#pragma unroll
+    for (int r = 0; r < kBskThreads / 64; ++r) nb += (int)L.bnd[round & 1][r];
+    if (nb == 0) {
+      hi = lo + width / kParts;
     } else {
-      const int l = 63 - __clzll((long long)below);
-      const double nlo = lo + width * (double)(l + 1) / 65.0;
-      hi = l == 63 ? hi : lo + width * (double)(l + 2) / 65.0;
+      const double nlo = lo + width * (double)nb / kParts;
+      hi = nb == kBskThreads ? hi : lo + width * (double)(nb + 1) / kParts;
       lo = nlo;
     }
   }
-  const double s2 = 0.5 * (lo + hi);
-  if (!(s2 > 0.0) || !isfinite(s2)) {
-    if (i == 0) set_status(status, ST_ZERO_ROW);
-    return;
-  }
-  if (i == 0 && norm2_out) *norm2_out = s2;
-  if (i < eta) coef[i] = (T)(w * (sums[i] - (double)b[tau[i]]) / s2);
+  return 0.5 * (lo + hi);
 }
 
-// x*_j -= sum_t coef_t a_{tau_t, j}; x_j = S_lambda(x*_j). Block: kSumCols chunks x kSumSeg
-// row groups (group r takes rows r, r + kSumSeg, ...), groups summed in order.
-template <typename T, int VEC>
-__global__ __launch_bounds__(kSumSeg * kSumCols) void bsk_update(const T* __restrict__ A, int64_t n, int64_t ld,
-                                                                 const int* __restrict__ tau, int eta,
-                                                                 const T* __restrict__ coef, T* __restrict__ z,
-                                                                 T* __restrict__ x, T lambda, int* status,
-                                                                 int64_t k) {
-  using V = Vec<T, VEC>;
-  __shared__ T cf[kBskMaxEta];
+template <typename T>
+__global__ __launch_bounds__(kBskThreads) void bsk_norms(const T* __restrict__ A, int64_t m, int64_t n, int64_t ld,
+                                                         const int* __restrict__ tau0, int eta, int64_t K, double w,
+                                                         T* __restrict__ alpha_k, double* __restrict__ norm2,
+                                                         int* status) {
+  __shared__ T tile[kBskMaxEta][kBskTile + 1];
   __shared__ int rows[kBskMaxEta];
-  __shared__ V red[kSumSeg][kSumCols];
-  if (status[0]) return;
-  const int tid = threadIdx.x, col = tid % kSumCols, grp = tid / kSumCols;
-  if (tid < eta) {
-    cf[tid] = coef[tid];
-    rows[tid] = tau[tid];
-  }
-  __syncthreads();
-  const int64_t nch = (n + VEC - 1) / VEC;
-  const int64_t qc = blockIdx.x * (int64_t)kSumCols + col;
-  V acc;
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) acc.v[e] = T(0);
-  if (qc < nch) {
-    for (int t = grp; t < eta; t += kSumSeg) {
-      const V a = load_vec<T, VEC>(A + (int64_t)rows[t] * ld, qc * VEC, n);
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) acc.v[e] += cf[t] * a.v[e];
+  __shared__ BskEig L;
+  const int tid = threadIdx.x;
+  const int eta4 = (eta + 3) & ~3;
+  const int bi = tid / 16, bj = tid % 16;  // this thread's 4x4 block of the Gram matrix
+  const bool gb = 4 * bi < eta && 4 * bj < eta;
+  constexpr int kLoads = kBskMaxEta * kBskTile / kBskThreads;  // tile elements a thread loads
+  for (int64_t k = blockIdx.x; k < K; k += gridDim.x) {
+    if (tid < kBskMaxEta) {
+      int r = -1;
+      if (tid < eta) {
+        r = tau0[k * eta + tid];
+        if (r < 0 || r >= m) {
+          set_status(status, ST_INDEX);
+          r = -1;
+        }
+      }
+      rows[tid] = r;
     }
-  }
-  red[grp][col] = acc;
-  __syncthreads();
-  int bad = 0;
-  if (grp == 0 && qc < nch) {
-    V sm = red[0][col];
-    for (int sg = 1; sg < kSumSeg; ++sg)
+    __syncthreads();
+    T acc[4][4];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) sm.v[e] += red[sg][col].v[e];
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const int64_t j = qc * VEC + e;
-      if (j < n) {
-        const T zj = z[j] - sm.v[e];
-        z[j] = zj;
-        x[j] = shrink(zj, lambda);
-        bad |= !isfinite(zj);
+      for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+    for (int64_t cb = 0; cb < n; cb += kBskTile) {
+      const int cw = (int)(n - cb < kBskTile ? n - cb : kBskTile);
+      T v[kLoads];
+#pragma unroll
+      for (int u = 0; u < kLoads; ++u) {  // all loads issued before any LDS store
+        const int e = tid + u * kBskThreads, t = e / kBskTile, j = e % kBskTile;
+        const int r = rows[t];
+        v[u] = (t < eta4 && j < cw && r >= 0) ? A[(int64_t)r * ld + cb + j] : T(0);
+      }
+      __syncthreads();  // the previous tile's reads are done
+#pragma unroll
+      for (int u = 0; u < kLoads; ++u) {
+        const int e = tid + u * kBskThreads;
+        tile[e / kBskTile][e % kBskTile] = v[u];
+      }
+      __syncthreads();
+      if (gb) {
+#pragma unroll 4
+        for (int j = 0; j < kBskTile; ++j) {
+          T a[4], c[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a[u] = tile[4 * bi + u][j];
+            c[u] = tile[4 * bj + u][j];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) acc[u][vv] += a[u] * c[vv];
+        }
       }
     }
+    if (gb) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+          if (4 * bi + u < eta && 4 * bj + vv < eta) L.Gm[4 * bi + u][4 * bj + vv] = (double)acc[u][vv];
+    }
+    __syncthreads();
+    const double s2 = gram_lambda_max(L, eta);
+    if (tid == 0) {
+      if (s2 > 0.0 && isfinite(s2)) {
+        alpha_k[k] = (T)((double)eta * w / s2);
+      } else {
+        alpha_k[k] = T(0);
+        set_status(status, ST_ZERO_ROW);
+      }
+      if (norm2) norm2[k] = s2;
+    }
+    __syncthreads();  // rows, tile and L are reused by the next step
   }
-  if (bad) set_status(status, ST_NONFINITE);
-  if (blockIdx.x == 0 && tid == 0) status[1] = (int)(k + 1);
+}
+
+template <typename T>
+__global__ void fill_value(T* p, int64_t count, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -631,53 +587,35 @@ hipError_t launch_power(const LbArgs<T>& a, int64_t iters, T* v, double* est, hi
   return hipGetLastError();
 }
 
+// Resident workgroups of bsk_norms (at most K).
 template <typename T>
-int bsk_plan(int64_t n, int eta, int* Gb, size_t* part_bytes) {
-  if (eta < 1 || eta > kBskMaxEta || n < 1) return 0;
-  int dev = 0, cus = 0;
+int bsk_grid(int64_t K) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&bsk_norms<T>, kBskThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    return 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const int64_t want = (n + 255) / 256;  // at least 256 columns a slice
-  *Gb = (int)(want < cus ? want : cus);
-  if (*Gb < 1) *Gb = 1;
-  *part_bytes = (size_t)(*Gb) * (size_t)(eta + eta * eta) * sizeof(T);
-  return 1;
+  const int64_t g = (int64_t)per_cu * cus;
+  return (int)(K < g ? (K > 0 ? K : 1) : g);
 }
 
 template <typename T>
-hipError_t launch_bsk(const BskArgs<T>& a, hipStream_t s) {
-  const int64_t ib = (a.n + 255) / 256;
-  const int ub = (int)(ib < 1024 ? ib : 1024);
-  hipLaunchKernelGGL(lb_init<T>, dim3(ub), dim3(256), 0, s, a.z, a.x, a.n, a.lambda, a.warm);
-  const int cnt = a.eta + a.eta * a.eta;
-  const int64_t pstride = cnt;
-  const int64_t nch = (a.n + a.vec - 1) / a.vec;
-  const dim3 ublocks((unsigned)((nch + kSumCols - 1) / kSumCols)), sblocks((unsigned)((cnt + kSumCols - 1) / kSumCols));
-  for (int64_t k = 0; k < a.K; ++k) {
-    const int* tau = a.tau + k * a.eta;
-    hipLaunchKernelGGL(bsk_partial<T>, dim3(a.Gb), dim3(kBskThreads), 0, s, a.A, a.m, a.n, a.ld, tau, a.eta, a.x,
-                       a.part, pstride, a.status);
-    hipLaunchKernelGGL(bsk_sum<T>, sblocks, dim3(kSumSeg * kSumCols), 0, s, a.part, a.Gb, pstride, cnt, a.sums,
-                       a.status);
-    hipLaunchKernelGGL(bsk_coef<T>, dim3(1), dim3(64), 0, s, a.sums, a.b, tau, a.eta, a.w, a.coef,
-                       a.norm2_hist ? a.norm2_hist + k : nullptr, a.status);
-    if (a.vec == 1)
-      hipLaunchKernelGGL((bsk_update<T, 1>), ublocks, dim3(kSumSeg * kSumCols), 0, s, a.A, a.n, a.ld, tau, a.eta,
-                         a.coef, a.z, a.x, a.lambda, a.status, k);
-    else
-      hipLaunchKernelGGL((bsk_update<T, kLbVec<T>>), ublocks, dim3(kSumSeg * kSumCols), 0, s, a.A, a.n, a.ld, tau,
-                         a.eta, a.coef, a.z, a.x, a.lambda, a.status, k);
-    if (a.xref && a.check_every > 0 && a.err_hist && (k + 1) % a.check_every == 0)
-      hipLaunchKernelGGL(lb_err<T>, dim3(1), dim3(1024), 0, s, a.x, a.xref, a.n,
-                         a.err_hist + (k + 1) / a.check_every - 1, a.status);
+hipError_t launch_bsk_norms(const BskArgs<T>& a, hipStream_t s) {
+  const int64_t ib = (a.m + 255) / 256;
+  hipLaunchKernelGGL(fill_value<T>, dim3((unsigned)(ib < 1024 ? ib : 1024)), dim3(256), 0, s, a.ones, a.m, T(1));
+  if (a.K > 0) {
+    const int G = bsk_grid<T>(a.K);
+    if (G < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bsk_norms<T>, dim3(G), dim3(kBskThreads), 0, s, a.A, a.m, a.n, a.ld, a.tau, a.eta, a.K, a.w,
+                       a.alpha_k, a.norm2_hist, a.status);
   }
   return hipGetLastError();
 }
 
-template int bsk_plan<float>(int64_t, int, int*, size_t*);
-template int bsk_plan<double>(int64_t, int, int*, size_t*);
-template hipError_t launch_bsk<float>(const BskArgs<float>&, hipStream_t);
-template hipError_t launch_bsk<double>(const BskArgs<double>&, hipStream_t);
+template hipError_t launch_bsk_norms<float>(const BskArgs<float>&, hipStream_t);
+template hipError_t launch_bsk_norms<double>(const BskArgs<double>&, hipStream_t);
+
 template int lb_plan<float>(int64_t, int, int*, size_t*, int*, int64_t*);
 template int lb_plan<double>(int64_t, int, int*, size_t*, int*, int64_t*);
 template hipError_t launch_lb<float>(const LbArgs<float>&, hipStream_t);
