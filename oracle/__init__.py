@@ -80,9 +80,9 @@ def _load():
             i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
             lib.oracle_rownorm2_dense.argtypes = [i64, i64, i64, vp, vp]
             lib.oracle_rownorm2_csr.argtypes = [i64, vp, vp, vp]
-            lib.oracle_rska_dense.argtypes = [i64, i64, i64, vp, vp, dbl, i32, dbl, vp, i64, vp, i64,
+            lib.oracle_rska_dense.argtypes = [i64, i64, i64, vp, vp, dbl, i32, dbl, vp, vp, i64, vp, i64,
                                               vp, vp, vp, i64, vp, vp, vp]
-            lib.oracle_rska_csr.argtypes = [i64, i64, vp, vp, vp, vp, dbl, i32, dbl, vp, i64, vp, i64,
+            lib.oracle_rska_csr.argtypes = [i64, i64, vp, vp, vp, vp, dbl, i32, dbl, vp, vp, i64, vp, i64,
                                             vp, vp, vp, i64, vp, vp, vp]
             lib.oracle_rska_dense_adjoint.argtypes = [i64, i64, i64, vp, vp, dbl, i32, vp, i64, vp, i64,
                                                       vp, vp, vp, vp]
@@ -198,11 +198,13 @@ def _common_out(n, m, z0, want_y, y0, K, check_every):
     return z, x, y, hist, nh
 
 
-def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, z0=None, want_y=False,
+def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None, z0=None, want_y=False,
                y0=None, check_every=0, xref=None, raise_on_error=True):
     """Dense RSKA, eq. (rska) / Algorithm 1, in FP64 (see ``rska_oracle.c``).
 
-    A (m x n) and b are upcast exactly to float64. Returns a dict with
+    A (m x n) and b are upcast exactly to float64. ``row_w`` (m, optional) are
+    per-row weights w_i (the matrix W of Definition 1; variants v3/v4 of Sec. 5):
+    row i is relaxed by alpha (or alpha_k[k]) times w_i. Returns a dict with
     z (= x*_K), x (= S_lambda(z)), y (dual, if want_y), hist (relative errors
     every ``check_every`` steps if xref is given), k_done and status.
     """
@@ -211,10 +213,11 @@ def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, z0=None, w
     m, n = A.shape
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     ak = None if alpha_k is None else _f64(alpha_k)
+    rw = None if row_w is None else _f64(row_w)
     z, x, y, hist, nh = _common_out(n, m, z0, want_y, y0, K, check_every)
     xr = None if xref is None else _f64(xref)
     kd = np.zeros(1, dtype=np.int64)
-    st = _load().oracle_rska_dense(m, n, n, _p(A), _p(b), float(lam), int(eta), float(alpha), _p(ak),
+    st = _load().oracle_rska_dense(m, n, n, _p(A), _p(b), float(lam), int(eta), float(alpha), _p(ak), _p(rw),
                                    int(K), _p(idx), int(off), _p(z), _p(x), _p(y),
                                    int(check_every) if xr is not None else 0, _p(xr), _p(hist), _p(kd))
     if st and raise_on_error:
@@ -222,7 +225,7 @@ def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, z0=None, w
     return {"z": z, "x": x, "y": y, "hist": hist[:nh], "k_done": int(kd[0]), "status": st}
 
 
-def rska_csr(row_ptr, col, val, n, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, z0=None,
+def rska_csr(row_ptr, col, val, n, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None, z0=None,
              want_y=False, y0=None, check_every=0, xref=None, raise_on_error=True):
     """CSR RSKA: the same iteration with rows stored as (row_ptr, col, val)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -232,18 +235,19 @@ def rska_csr(row_ptr, col, val, n, b, lam, eta, alpha, K, idx, *, off=0, alpha_k
     m = len(row_ptr) - 1
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     ak = None if alpha_k is None else _f64(alpha_k)
+    rw = None if row_w is None else _f64(row_w)
     z, x, y, hist, nh = _common_out(n, m, z0, want_y, y0, K, check_every)
     xr = None if xref is None else _f64(xref)
     kd = np.zeros(1, dtype=np.int64)
     st = _load().oracle_rska_csr(m, n, _p(row_ptr), _p(col), _p(val), _p(b), float(lam), int(eta),
-                                 float(alpha), _p(ak), int(K), _p(idx), int(off), _p(z), _p(x), _p(y),
+                                 float(alpha), _p(ak), _p(rw), int(K), _p(idx), int(off), _p(z), _p(x), _p(y),
                                  int(check_every) if xr is not None else 0, _p(xr), _p(hist), _p(kd))
     if st and raise_on_error:
         raise OracleError(st, "rska_csr")
     return {"z": z, "x": x, "y": y, "hist": hist[:nh], "k_done": int(kd[0]), "status": st}
 
 
-def rska_dense_rows(rows_of, b, m, n, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, z0=None):
+def rska_dense_rows(rows_of, b, m, n, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None, z0=None):
     """Dense RSKA on a matrix too large to hand over whole.
 
     Only the rows that the stream references enter the iteration, so the
@@ -258,7 +262,8 @@ def rska_dense_rows(rows_of, b, m, n, lam, eta, alpha, K, idx, *, off=0, alpha_k
     uniq, inv = np.unique(used, return_inverse=True)
     Asub = _f64(rows_of(uniq))
     bsub = _f64(np.asarray(b)[uniq]) if not callable(b) else _f64(b(uniq))
-    return rska_dense(Asub, bsub, lam, eta, alpha, K, inv.astype(np.int32), alpha_k=alpha_k, z0=z0)
+    rw = None if row_w is None else _f64(np.asarray(row_w)[uniq])
+    return rska_dense(Asub, bsub, lam, eta, alpha, K, inv.astype(np.int32), alpha_k=alpha_k, row_w=rw, z0=z0)
 
 
 def rska_multirhs(A, B, lam, eta, alpha, K, idx, **kw):

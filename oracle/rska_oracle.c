@@ -93,14 +93,16 @@ static double rel_err(int64_t n, const double *x, const double *xref) {
  * paper's x*_0 = 0) and x_0 = S_lambda(z). x receives S_lambda(z_K).
  * y (nullable, length m) is in/out: y[i_t] -= c_t each step.
  * Step k uses indices idx[off + k*eta + t], t = 0..eta-1, and the relaxation
- * alpha_k[k] if alpha_k is given, else alpha.
+ * alpha_k[k] if alpha_k is given, else alpha, times row_w[i] for row i when
+ * row_w (length m) is given: the diagonal weight matrix W of Definition 1
+ * (variants v3/v4 of Sec. 5), c_t = (w_i / eta) (<a_i, x> - b_i) / ||a_i||^2.
  * If check_every > 0 and xref/err_hist are given, err_hist[q] receives the
  * relative error after step (q+1)*check_every.
  * *k_done receives the number of completed steps (nullable).
  */
 int oracle_rska_dense(int64_t m, int64_t n, int64_t ld, const double *A, const double *b,
                       double lambda, int32_t eta, double alpha, const double *alpha_k,
-                      int64_t K, const int32_t *idx, int64_t off,
+                      const double *row_w, int64_t K, const int32_t *idx, int64_t off,
                       double *z, double *x, double *y,
                       int64_t check_every, const double *xref, double *err_hist,
                       int64_t *k_done) {
@@ -125,7 +127,7 @@ int oracle_rska_dense(int64_t m, int64_t n, int64_t ld, const double *A, const d
       for (int64_t j = 0; j < n; ++j) r2 += ai[j] * ai[j];
       if (r2 == 0.0) { st = OR_ZERO_ROW; goto done; }
       for (int64_t j = 0; j < n; ++j) dot += ai[j] * x[j];
-      c[t] = (ak / (double)eta) * (dot - b[i]) / r2;
+      c[t] = ((row_w ? ak * row_w[i] : ak) / (double)eta) * (dot - b[i]) / r2;
     }
     /* delta_k = sum_t c_t a_{tau_t}, formed first, then subtracted */
     for (int64_t j = 0; j < n; ++j) delta[j] = 0.0;
@@ -159,7 +161,7 @@ done:
 int oracle_rska_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                     const double *val, const double *b,
                     double lambda, int32_t eta, double alpha, const double *alpha_k,
-                    int64_t K, const int32_t *idx, int64_t off,
+                    const double *row_w, int64_t K, const int32_t *idx, int64_t off,
                     double *z, double *x, double *y,
                     int64_t check_every, const double *xref, double *err_hist,
                     int64_t *k_done) {
@@ -185,7 +187,7 @@ int oracle_rska_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t 
         dot += val[p] * x[col[p]];
       }
       if (r2 == 0.0) { st = OR_ZERO_ROW; goto done; }
-      c[t] = (ak / (double)eta) * (dot - b[i]) / r2;
+      c[t] = ((row_w ? ak * row_w[i] : ak) / (double)eta) * (dot - b[i]) / r2;
     }
     for (int64_t j = 0; j < n; ++j) delta[j] = 0.0;
     for (int32_t t = 0; t < eta; ++t) {

@@ -572,3 +572,64 @@ def test_bsk_consistent_limit_matches_linearized_bregman_limit():
     lb = oracle.lb_dense(c["A"], c["b"], lam, 1.0 / s2, 6000)
     assert np.linalg.norm(c["A"] @ got["x"] - c["b"]) <= 1e-8 * np.linalg.norm(c["b"])
     assert np.allclose(got["x"], lb["x"], atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# Per-row weights W = diag(w_i) (Definition 1; variants v3/v4 of Sec. 5)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("eta,alpha", [(1, 1.0), (5, 1.0), (8, 0.6)])
+def test_row_weights_one_step_matches_matrix_form(eta, alpha):
+    """x*_{k+1} = x*_k - A^T M_k (A x_k - b) with M_k = (1/eta) sum_t w_{tau_t} e e^T / ||a||^2,
+    w_i = alpha * rho_i for per-row weights rho (repeated rows counted each time)."""
+    rng = _rng(70 + eta)
+    m, n, lam = 11, 7, 0.3
+    A = rng.normal(size=(m, n))
+    b = rng.normal(size=m)
+    z0 = rng.normal(size=n)
+    rho = rng.uniform(0.0, 1.0, size=m)
+    tau = rng.integers(0, m, size=eta).astype(np.int32)
+    tau[-1] = tau[0]
+    out = oracle.rska_dense(A, b, lam, eta, alpha, 1, tau, z0=z0, row_w=rho)
+    x0 = oracle.soft_threshold(z0, lam)
+    M = oracle.sampling_matrix(A, tau, alpha * rho[tau])
+    assert _rel(out["z"], z0 - A.T @ (M @ (A @ x0 - b))) <= 1e-13
+
+
+def test_row_weights_csr_equals_dense_and_unit_weights_change_nothing():
+    c = inputs.csr_system(200, 90, 6, 5, seed=72, dtype="f64")
+    A = np.zeros((c["m"], c["n"]))
+    for i in range(c["m"]):
+        sl = slice(c["row_ptr"][i], c["row_ptr"][i + 1])
+        A[i, c["col"][sl]] = c["val"][sl]
+    K, eta = 150, 5
+    idx = inputs.index_stream(inputs.csr_sampling_weights(c["row_ptr"], c["val"]), K, eta, 73)
+    rho = _rng(74).uniform(0.0, 1.0, size=c["m"])
+    d = oracle.rska_dense(A, c["b"], 0.5, eta, 2.0, K, idx, row_w=rho)
+    s = oracle.rska_csr(c["row_ptr"], c["col"], c["val"], c["n"], c["b"], 0.5, eta, 2.0, K, idx, row_w=rho)
+    assert _rel(s["z"], d["z"]) <= 1e-13
+    u = oracle.rska_dense(A, c["b"], 0.5, eta, 2.0, K, idx, row_w=np.ones(c["m"]))
+    p = oracle.rska_dense(A, c["b"], 0.5, eta, 2.0, K, idx)
+    assert np.array_equal(u["z"], p["z"])
+
+
+def test_v4_coupling_and_convergence():
+    """v4: w_i ~ U[0,1], p_i proportional to ||a_i||^2 / w_i, so that P W D^-2 = alpha I with
+    alpha = (sum_j ||a_j||^2 / w_j)^-1 (the coupling of Assumption 1): the sampled stream follows p,
+    and the weighted iteration converges to x_hat on a consistent system."""
+    c = inputs.dense_system(150, 40, 4, dtype="f64", seed=75)
+    A = c["A"]
+    m = A.shape[0]
+    rng = _rng(76)
+    rho = rng.uniform(0.05, 1.0, size=m)
+    r2 = (A * A).sum(axis=1)
+    p = (r2 / rho) / (r2 / rho).sum()
+    # E[M_k] = sum_i p_i rho_i e_i e_i^T / ||a_i||^2 = I / sum_j (||a_j||^2 / rho_j)
+    alpha = 1.0 / (r2 / rho).sum()
+    assert np.allclose(p * rho / r2, alpha, rtol=1e-12)
+    eta, K = 10, 8000
+    idx = inputs.index_stream(r2 / rho, K, eta, 77)
+    counts = np.bincount(idx, minlength=m) / idx.size
+    assert np.abs(counts - p).max() <= 6 * np.sqrt(p.max() / idx.size)
+    out = oracle.rska_dense(A, c["b"], 0.5, eta, 1.0, K, idx, row_w=rho)
+    assert _rel(out["x"], c["xhat"]) <= 1e-10
