@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RSK_ABI_VERSION 1
+#define RSK_ABI_VERSION 2
 
 typedef enum { RSK_F32 = 0, RSK_F64 = 1 } rsk_dtype;
 
@@ -95,6 +95,10 @@ typedef struct {
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register tile */
+  const void *row_w;           /* nullable device array (m, dtype of A): per-row weights w_i, the diagonal W of
+                                  Definition 1 (variants v3/v4 of Sec. 5); row i is relaxed by alpha (or
+                                  alpha_k[k]) times w_i. Dense, CSR and multi-RHS solves; not the adjoint or
+                                  the block method. */
 } rsk_params;
 
 /*
@@ -143,6 +147,15 @@ typedef struct {
  */
 int32_t rsk_workspace_size_sampling_cdf(int64_t m, size_t *bytes);
 int32_t rsk_sampling_cdf_dense(const rsk_dense *A, double *cdf, void *workspace, size_t ws_bytes, void *stream);
+/* The same running sums of ||a_i||^2 / w_i (row_w: device, m, dtype of A): the probabilities
+ * p_i proportional to ||a_i||^2 / w_i of variant v4 (Sec. 5), coupled to the per-row weights of
+ * rsk_params.row_w as in Assumption 1. Same workspace. */
+int32_t rsk_sampling_cdf_dense_weighted(const rsk_dense *A, const void *row_w, double *cdf, void *workspace,
+                                        size_t ws_bytes, void *stream);
+/* Running sums of arbitrary non-negative weights (device double, m): cdf for any sampling
+ * distribution p_i proportional to weights[i]. Same scan and workspace size. */
+int32_t rsk_sampling_cdf_weights(const double *weights, int64_t m, double *cdf, void *workspace, size_t ws_bytes,
+                                 void *stream);
 int32_t rsk_sample_stream(const double *cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int32_t eta,
                           int32_t *out, void *stream);
 

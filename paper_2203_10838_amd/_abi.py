@@ -30,7 +30,7 @@ class RskParams(ctypes.Structure):
     _fields_ = [("lambda_", c_dbl), ("eta", c_i32), ("alpha", c_dbl), ("alpha_k", c_vp), ("K", c_i64),
                 ("index_stream", c_vp), ("stream_offset", c_i64), ("rownorm2", c_vp), ("warm_start", c_i32),
                 ("x_ref", c_vp), ("check_every", c_i64), ("tol", c_dbl), ("err_hist", c_vp), ("y_out", c_vp),
-                ("status_dev", c_vp), ("grid", c_i32), ("kernel", c_i32)]
+                ("status_dev", c_vp), ("grid", c_i32), ("kernel", c_i32), ("row_w", c_vp)]
 
 
 class RskBatchItem(ctypes.Structure):
@@ -63,6 +63,8 @@ SIGNATURES = {
                                 c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "rsk_workspace_size_sampling_cdf": (c_i32, [c_i64, ctypes.POINTER(c_sz)]),
     "rsk_sampling_cdf_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_vp, c_sz, c_vp]),
+    "rsk_sampling_cdf_dense_weighted": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "rsk_sampling_cdf_weights": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "rsk_sample_stream": (c_i32, [c_vp, c_i64, ctypes.c_uint64, c_i64, c_i64, c_i32, c_vp, c_vp]),
     "rsk_workspace_size_lb_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(c_sz)]),
     "rsk_lb_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskLbParams), c_vp, c_vp, c_vp, c_sz,

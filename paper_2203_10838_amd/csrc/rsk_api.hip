@@ -173,7 +173,7 @@ int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, vo
   unsigned char* w = (unsigned char*)ws;
   rsk::DenseArgs<T> a;
   a.A = (const T*)A->val; a.m = A->m; a.n = A->n; a.ld = A->ld;
-  a.b = (const T*)b; a.r2 = (const T*)p->rownorm2;
+  a.b = (const T*)b; a.r2 = (const T*)p->rownorm2; a.row_w = (const T*)p->row_w;
   a.lambda = (T)p->lambda; a.alpha = (T)p->alpha; a.alpha_k = (const T*)p->alpha_k;
   a.eta = p->eta; a.K = p->K;
   a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
@@ -247,7 +247,7 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
   unsigned char* w = (unsigned char*)ws;
   rsk::CsrArgs<T> a;
   a.row_ptr = A->row_ptr; a.col = A->col; a.val = (const T*)A->val; a.m = A->m; a.n = A->n;
-  a.b = (const T*)b; a.r2 = (const T*)p->rownorm2;
+  a.b = (const T*)b; a.r2 = (const T*)p->rownorm2; a.row_w = (const T*)p->row_w;
   a.lambda = (T)p->lambda; a.alpha = (T)p->alpha; a.alpha_k = (const T*)p->alpha_k;
   a.eta = p->eta; a.K = p->K;
   a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
@@ -350,7 +350,7 @@ void fill_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_param
   rsk::MultiRhsArgs& a = *ap;
   unsigned char* w = (unsigned char*)workspace;
   a.A = (const float*)A->val; a.m = A->m; a.n = A->n; a.ld = A->ld;
-  a.B = (const float*)B; a.R = R; a.r2 = (const float*)p->rownorm2;
+  a.B = (const float*)B; a.R = R; a.r2 = (const float*)p->rownorm2; a.row_w = (const float*)p->row_w;
   a.lambda = (float)p->lambda; a.alpha = (float)p->alpha; a.alpha_k = (const float*)p->alpha_k;
   a.eta = p->eta; a.K = p->K;
   a.idx = p->index_stream ? p->index_stream + p->stream_offset : nullptr;
@@ -369,6 +369,7 @@ int32_t adj_layout(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t c
                    AdjLayout* L) {
   if (ckpt_every < 1) return RSK_ERR_INVALID_ARG;
   if (p->K > 0 && !p->alpha_k) return RSK_ERR_INVALID_ARG;
+  if (p->row_w) return RSK_ERR_UNSUPPORTED;  // the reverse pass has no per-row weights
   if (p->eta > rsk::kAdjMaxEtaHost) return RSK_ERR_UNSUPPORTED;
   const size_t nr = (size_t)A->n * R * sizeof(float), er = (size_t)pl.eta_pad * R * sizeof(float);
   const int64_t C = ckpt_every < p->K ? ckpt_every : (p->K > 0 ? p->K : 1);
@@ -446,7 +447,7 @@ int32_t check_bsk(const rsk_dense* A, const rsk_params* p) {
   if (p->eta < 1 || p->K < 0 || p->K >= (int64_t(1) << 31) || p->stream_offset < 0) return RSK_ERR_INVALID_ARG;
   if (!(p->lambda >= 0.0) || !isfinite(p->lambda) || !finite_pos(p->alpha)) return RSK_ERR_INVALID_ARG;
   if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
-  if (p->alpha_k) return RSK_ERR_UNSUPPORTED;
+  if (p->alpha_k || p->row_w) return RSK_ERR_UNSUPPORTED;
   if (p->eta > rsk::kBskMaxEta || A->m > INT32_MAX) return RSK_ERR_UNSUPPORTED;
   return RSK_OK;
 }
@@ -698,9 +699,35 @@ int32_t rsk_sampling_cdf_dense(const rsk_dense* A, double* cdf, void* workspace,
   if (!workspace || ws_bytes < rsk::sampling_cdf_ws_bytes(A->m) || ((uintptr_t)workspace) % 256)
     return RSK_ERR_WORKSPACE;
   const hipError_t e = A->dtype == RSK_F64
-      ? rsk::launch_sampling_cdf<double>((const double*)A->val, A->m, A->n, A->ld, cdf, workspace, (hipStream_t)stream)
-      : rsk::launch_sampling_cdf<float>((const float*)A->val, A->m, A->n, A->ld, cdf, workspace, (hipStream_t)stream);
+      ? rsk::launch_sampling_cdf<double>((const double*)A->val, A->m, A->n, A->ld, nullptr, cdf, workspace,
+                                         (hipStream_t)stream)
+      : rsk::launch_sampling_cdf<float>((const float*)A->val, A->m, A->n, A->ld, nullptr, cdf, workspace,
+                                        (hipStream_t)stream);
   return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_sampling_cdf_dense_weighted(const rsk_dense* A, const void* row_w, double* cdf, void* workspace,
+                                        size_t ws_bytes, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!cdf || !row_w) return RSK_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < rsk::sampling_cdf_ws_bytes(A->m) || ((uintptr_t)workspace) % 256)
+    return RSK_ERR_WORKSPACE;
+  const hipError_t e = A->dtype == RSK_F64
+      ? rsk::launch_sampling_cdf<double>((const double*)A->val, A->m, A->n, A->ld, (const double*)row_w, cdf,
+                                         workspace, (hipStream_t)stream)
+      : rsk::launch_sampling_cdf<float>((const float*)A->val, A->m, A->n, A->ld, (const float*)row_w, cdf, workspace,
+                                        (hipStream_t)stream);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+}
+
+int32_t rsk_sampling_cdf_weights(const double* weights, int64_t m, double* cdf, void* workspace, size_t ws_bytes,
+                                 void* stream) {
+  if (!weights || !cdf || m <= 0) return RSK_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < rsk::sampling_cdf_ws_bytes(m) || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
+  return rsk::launch_sampling_cdf_weights(weights, m, cdf, workspace, (hipStream_t)stream) == hipSuccess
+             ? RSK_OK
+             : RSK_ERR_HIP;
 }
 
 int32_t rsk_sample_stream(const double* cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int32_t eta,

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
 #pragma unroll
         for (int u = 0; u < kRowChunk; ++u) dot += vv[u] * xg[u];
       }
-      const T rn = a.r2[i];
+      const T rn = weighted_rn(a.r2, a.row_w, i);
       T c;
       if (rn == T(0)) { c = T(NAN); lerr = ST_ZERO_ROW; }
       else c = (ak / T(eta)) * (dot - a.b[i]) / rn;
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
         dot = sum32(dot);
         T c = T(0);
         if (i >= 0) {
-          const T rn = a.r2[i];
+          const T rn = weighted_rn(a.r2, a.row_w, i);
           if (rn == T(0)) { lerr = ST_ZERO_ROW; c = T(NAN); }
           else c = (ak / T(eta)) * (dot - a.b[i]) / rn;
           if (!isfinite(c) && !lerr) lerr = ST_NONFINITE;

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       orn[j] = 1.f;
       if (lane == 0 && t < ot1) {
         const int i = tk[t];
-        if (i >= 0 && (int64_t)i < a.m) { ob[j] = a.b[i]; orn[j] = a.r2[i]; }
+        if (i >= 0 && (int64_t)i < a.m) { ob[j] = a.b[i]; orn[j] = weighted_rn(a.r2, a.row_w, i); }
       }
     }
   };

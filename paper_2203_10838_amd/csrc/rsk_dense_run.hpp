@@ -221,7 +221,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
       const int ic = ok ? i : 0;
       taub[t] = ic;
       bqb[t] = a.b[ic];
-      rqb[t] = a.r2[ic];
+      rqb[t] = weighted_rn(a.r2, a.row_w, ic);
     }
   }
 
@@ -354,7 +354,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
           if (!ok) next_err = ST_INDEX;
           ni[p] = ok ? ni[p] : 0;
           nb[p] = a.b[ni[p]];
-          nr[p] = a.r2[ni[p]];
+          nr[p] = weighted_rn(a.r2, a.row_w, ni[p]);
         }
       }
     }
@@ -528,7 +528,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
           const int ic = ok ? i : 0;
           tn[t] = ic;
           bn[t] = a.b[ic];
-          rn[t] = a.r2[ic];
+          rn[t] = weighted_rn(a.r2, a.row_w, ic);
         }
       }
     }

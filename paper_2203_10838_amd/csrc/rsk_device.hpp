@@ -104,6 +104,15 @@ __device__ __forceinline__ void set_status(int* status, int code) {
   if (code) atomicCAS(status, 0, code);
 }
 
+// ||a_i||^2 / w_i: the row norm with the row's weight of Definition 1 folded in (variants
+// v3/v4 of Sec. 5), so that (alpha/eta)(r - b)/(||a||^2/w) relaxes the row by alpha w. A zero
+// row stays 0 (reported as such); w = 0 gives an infinite norm, i.e. no update from the row.
+template <typename T>
+__device__ __forceinline__ T weighted_rn(const T* r2, const T* row_w, int64_t i) {
+  const T rn = r2[i];
+  return (row_w && rn != T(0)) ? rn / row_w[i] : rn;
+}
+
 template <typename T>
 __device__ __forceinline__ T shrink(T v, T lambda) {
   // S_lambda(v) = max(|v| - lambda, 0) sign(v); |v| == lambda gives 0.

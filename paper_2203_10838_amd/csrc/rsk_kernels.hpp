@@ -16,6 +16,7 @@ struct DenseArgs {
   int64_t m, n, ld;
   const T* b;
   const T* r2;            // ||a_i||^2
+  const T* row_w = nullptr;  // nullable per-row weights w_i (row i relaxed by alpha w_i)
   T lambda, alpha;
   const T* alpha_k;       // nullable, per-step relaxation
   int eta;
@@ -90,6 +91,7 @@ struct CsrArgs {
   int64_t m, n;
   const T* b;
   const T* r2;
+  const T* row_w = nullptr;  // nullable per-row weights
   T lambda, alpha;
   const T* alpha_k;
   int eta;
@@ -129,6 +131,7 @@ struct MultiRhsArgs {
   const float* B;         // m x R row-major
   int R;
   const float* r2;
+  const float* row_w = nullptr;  // nullable per-row weights
   float lambda, alpha;
   const float* alpha_k;   // nullable, device
   int eta;
@@ -309,8 +312,9 @@ hipError_t launch_bsk_norms(const BskArgs<T>& a, hipStream_t stream);
 // Row sampler (Philox4x32-10 + inverse CDF) and the FP64 cdf of the row norms.
 size_t sampling_cdf_ws_bytes(int64_t m);
 template <typename T>
-hipError_t launch_sampling_cdf(const T* A, int64_t m, int64_t n, int64_t ld, double* cdf, void* ws,
+hipError_t launch_sampling_cdf(const T* A, int64_t m, int64_t n, int64_t ld, const T* row_w, double* cdf, void* ws,
                                hipStream_t stream);
+hipError_t launch_sampling_cdf_weights(const double* w, int64_t m, double* cdf, void* ws, hipStream_t stream);
 hipError_t launch_sample_stream(const double* cdf, int64_t m, uint64_t seed, int64_t k0, int64_t K, int eta,
                                 int32_t* out, hipStream_t stream);
 

@@ -179,9 +179,9 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
 // indices and coefficients, marks the step done. grid-stride over eta_pad x R.
 // With Rh non-null the residuals R_tau = sum_s Y_s - B_tau are stored as well (the adjoint's recompute).
 __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, const int32_t* __restrict__ tau, int eta,
-                            const float* __restrict__ B, int R, const float* __restrict__ r2, float alpha,
-                            const float* __restrict__ alpha_k, int64_t k, float* __restrict__ C,
-                            float* __restrict__ Rh, int* status) {
+                            const float* __restrict__ B, int R, const float* __restrict__ r2,
+                            const float* __restrict__ row_w, float alpha, const float* __restrict__ alpha_k,
+                            int64_t k, float* __restrict__ C, float* __restrict__ Rh, int* status) {
   if (status[0]) return;
   const float scale = (alpha_k ? alpha_k[k] : alpha) / (float)eta;
   const size_t total = (size_t)eta_pad * R;
@@ -192,7 +192,7 @@ __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, con
       const int i = tau[t];
       float y = 0.f;
       for (int s = 0; s < S; ++s) y += Y[(size_t)s * total + e];
-      const float rn = r2[i];
+      const float rn = weighted_rn(r2, row_w, i);
       if (rn == 0.f) set_status(status, ST_ZERO_ROW);
       const float res = y - B[(int64_t)i * R + r];
       if (Rh) Rh[e] = res;
@@ -277,7 +277,7 @@ static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, fl
   hipLaunchKernelGGL(gemm_at_x, dim3(gt, gr, a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R, a.Y,
                      a.eta_pad, a.kspan, a.status);
   hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
-                     a.alpha, a.alpha_k, k, a.C, rh, a.status);
+                     a.row_w, a.alpha, a.alpha_k, k, a.C, rh, a.status);
   hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R, zin,
                      zout, a.x, a.lambda, a.status);
   const int32_t* tn = (k + 1 < a.K) ? tk + a.eta : tk;

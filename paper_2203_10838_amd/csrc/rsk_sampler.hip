@@ -64,9 +64,11 @@ __global__ __launch_bounds__(256) void sample_stream_kernel(const double* __rest
   }
 }
 
-// ||a_i||^2 in double (row i read once, coalesced).
+// ||a_i||^2 in double (row i read once, coalesced), divided by row_w[i] when given (the
+// sampling weights ||a_i||^2 / w_i of variant v4, Sec. 5).
 template <typename T>
-__global__ void rownorm2_f64_kernel(const T* __restrict__ A, int64_t m, int64_t n, int64_t ld, double* __restrict__ w) {
+__global__ void rownorm2_f64_kernel(const T* __restrict__ A, int64_t m, int64_t n, int64_t ld,
+                                    const T* __restrict__ row_w, double* __restrict__ w) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -78,7 +80,7 @@ __global__ void rownorm2_f64_kernel(const T* __restrict__ A, int64_t m, int64_t 
       s += v * v;
     }
     s = wave_sum(s);
-    if (lane == 0) w[i] = s;
+    if (lane == 0) w[i] = row_w ? s / (double)row_w[i] : s;
   }
 }
 
@@ -148,18 +150,28 @@ size_t sampling_cdf_ws_bytes(int64_t m) {
   return ((size_t)m * sizeof(double) + 255) / 256 * 256 + ((size_t)nch * sizeof(double) + 255) / 256 * 256;
 }
 
-template <typename T>
-hipError_t launch_sampling_cdf(const T* A, int64_t m, int64_t n, int64_t ld, double* cdf, void* ws,
-                               hipStream_t stream) {
-  double* w = (double*)ws;
-  double* csum = (double*)((unsigned char*)ws + ((size_t)m * sizeof(double) + 255) / 256 * 256);
+static void launch_scan(const double* w, int64_t m, double* cdf, double* csum, hipStream_t stream) {
   const int64_t nch = (m + kScanChunk - 1) / kScanChunk;
-  const int64_t waves = m < 65536 ? m : 65536;
-  hipLaunchKernelGGL(rownorm2_f64_kernel<T>, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, stream, A, m,
-                     n, ld, w);
   hipLaunchKernelGGL(scan_chunk_sums, dim3((unsigned)nch), dim3(kScanThreads), 0, stream, w, m, csum);
   hipLaunchKernelGGL(scan_chunk_prefix, dim3(1), dim3(64), 0, stream, csum, nch);
   hipLaunchKernelGGL(scan_chunk_apply, dim3((unsigned)nch), dim3(kScanThreads), 0, stream, w, m, csum, cdf);
+}
+
+template <typename T>
+hipError_t launch_sampling_cdf(const T* A, int64_t m, int64_t n, int64_t ld, const T* row_w, double* cdf, void* ws,
+                               hipStream_t stream) {
+  double* w = (double*)ws;
+  double* csum = (double*)((unsigned char*)ws + ((size_t)m * sizeof(double) + 255) / 256 * 256);
+  const int64_t waves = m < 65536 ? m : 65536;
+  hipLaunchKernelGGL(rownorm2_f64_kernel<T>, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, stream, A, m,
+                     n, ld, row_w, w);
+  launch_scan(w, m, cdf, csum, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_sampling_cdf_weights(const double* w, int64_t m, double* cdf, void* ws, hipStream_t stream) {
+  double* csum = (double*)((unsigned char*)ws + ((size_t)m * sizeof(double) + 255) / 256 * 256);
+  launch_scan(w, m, cdf, csum, stream);
   return hipGetLastError();
 }
 
@@ -174,8 +186,9 @@ hipError_t launch_sample_stream(const double* cdf, int64_t m, uint64_t seed, int
   return hipGetLastError();
 }
 
-template hipError_t launch_sampling_cdf<float>(const float*, int64_t, int64_t, int64_t, double*, void*, hipStream_t);
-template hipError_t launch_sampling_cdf<double>(const double*, int64_t, int64_t, int64_t, double*, void*,
-                                                hipStream_t);
+template hipError_t launch_sampling_cdf<float>(const float*, int64_t, int64_t, int64_t, const float*, double*,
+                                               void*, hipStream_t);
+template hipError_t launch_sampling_cdf<double>(const double*, int64_t, int64_t, int64_t, const double*, double*,
+                                                void*, hipStream_t);
 
 }  // namespace rsk

@@ -90,6 +90,11 @@ def csr_system(m: int, n: int, nnz_row: int, s: int, *, seed: int = 0, dtype="f3
             "xhat": xhat, "b": b.astype(dt), "m": m, "n": n}
 
 
+def row_weights(m: int, seed: int, dtype="f32", lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Per-row weights w_i drawn i.i.d. from U[lo, hi] (variants v3/v4 of Sec. 5 use U[0, 1])."""
+    return _rng(seed).uniform(lo, hi, size=m).astype(_DT[dtype])
+
+
 def row_sampling_weights(A) -> np.ndarray:
     """Sampling weights proportional to ||a_i||^2 of the stored rows (float64).
 

@@ -84,7 +84,7 @@ class SolveResult:
 
 def make_params(*, lam, eta, alpha, K, index_stream, rownorm2_t, status_dev, stream_offset=0, alpha_k=None,
                 warm_start=False, x_ref=None, check_every=0, tol=0.0, err_hist=None, y_out=None, grid=0,
-                kernel=0, dtype=None) -> _abi.RskParams:
+                kernel=0, dtype=None, row_w=None) -> _abi.RskParams:
     if K > 0:
         _dev(index_stream, "index_stream", torch.int32, stream_offset + K * eta)
     return _abi.RskParams(
@@ -94,7 +94,7 @@ def make_params(*, lam, eta, alpha, K, index_stream, rownorm2_t, status_dev, str
         _dev(rownorm2_t, "rownorm2", dtype), 1 if warm_start else 0,
         _dev(x_ref, "x_ref", dtype), int(check_every), float(tol),
         _dev(err_hist, "err_hist", torch.float64), _dev(y_out, "y_out", dtype),
-        _dev(status_dev, "status_dev", torch.int32, 2), int(grid), int(kernel))
+        _dev(status_dev, "status_dev", torch.int32, 2), int(grid), int(kernel), _dev(row_w, "row_w", dtype))
 
 
 def workspace_size_dense(A: torch.Tensor, params: _abi.RskParams) -> int:
@@ -116,8 +116,12 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
                 rownorm2_t: Optional[torch.Tensor] = None, x_star: Optional[torch.Tensor] = None,
                 warm_start: bool = False, x_ref: Optional[torch.Tensor] = None, check_every: int = 0,
                 tol: float = 0.0, y_out: Optional[torch.Tensor] = None, grid: int = 0, kernel: int = 0,
-                workspace: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
+                row_w: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                check: bool = True) -> SolveResult:
     """K steps of RSKA (eq. (rska), Algorithm 1) on a dense system, one persistent launch.
+
+    ``row_w`` (m, optional): per-row weights w_i of Definition 1 (variants v3/v4 of Sec. 5);
+    row i is then relaxed by alpha (or alpha_k[k]) times w_i.
 
     ``x_star`` (optional, in/out) receives x*_K; with ``warm_start`` it is also x*_0.
     With ``check`` the call synchronises, reads the device status and raises
@@ -140,7 +144,9 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
     params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
                          status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k,
                          warm_start=warm_start, x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist,
-                         y_out=y_out, grid=grid, kernel=kernel, dtype=dt)
+                         y_out=y_out, grid=grid, kernel=kernel, dtype=dt, row_w=row_w)
+    if row_w is not None:
+        _dev(row_w, "row_w", dt, m)
     if y_out is not None:
         _dev(y_out, "y_out", dt, m)
     d = dense_desc(A)
@@ -187,8 +193,8 @@ def solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: in
               alpha_k: Optional[torch.Tensor] = None, rownorm2_t: Optional[torch.Tensor] = None,
               x_star: Optional[torch.Tensor] = None, warm_start: bool = False, x_ref: Optional[torch.Tensor] = None,
               check_every: int = 0, tol: float = 0.0, y_out: Optional[torch.Tensor] = None,
-              grid: int = 0, kernel: int = 0, workspace: Optional[torch.Tensor] = None,
-              check: bool = True) -> SolveResult:
+              grid: int = 0, kernel: int = 0, row_w: Optional[torch.Tensor] = None,
+              workspace: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
     """K steps of RSKA on a CSR system (kernel 1: one workgroup, 2: multi-workgroup, 0: by eta)."""
     d = csr_desc(row_ptr, col, val, n)
     dt = val.dtype
@@ -208,7 +214,9 @@ def solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: in
     params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
                          status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, warm_start=warm_start,
                          x_ref=x_ref, check_every=check_every, tol=tol, err_hist=err_hist, y_out=y_out, grid=grid,
-                         kernel=kernel, dtype=dt)
+                         kernel=kernel, dtype=dt, row_w=row_w)
+    if row_w is not None:
+        _dev(row_w, "row_w", dt, d.m)
     if y_out is not None:
         _dev(y_out, "y_out", dt, d.m)
     nbytes = ctypes.c_size_t(0)
@@ -239,7 +247,7 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
                    rownorm2_t: Optional[torch.Tensor] = None, X_star: Optional[torch.Tensor] = None,
                    warm_start: bool = False, workspace: Optional[torch.Tensor] = None,
                    ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
-                   check: bool = True) -> SolveResult:
+                   row_w: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
     """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major).
 
     With ``ckpt`` (ceil(K/ckpt_every) x n x R float32) the x* checkpoints the
@@ -262,7 +270,9 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
     status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
     params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
                          status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, warm_start=warm_start,
-                         dtype=dt)
+                         dtype=dt, row_w=row_w)
+    if row_w is not None:
+        _dev(row_w, "row_w", dt, m)
     d = dense_desc(A)
     nbytes = ctypes.c_size_t(0)
     st = _lib().rsk_workspace_size_multirhs(ctypes.byref(d), R, ctypes.byref(params), ctypes.byref(nbytes))
@@ -344,18 +354,40 @@ def adjoint_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, 
 # Row sampler
 # ---------------------------------------------------------------------------
 
-def sampling_cdf(A: torch.Tensor) -> torch.Tensor:
-    """Running sums of the FP64 row norms ||a_i||^2 on the device (m doubles)."""
-    d = dense_desc(A)
+def _cdf_workspace(m: int, device) -> torch.Tensor:
     nbytes = ctypes.c_size_t(0)
-    st = _lib().rsk_workspace_size_sampling_cdf(d.m, ctypes.byref(nbytes))
+    st = _lib().rsk_workspace_size_sampling_cdf(int(m), ctypes.byref(nbytes))
     if st:
         raise RskError(st, "rsk_workspace_size_sampling_cdf")
-    ws = _workspace(nbytes.value, A.device)
+    return _workspace(nbytes.value, device)
+
+
+def sampling_cdf(A: torch.Tensor, row_w: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Running sums of the FP64 row norms ||a_i||^2 on the device (m doubles); with ``row_w``
+    the sums of ||a_i||^2 / w_i (variant v4's probabilities, Sec. 5)."""
+    d = dense_desc(A)
+    ws = _cdf_workspace(d.m, A.device)
     cdf = torch.empty(A.shape[0], dtype=torch.float64, device=A.device)
-    st = _lib().rsk_sampling_cdf_dense(ctypes.byref(d), cdf.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    if row_w is None:
+        st = _lib().rsk_sampling_cdf_dense(ctypes.byref(d), cdf.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    else:
+        _dev(row_w, "row_w", A.dtype, A.shape[0])
+        st = _lib().rsk_sampling_cdf_dense_weighted(ctypes.byref(d), row_w.data_ptr(), cdf.data_ptr(), ws.data_ptr(),
+                                                    ws.numel(), _stream())
     if st:
         raise RskError(st, "rsk_sampling_cdf_dense")
+    return cdf
+
+
+def sampling_cdf_weights(weights: torch.Tensor) -> torch.Tensor:
+    """Running sums of arbitrary non-negative FP64 weights on the device (m doubles)."""
+    _dev(weights, "weights", torch.float64)
+    ws = _cdf_workspace(weights.numel(), weights.device)
+    cdf = torch.empty(weights.numel(), dtype=torch.float64, device=weights.device)
+    st = _lib().rsk_sampling_cdf_weights(weights.data_ptr(), weights.numel(), cdf.data_ptr(), ws.data_ptr(),
+                                         ws.numel(), _stream())
+    if st:
+        raise RskError(st, "rsk_sampling_cdf_weights")
     return cdf
 
 
