@@ -130,7 +130,8 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb", "bsk"], default=None,
+    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb", "bsk", "variants"],
+                    default=None,
                     help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
@@ -145,15 +146,17 @@ def main():
     from paper_2203_10838_amd import inputs, params, rsk
 
     dev = torch.device("cuda:0")
-    if args.only in ("lb", "bsk"):
+    if args.only in ("lb", "bsk", "variants"):
         stream = torch.cuda.current_stream()
         sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
         b = torch.from_numpy(sysd["b"]).to(dev)
         xhat = torch.from_numpy(sysd["xhat"]).to(dev)
         if args.only == "lb":
             out = lb_run(sysd["A"], b, xhat, dev, stream)
-        else:
+        elif args.only == "bsk":
             out = bsk_run(sysd["A"], b, xhat, sysd["weights"], dev, stream)
+        else:
+            out = variants_run(sysd["A"], b, xhat, dev, stream)
         print(json.dumps({args.only: out}), flush=True)
         return
     if args.only:
@@ -266,6 +269,7 @@ def main():
         out["time_to_plateau"] = plateau_runs(solve, inputs, weights, xhat, dev, stream)
         out["lb"] = lb_run(A, b, xhat, dev, stream)
         out["bsk"] = bsk_run(A, b, xhat, weights, dev, stream)
+        out["variants"] = variants_run(A, b, xhat, dev, stream)
 
     if not args.no_sweep:
         out["sampler"] = sampler_run(A, dev, stream)
@@ -579,6 +583,51 @@ def lb_run(A, b, xhat, dev, stream, Kmax=800, C=5, K_rate=40):
            "max_iterations_run": Kmax}
     log(f"[bench] lb: {out}")
     return out
+
+
+def variants_run(A, b, xhat, dev, stream, eta=1024, Kmax=8000, C=20):
+    """The RSKA variants of Sec. 5 on the headline system, streams from the device sampler:
+    v1 alpha = 1; v2 alpha = alpha*(eta); v3 w_i ~ U[0,1], p_i ~ ||a_i||^2; v4 w_i ~ U[0,1],
+    p_i ~ ||a_i||^2 / w_i (alpha = 1, the weights carry the relaxation). Per variant: the
+    relative error after 1000, 2000, 4000 and 8000 steps, the steps (and their time) to come
+    within 5% of v2's error plateau if reached, and microseconds per step."""
+    import torch
+    from paper_2203_10838_amd import inputs, params, rsk
+    m, n = A.shape
+    r2 = rsk.rownorm2(A)
+    w = torch.from_numpy(inputs.row_weights(m, SEED + 7, "f32")).to(dev)
+    fro2 = float(r2.double().sum())
+    smax2 = spectral_norm_sq(A)
+    cdf = rsk.sampling_cdf(A)
+    cdf_w = rsk.sampling_cdf(A, row_w=w)
+    res, target = [], None
+    for name, alpha, row_w, c in (("v2", params.optimal_alpha(eta, fro2, smax2), None, cdf), ("v1", 1.0, None, cdf),
+                                  ("v3", 1.0, w, cdf), ("v4", 1.0, w, cdf_w)):
+        ix = rsk.sample_stream(c, seed=SEED + 8, K=Kmax, eta=eta)
+        cal = rsk.solve_dense(A, b, lam=LAM, eta=eta, alpha=alpha, K=Kmax, index_stream=ix, rownorm2_t=r2,
+                              row_w=row_w, x_ref=xhat, check_every=C)
+        h = cal.err_hist.cpu().numpy()
+        if target is None:
+            target = 1.05 * float(np.median(h[int(len(h) * 0.8):]))
+        hit = h <= target
+        kstar = (int(np.argmax(hit)) + 1) * C if hit.any() else None
+        K_t = kstar if kstar else Kmax
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        rsk.solve_dense(A, b, lam=LAM, eta=eta, alpha=alpha, K=K_t, index_stream=ix, rownorm2_t=r2,
+                        row_w=row_w, check=False)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        ms = a0.elapsed_time(a1)
+        res.append({"variant": name, "alpha": round(alpha, 3),
+                    "rel_err_at": {str(k): float(h[k // C - 1]) for k in (1000, 2000, 4000, 8000) if k <= Kmax},
+                    "steps_to_v2_plateau": kstar, "ms_to_v2_plateau": round(ms, 3) if kstar else None,
+                    "us_per_step": round(ms * 1e3 / K_t, 2)})
+        log(f"[bench] variant {res[-1]}")
+    return {"workload": f"RSKA variants v1-v4 of Sec. 5, dense {m}x{n} float32, lambda={LAM}, eta={eta}",
+            "v2_plateau_x1.05": target, "runs": res}
 
 
 def bsk_run(A, b, xhat, weights, dev, stream, eta=64, Kmax=30000, C=100, K_rate=400):
