@@ -15,6 +15,11 @@
 //    zero x entry in the dot, and its column sum is discarded.
 //  * The step's tile stays in VGPRs from the dots to the transposed update:
 //    A is read from HBM exactly once per step.
+//  * With 512 threads (eta > 768), the first NPF (pass, chunk) slots of the
+//    next step's tile (up to 144 KB a workgroup) are loaded straight into LDS
+//    (global_load_lds, no VGPRs) by the waves that take no part in the
+//    exchange, while the exchange runs; the next step reads them from LDS, so
+//    only the other slots load from HBM on the step's critical path.
 //  * Each pass publishes its partial dots as soon as its own loads have
 //    landed; the next step's indices, and b and ||a||^2 of the rows this
 //    workgroup reduces, are fetched a step ahead.
@@ -63,6 +68,13 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   __shared__ float4 red[kRtWaves][4 * CPL];       // per-wave column sums
   __shared__ float cs[RP * kRtRowsPerPass];        // step coefficients
   __shared__ double mon[2 * kRtWaves + 2];
+  // next-step tile slots prefetched into LDS: (p, r) with s = p * CPL + r < NPF; LDS slot s * NT + tid
+  // holds tile[p][r] of thread tid. PL passes hold prefetched slots.
+  constexpr int kPfBudget = 147456 / (NT * 16);
+  constexpr int NPF = NT == 512 ? (RP * CPL < kPfBudget ? RP * CPL : kPfBudget) : 0;
+  constexpr int PL = (NPF + CPL - 1) / CPL;
+  __shared__ float4 pf[NPF > 0 ? NPF * NT : 1];
+  __shared__ int nrow[PL > 0 ? PL * kRtRowsPerPass : 1];  // rows of the passes holding prefetched slots
 
   const int g = blockIdx.x, G = a.G, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int eta = a.eta;
@@ -134,6 +146,40 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   // every workgroup read the same indices, so all skip the loop alike
   if (__syncthreads_or(lerr)) stop_code = ST_INDEX;
 
+  // LDS prefetch of slots s < NPF: the issuing waves (the upper half) load, for consumer wave j,
+  // tile slot (p, r) of each of its 64 lanes; lane l of the issuing wave stands for lane l of
+  // wave j, so the 64 x 16 B that one global_load_lds writes are the 64 consumers' slots in order.
+  auto publish_rows = [&](const int (&rows)[RP]) {
+    if constexpr (NPF > 0) {
+#pragma unroll
+      for (int p = 0; p < PL; ++p)
+        if (sl == 0) nrow[p * kRtRowsPerPass + 16 * wave + ri] = rows[p];
+    }
+  };
+  auto issue_prefetch = [&]() {
+    if constexpr (NPF > 0) {
+      if (wave >= kRtWaves / 2) {
+        for (int I = wave - kRtWaves / 2; I < NPF * kRtWaves; I += kRtWaves / 2) {
+          const int j = I % kRtWaves, sp = I / kRtWaves, r = sp % CPL, p = sp / CPL;
+          const int row = nrow[p * kRtRowsPerPass + 16 * j + ri];
+          const int q = sl + 4 * r;
+          const float* gp = a.A + (int64_t)(row < 0 ? 0 : row) * a.ld + c0 + 4 * (q < qlast ? q : qlast);
+          __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void*)&pf[(p * CPL + r) * NT + 64 * j],
+                                           16, 0, 0);
+        }
+      }
+    }
+  };
+  if constexpr (NPF > 0) {
+    if (!stop_code && a.K > 0) {
+      publish_rows(rowi);
+      __syncthreads();
+      issue_prefetch();
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+
   for (int64_t k = 0; k < a.K && !stop_code; ++k) {
     // Re-derive the lane coordinates from an opaque copy of the thread id each
     // step: otherwise the compiler hoists every lane-dependent address out of
@@ -146,17 +192,24 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     u64* xP = a.xP + (size_t)(k & 1) * G * eta;
     const bool has_next = k + 1 < a.K;
 
-    // every load of the step (rows past eta read row 0 and are never used)
+    // every load of the step (rows past eta read row 0 and are never used); slots
+    // p * CPL + r < NPF were prefetched into LDS during the previous step
     float4 tile[RP][CPL];
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
       const float* rowp = a.A + (int64_t)(rowi[p] < 0 ? 0 : rowi[p]) * a.ld + c0;
 #pragma unroll
       for (int r = 0; r < CPL; ++r) {
+        if (p * CPL + r < NPF) continue;
         const int q = sl + 4 * r;  // clamped into the row: past the slice it meets x = 0
         tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
       }
     }
+#pragma unroll
+    for (int p = 0; p < PL; ++p)
+#pragma unroll
+      for (int r = 0; r < CPL; ++r)
+        if (p * CPL + r < NPF) tile[p][r] = pf[(p * CPL + r) * NT + tid];
     int rown[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) rown[p] = -1;
@@ -174,6 +227,14 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       const int t = p * kRtRowsPerPass + 16 * wave + ri;
       if (sl == 0 && t < eta) put_tagged(&xP[(size_t)g * eta + t], acc, tag);
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (NPF > 0) {
+      // every wave has consumed its LDS slots (the dots used them): the next step's may land
+      if (has_next) {
+        publish_rows(rown);
+        __syncthreads();
+        issue_prefetch();
+      }
     }
     // reduce the owned rows over the G workgroups; c_t = (alpha/eta)(r_t - b)/||a||^2
 #pragma unroll
@@ -250,6 +311,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       xv[tid] = shrink(z, a.lambda);
     }
     k_done = k + 1;
+    if constexpr (NPF > 0) __builtin_amdgcn_s_waitcnt(0);  // the prefetch has landed before the barrier
     // the next step's indices were checked by every workgroup alike
     const int next_bad = __syncthreads_or(nerr);
 
@@ -299,6 +361,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     for (int p = 0; p < RP; ++p) rowi[p] = rown[p];
   }
   if (stop_code && tid == 0) set_status(a.status, stop_code);
+  if constexpr (NPF > 0) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int j = tid; j < wq * 4; j += kRtThreads) {
     const int64_t c = c0 + j;
