@@ -15,8 +15,8 @@
 //    zero x entry in the dot, and its column sum is discarded.
 //  * The step's tile stays in VGPRs from the dots to the transposed update:
 //    A is read from HBM exactly once per step.
-//  * With 512 threads (eta > 768), the first NPF (pass, chunk) slots of the
-//    next step's tile (up to 144 KB a workgroup) are loaded straight into LDS
+//  * The first NPF (pass, chunk) slots of the next step's tile (up to 144 KB
+//    a workgroup; all slots for tiles that fit) are loaded straight into LDS
 //    (global_load_lds, no VGPRs) by the waves that take no part in the
 //    exchange, while the exchange runs; the next step reads them from LDS, so
 //    only the other slots load from HBM on the step's critical path.
@@ -71,7 +71,8 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   // next-step tile slots prefetched into LDS: (p, r) with s = p * CPL + r < NPF; LDS slot s * NT + tid
   // holds tile[p][r] of thread tid. PL passes hold prefetched slots.
   constexpr int kPfBudget = 147456 / (NT * 16);
-  constexpr int NPF = NT == 512 ? (RP * CPL < kPfBudget ? RP * CPL : kPfBudget) : 0;
+  // (1024-thread tiles wider than 12 slots leave no registers for the prefetch loop)
+  constexpr int NPF = (NT == 1024 && RP * CPL > 12) ? 0 : (RP * CPL < kPfBudget ? RP * CPL : kPfBudget);
   constexpr int PL = (NPF + CPL - 1) / CPL;
   __shared__ float4 pf[NPF > 0 ? NPF * NT : 1];
   __shared__ int nrow[PL > 0 ? PL * kRtRowsPerPass : 1];  // rows of the passes holding prefetched slots
