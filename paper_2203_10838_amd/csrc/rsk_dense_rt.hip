@@ -74,6 +74,10 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   // (1024-thread tiles wider than 12 slots leave no registers for the prefetch loop)
   constexpr int NPF = (NT == 1024 && RP * CPL > 12) ? 0 : (RP * CPL < kPfBudget ? RP * CPL : kPfBudget);
   constexpr int PL = (NPF + CPL - 1) / CPL;
+  // s_waitcnt immediate with vmcnt = kHbmSlots (bits 3:0 and 15:14), expcnt and lgkmcnt not waited on
+  constexpr int kHbmSlots = RP * CPL - NPF;
+  static_assert(kHbmSlots < 64, "vmcnt holds at most 63");
+  constexpr int kWaitPrefetch = (kHbmSlots & 15) | ((kHbmSlots >> 4) << 14) | (7 << 4) | (15 << 8);
   __shared__ float4 pf[NPF > 0 ? NPF * NT : 1];
   __shared__ int nrow[PL > 0 ? PL * kRtRowsPerPass : 1];  // rows of the passes holding prefetched slots
 
@@ -181,6 +185,23 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     }
   }
 
+  // The step's tile. Slots p * CPL + r < NPF come from the LDS prefetch; the others load from
+  // HBM: for step 0 here, for step k + 1 during step k's update, chunk by chunk as soon as the
+  // update has used it (rows past eta read row 0 and are never used).
+  float4 tile[RP][CPL];
+  if (!stop_code && a.K > 0) {
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const float* rowp = a.A + (int64_t)(rowi[p] < 0 ? 0 : rowi[p]) * a.ld + c0;
+#pragma unroll
+      for (int r = 0; r < CPL; ++r) {
+        if (p * CPL + r < NPF) continue;
+        const int q = sl + 4 * r;  // clamped into the row: past the slice it meets x = 0
+        tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
+      }
+    }
+  }
+
   for (int64_t k = 0; k < a.K && !stop_code; ++k) {
     // Re-derive the lane coordinates from an opaque copy of the thread id each
     // step: otherwise the compiler hoists every lane-dependent address out of
@@ -193,19 +214,6 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     u64* xP = a.xP + (size_t)(k & 1) * G * eta;
     const bool has_next = k + 1 < a.K;
 
-    // every load of the step (rows past eta read row 0 and are never used); slots
-    // p * CPL + r < NPF were prefetched into LDS during the previous step
-    float4 tile[RP][CPL];
-#pragma unroll
-    for (int p = 0; p < RP; ++p) {
-      const float* rowp = a.A + (int64_t)(rowi[p] < 0 ? 0 : rowi[p]) * a.ld + c0;
-#pragma unroll
-      for (int r = 0; r < CPL; ++r) {
-        if (p * CPL + r < NPF) continue;
-        const int q = sl + 4 * r;  // clamped into the row: past the slice it meets x = 0
-        tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
-      }
-    }
 #pragma unroll
     for (int p = 0; p < PL; ++p)
 #pragma unroll
@@ -237,6 +245,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
         issue_prefetch();
       }
     }
+    int bad = 0;
     // reduce the owned rows over the G workgroups; c_t = (alpha/eta)(r_t - b)/||a||^2
 #pragma unroll
     for (int j = 0; j < kOwnMax; ++j) {
@@ -252,8 +261,12 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
           float c;
           if (orn[j] == 0.f) { c = NAN; set_status(a.status, ST_ZERO_ROW); }
           else c = (ak / (float)eta) * (sum - ob[j]) / orn[j];
-          if (a.two_hop) put_tagged(&a.xC[t], c, tag);
-          else cs[t] = c;
+          if (a.two_hop) {
+            put_tagged(&a.xC[t], c, tag);
+          } else {
+            cs[t] = c;
+            bad |= !isfinite(c);
+          }
         }
       }
     }
@@ -264,21 +277,32 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
                         lerr);
 #pragma unroll
       for (int i = 0; i < RP; ++i)
-        if (tid + kRtRowsPerPass * i < eta) cs[tid + kRtRowsPerPass * i] = v[i];
+        if (tid + kRtRowsPerPass * i < eta) {
+          cs[tid + kRtRowsPerPass * i] = v[i];
+          bad |= !isfinite(v[i]);
+        }
     }
     if (lerr) set_status(a.status, lerr);
-    if (__syncthreads_or(lerr)) { stop_code = ST_ABORTED; break; }
+    // One or-barrier agrees on every condition of the step (an expired wait, a non-finite
+    // coefficient, a bad index in the next step), so that the barriers after the update are
+    // plain ones, which do not wait for the next step's loads; every workgroup holds the same
+    // c_t and the same indices, so all stop at the same step.
+    int next_bad = 0;
+    if (__syncthreads_or(lerr | bad | nerr)) {
+      if (__syncthreads_or(lerr)) { stop_code = ST_ABORTED; break; }
+      if (__syncthreads_or(bad)) { stop_code = ST_NONFINITE; break; }
+      next_bad = 1;
+    }
 
     // transposed update: per chunk slot, sum over own rows, then the 16 lanes
     // holding that chunk, then the waves
     float cp[RP];
-    int bad = 0;
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
       const int t = p * kRtRowsPerPass + 16 * wave + ri;
       cp[p] = t < eta ? cs[t] : 0.f;
-      bad |= !isfinite(cp[p]);
     }
+    const bool load_next = has_next && !next_bad;
     if (a.y && g == 0)
       for (int t = tid; t < eta; t += kRtThreads) atomicAdd(&a.y[a.idx[k * (int64_t)eta + t]], -cs[t]);
 #pragma unroll
@@ -291,15 +315,23 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
         d.z += cp[p] * tile[p][r].z;
         d.w += cp[p] * tile[p][r].w;
       }
+      // chunk r of the tile is used up: its next-step slots load now
+      if (load_next) {
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+          if (p * CPL + r < NPF) continue;
+          const float* rowp = a.A + (int64_t)(rown[p] < 0 ? 0 : rown[p]) * a.ld + c0;
+          const int q = sl + 4 * r;
+          tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
+        }
+      }
       d.x = row16_sum(d.x);
       d.y = row16_sum(d.y);
       d.z = row16_sum(d.z);
       d.w = row16_sum(d.w);
       if (ri == 0) red[wave][sl + 4 * r] = d;
     }
-    // one barrier publishes red[] and agrees on a non-finite coefficient
-    // (every workgroup holds the same c_t, so all stop at this step)
-    if (__syncthreads_or(bad)) { stop_code = ST_NONFINITE; break; }
+    __syncthreads();  // publishes red[]
     if (tid < 4 * wq) {  // chunks past the slice carry clamped data: discarded
       const int q = tid >> 2, e = tid & 3;
       float dsum = 0.f;
@@ -312,9 +344,15 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       xv[tid] = shrink(z, a.lambda);
     }
     k_done = k + 1;
-    if constexpr (NPF > 0) __builtin_amdgcn_s_waitcnt(0);  // the prefetch has landed before the barrier
-    // the next step's indices were checked by every workgroup alike
-    const int next_bad = __syncthreads_or(nerr);
+    if constexpr (NPF > 0) {
+      // the LDS prefetch has landed before the barrier: the only loads this wave issued after
+      // it are the update's kHbmSlots next-step slots (older ones are done at vmcnt <= kHbmSlots)
+      if (wave >= kRtWaves / 2) {
+        if (load_next) __builtin_amdgcn_s_waitcnt(kWaitPrefetch);
+        else __builtin_amdgcn_s_waitcnt(0);
+      }
+    }
+    __syncthreads();
 
     if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
       const unsigned mtag = (unsigned)((k + 1) / a.check_every);
@@ -362,7 +400,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     for (int p = 0; p < RP; ++p) rowi[p] = rown[p];
   }
   if (stop_code && tid == 0) set_status(a.status, stop_code);
-  if constexpr (NPF > 0) __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_waitcnt(0);  // no load of a step that will not run stays in flight
   __syncthreads();
   for (int j = tid; j < wq * 4; j += kRtThreads) {
     const int64_t c = c0 + j;
