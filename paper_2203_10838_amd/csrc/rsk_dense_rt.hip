@@ -68,6 +68,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   __shared__ float4 red[kRtWaves][4 * CPL];       // per-wave column sums
   __shared__ float cs[RP * kRtRowsPerPass];        // step coefficients
   __shared__ double mon[2 * kRtWaves + 2];
+  __shared__ int orflag[2];  // step-parity flag words of the block OR
   // next-step tile slots prefetched into LDS: (p, r) with s = p * CPL + r < NPF; LDS slot s * NT + tid
   // holds tile[p][r] of thread tid. PL passes hold prefetched slots.
   constexpr int kPfBudget = 147456 / (NT * 16);
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   const int ot0 = a.two_hop ? g * per : 0;
   const int ot1 = (ot0 + per < eta) ? ot0 + per : eta;
 
+  if (tid < 2) orflag[tid] = 0;
   for (int j = tid; j < 16 * CPL; j += kRtThreads) {
     const int64_t c = c0 + j;
     const float z = (a.warm && j < wq * 4 && c < a.n) ? a.x_star[c] : 0.f;
@@ -287,12 +289,16 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     // coefficient, a bad index in the next step), so that the barriers after the update are
     // plain ones, which do not wait for the next step's loads; every workgroup holds the same
     // c_t and the same indices, so all stop at the same step.
-    int next_bad = 0;
-    if (__syncthreads_or(lerr | bad | nerr)) {
-      if (__syncthreads_or(lerr)) { stop_code = ST_ABORTED; break; }
-      if (__syncthreads_or(bad)) { stop_code = ST_NONFINITE; break; }
-      next_bad = 1;
-    }
+    // Block OR in one barrier: the flag word of this step's parity collects the bits, the other
+    // word (last read before the previous step's final barrier) is cleared for the next step.
+    const int flag = (lerr ? 1 : 0) | (bad ? 2 : 0) | (nerr ? 4 : 0);
+    if (flag) atomicOr(&orflag[k & 1], flag);
+    __syncthreads();
+    const int fl = orflag[k & 1];
+    if (tid == 0) orflag[(k + 1) & 1] = 0;
+    if (fl & 1) { stop_code = ST_ABORTED; break; }
+    if (fl & 2) { stop_code = ST_NONFINITE; break; }
+    const int next_bad = fl & 4;
 
     // transposed update: per chunk slot, sum over own rows, then the 16 lanes
     // holding that chunk, then the waves
