@@ -188,8 +188,8 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   }
 
   // The step's tile. Slots p * CPL + r < NPF come from the LDS prefetch; the others load from
-  // HBM: for step 0 here, for step k + 1 during step k's update, chunk by chunk as soon as the
-  // update has used it (rows past eta read row 0 and are never used).
+  // HBM: for step 0 here, for step k + 1 at the end of step k's update (rows past eta read row 0
+  // and are never used).
   float4 tile[RP][CPL];
   if (!stop_code && a.K > 0) {
 #pragma unroll
@@ -321,21 +321,25 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
         d.z += cp[p] * tile[p][r].z;
         d.w += cp[p] * tile[p][r].w;
       }
-      // chunk r of the tile is used up: its next-step slots load now
-      if (load_next) {
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-          if (p * CPL + r < NPF) continue;
-          const float* rowp = a.A + (int64_t)(rown[p] < 0 ? 0 : rown[p]) * a.ld + c0;
-          const int q = sl + 4 * r;
-          tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
-        }
-      }
       d.x = row16_sum(d.x);
       d.y = row16_sum(d.y);
       d.z = row16_sum(d.z);
       d.w = row16_sum(d.w);
       if (ri == 0) red[wave][sl + 4 * r] = d;
+    }
+    // the tile is used up: the next step's HBM slots load now, row by row (a row's chunks issued
+    // back to back keep the DRAM pages open), and stay in flight across the plain barriers
+    if (load_next) {
+#pragma unroll
+      for (int p = 0; p < RP; ++p) {
+        const float* rowp = a.A + (int64_t)(rown[p] < 0 ? 0 : rown[p]) * a.ld + c0;
+#pragma unroll
+        for (int r = 0; r < CPL; ++r) {
+          if (p * CPL + r < NPF) continue;
+          const int q = sl + 4 * r;
+          tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
+        }
+      }
     }
     __syncthreads();  // publishes red[]
     if (tid < 4 * wq) {  // chunks past the slice carry clamped data: discarded
