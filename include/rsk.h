@@ -284,7 +284,7 @@ int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, 
  *   order      device int32[nsys], a permutation of 0..nsys-1 (nullable: identity).
  *              Largest work first balances the CUs best. A repeated entry makes
  *              two groups write the same x (undefined result).
- *   wg_bytes   target row bytes per workgroup per step (0: 48 KiB). Must be the
+ *   wg_bytes   target row bytes per workgroup per step (0: 56 KiB). Must be the
  *              value given to rsk_workspace_size_batched.
  * Per-system status_dev[0] is reset by the call; it ends 0 or an RSK_ERR_*
  * code, status_dev[1] the steps completed. The kernels plan from the device

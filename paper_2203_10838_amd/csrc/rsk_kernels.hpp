@@ -178,7 +178,7 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream);
 // (workspace and LDS sizing) and on the device (tickets and offsets).
 constexpr int kBatchGcap = 256;                 // most workgroups one system may use
 constexpr size_t kBatchLdsCap = 80 * 1024;      // LDS of one workgroup: two fit a CU
-constexpr int64_t kBatchWgBytes = 48 * 1024;    // default row bytes per workgroup per step
+constexpr int64_t kBatchWgBytes = 56 * 1024;    // default row bytes per workgroup per step (swept: 16-96 KiB)
 constexpr int64_t kBatchRegionHead = 32;        // words: join counter + padding
 
 struct BatchPlan {
