@@ -116,6 +116,17 @@ __device__ __forceinline__ T lane_sum(T v, int width) {
   return v;
 }
 
+// Block OR in one barrier (HIP's __syncthreads_or costs three and waits for every outstanding
+// load): the bits go into the word of this step's parity, read after the barrier; the other
+// word, last read before an earlier barrier, is cleared for the next step.
+__device__ __forceinline__ int block_or(int* words, int v, int64_t k) {
+  if (v) atomicOr(&words[k & 1], v);
+  __syncthreads();
+  const int r = words[k & 1];
+  if (threadIdx.x == 0) words[(k + 1) & 1] = 0;
+  return r;
+}
+
 // c_t = (alpha_k/eta) (r_t - b_t) / ||a_t||^2 from the row's prefetched b and norm.
 template <typename T>
 __device__ __forceinline__ T coef_of(T s, T bt, T rn, T ak, int eta, int& zero_row) {
@@ -196,6 +207,9 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
   T* rqb = reinterpret_cast<T*>(smem + L.rq);
   V* red = reinterpret_cast<V*>(smem + L.red);
   double* mon = reinterpret_cast<double*>(smem + L.flags);
+  static_assert((2 * NW + 1) * sizeof(double) <= 96, "monitor words overlap the block-OR words");
+  int* orA = reinterpret_cast<int*>(smem + L.flags + 96);   // after the exchange: 1 aborted, 2 non-finite
+  int* orB = orA + 2;                                        // end of step: 4 bad index in the next step
   V* tile = reinterpret_cast<V*>(smem + L.tile);
   T* xr = reinterpret_cast<T*>(smem + L.xr);
 
@@ -230,6 +244,10 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
   const int rstride = NW * rpw;
   int64_t k_done = 0;
   int stop_code = 0;
+  if (tid < 4) orA[tid] = 0;  // orA[0..1] and orB[0..1]
+  // step 0's rows were fetched above; every workgroup checks all of them (this barrier also
+  // orders the clearing of the flag words)
+  int row_bad = __syncthreads_or(row_err);
 
   for (int64_t k = 0; k < a.K; ++k) {
     const unsigned tag = (unsigned)(k + 1);
@@ -246,7 +264,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
 
     // 1. the step's rows were fetched in the previous step; every workgroup
     //    checks all of them, so a bad index stops every workgroup at this step
-    if (__syncthreads_or(row_err)) { stop_code = ST_INDEX; break; }
+    if (row_bad) { stop_code = ST_INDEX; break; }
     const bool has_next = k + 1 < a.K;
     const int32_t* tk1 = a.idx + (k + 1) * (int64_t)eta;
     int ni[PF];
@@ -422,12 +440,13 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
       for (int t = tid; t < eta; t += NT) cs[t] = wait_tagged<T>(&a.xC[(size_t)t * W], tag, lerr);
     }
     if (zero_row) set_status(a.status, ST_ZERO_ROW);
-    __syncthreads();
+    // every path above wrote cs[t] for t = tid, tid + NT, ...: each thread checks its own
     int bad = 0;
     for (int t = tid; t < eta; t += NT) bad |= !isfinite(cs[t]);
     if (lerr) set_status(a.status, lerr);
-    const int any_err = __syncthreads_or(lerr);
-    if (__syncthreads_or(bad) || any_err) { stop_code = any_err ? ST_ABORTED : ST_NONFINITE; break; }
+    // one barrier publishes cs[] and agrees on an expired wait or a non-finite coefficient
+    const int fl = block_or(orA, (lerr ? 1 : 0) | (bad ? 2 : 0), k);
+    if (fl) { stop_code = (fl & 1) ? ST_ABORTED : ST_NONFINITE; break; }
 
     if (a.y && g == 0)
       for (int t = tid; t < eta; t += NT) atomicAdd(&a.y[tau[t]], -cs[t]);
@@ -532,9 +551,9 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
         }
       }
     }
-    row_err = next_err;
-    // columns past n inside the last chunk stay zero: their tile entries are zero
-    __syncthreads();
+    // columns past n inside the last chunk stay zero: their tile entries are zero; the
+    // barrier agrees on a bad index among the next step's rows
+    row_bad = block_or(orB, next_err ? 4 : 0, k) & 4;
     k_done = k + 1;
     // 6. monitor
     if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
