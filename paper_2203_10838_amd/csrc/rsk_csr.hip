@@ -106,10 +106,12 @@ __global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
   __shared__ T cs[kCsrMaxEta];
   __shared__ double wmax[kCsrWaves];
   __shared__ double mon[2 * kCsrWaves];
+  __shared__ int orw[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int eta = a.eta;
   // one sampled row per thread; eta <= 512 keeps each thread's row in registers
   const bool resident = eta <= kCsrThreads;
+  if (tid < 2) orw[tid] = 0;
 
   for (int64_t j = tid; j < a.n; j += kCsrThreads) {
     const T z = a.warm ? a.x_star[j] : T(0);
@@ -165,15 +167,15 @@ __global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
       if (resident && p1 - p0 > kRowChunk) load_chunk(a, p0, p1, 0, jc, vv);
     }
     if (lerr) set_status(a.status, lerr);
-    if (__syncthreads_or(lerr)) {
-      stop_code = ST_INDEX;  // the thread that found the fault set the exact code first
-      break;
-    }
+    // each thread checks the coefficients it wrote; one barrier publishes cs[] and wmax[] and
+    // agrees on a fault (the thread that found it set the exact code first) or a non-finite c_t
     int bad = 0;
     for (int t = tid; t < eta; t += kCsrThreads) bad |= !isfinite(cs[t]);
     for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
     if (lane == 0) wmax[wave] = vmax;
-    if (__syncthreads_or(bad)) { stop_code = ST_NONFINITE; break; }
+    const int fl = block_or(orw, (lerr ? 1 : 0) | (bad ? 2 : 0), k);
+    if (fl & 1) { stop_code = ST_INDEX; break; }
+    if (fl & 2) { stop_code = ST_NONFINITE; break; }
     double gmax = 0.0;
     for (int w = 0; w < kCsrWaves; ++w) gmax = fmax(gmax, wmax[w]);
     // power-of-two quantum q = 2^(e-40): |v/q| < 2^41

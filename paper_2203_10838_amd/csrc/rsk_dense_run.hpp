@@ -116,17 +116,6 @@ __device__ __forceinline__ T lane_sum(T v, int width) {
   return v;
 }
 
-// Block OR in one barrier (HIP's __syncthreads_or costs three and waits for every outstanding
-// load): the bits go into the word of this step's parity, read after the barrier; the other
-// word, last read before an earlier barrier, is cleared for the next step.
-__device__ __forceinline__ int block_or(int* words, int v, int64_t k) {
-  if (v) atomicOr(&words[k & 1], v);
-  __syncthreads();
-  const int r = words[k & 1];
-  if (threadIdx.x == 0) words[(k + 1) & 1] = 0;
-  return r;
-}
-
 // c_t = (alpha_k/eta) (r_t - b_t) / ||a_t||^2 from the row's prefetched b and norm.
 template <typename T>
 __device__ __forceinline__ T coef_of(T s, T bt, T rn, T ak, int eta, int& zero_row) {

@@ -99,6 +99,17 @@ __device__ __forceinline__ void wait_tagged_batch(const u64* base, size_t stride
   }
 }
 
+// Block OR in one barrier (HIP's __syncthreads_or costs three and waits for every outstanding
+// load): the bits go into the word of this step's parity, read after the barrier; the other
+// word, last read before an earlier barrier, is cleared for the next step.
+__device__ __forceinline__ int block_or(int* words, int v, int64_t k) {
+  if (v) atomicOr(&words[k & 1], v);
+  __syncthreads();
+  const int r = words[k & 1];
+  if (threadIdx.x == 0) words[(k + 1) & 1] = 0;
+  return r;
+}
+
 // First error wins.
 __device__ __forceinline__ void set_status(int* status, int code) {
   if (code) atomicCAS(status, 0, code);
