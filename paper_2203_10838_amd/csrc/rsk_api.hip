@@ -267,9 +267,9 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
 }
 
 struct MultiPlan {
-  int S, eta_pad;
+  int S, eta_pad, S2;
   int64_t kspan;
-  size_t offY, offC, bytes;
+  size_t offY, offC, offW, bytes;
 };
 
 int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiPlan* pl) {
@@ -288,9 +288,18 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   pl->kspan = (A->n + S - 1) / S;
   pl->kspan = (pl->kspan + 15) / 16 * 16;
   pl->S = (int)((A->n + pl->kspan - 1) / pl->kspan);
+  // the A_tau^T products write n x R: with fewer 64 x 64 tiles than CUs their sampled rows
+  // are split over S2 workgroups (at least 64 rows each) and summed in a second kernel
+  const int att_tiles = (int)((A->n + 63) / 64) * ((R + 63) / 64);
+  int S2 = cus / att_tiles;
+  const int max_s2 = (p->eta + 63) / 64;
+  if (S2 > max_s2) S2 = max_s2;
+  S2 = S2 >= 8 ? 8 : S2 >= 4 ? 4 : S2 >= 2 ? 2 : 1;  // the reduction kernels take 2, 4 or 8
+  pl->S2 = S2;
   size_t o = 0;
   pl->offY = o; o = align256(o + (size_t)pl->S * pl->eta_pad * R * sizeof(float));
   pl->offC = o; o = align256(o + (size_t)pl->eta_pad * R * sizeof(float));
+  pl->offW = o; o = align256(o + (S2 > 1 ? (size_t)S2 * A->n * R * sizeof(float) : 0));
   pl->bytes = o;
   return RSK_OK;
 }
@@ -358,6 +367,10 @@ void fill_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_param
   a.status = p->status_dev;
   a.Y = (float*)(w + pl.offY); a.C = (float*)(w + pl.offC);
   a.S = pl.S; a.eta_pad = pl.eta_pad; a.kspan = pl.kspan;
+  // the row-split epilogue moves float4 of X* and X: used only when both are 16-byte aligned
+  const bool al = ((uintptr_t)X_star) % 16 == 0 && ((uintptr_t)X) % 16 == 0;
+  a.S2 = (pl.S2 > 1 && al) ? pl.S2 : 1;
+  a.Wp = a.S2 > 1 ? (float*)(w + pl.offW) : nullptr;
 }
 
 // Adjoint workspace: the forward's (Y, C) then Zh, Rh, x, zbar and the partial sums.

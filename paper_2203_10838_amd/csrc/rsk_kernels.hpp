@@ -145,6 +145,8 @@ struct MultiRhsArgs {
   float* C;               // eta_pad x R coefficients
   int S, eta_pad;
   int64_t kspan;
+  int S2 = 1;             // row splits of the A_tau^T products (small n x R outputs)
+  float* Wp = nullptr;    // S2 x n x R partials of A_tau^T C when S2 > 1
 };
 // ckpt (nullable): x*_k is copied to ckpt[k / ckpt_every] before every step k with k % ckpt_every == 0.
 hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckpt = nullptr, int64_t ckpt_every = 1);

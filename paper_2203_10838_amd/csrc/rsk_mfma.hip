@@ -258,6 +258,75 @@ __global__ __launch_bounds__(NTH) void gemm_att_c_update(const float* __restrict
       }
 }
 
+// Row-split A_tau^T C for outputs too small to fill the chip: split s (blockIdx.z) takes the
+// sampled rows [s eta / S2, (s + 1) eta / S2) and writes its raw 64 x 64 tile to Wp[s].
+// grid = (ceil(n/64), R/64, S2).
+__global__ __launch_bounds__(NTH) void gemm_att_partial(const float* __restrict__ A, int64_t ld, int64_t n,
+                                                        const int32_t* __restrict__ tau, int eta,
+                                                        const float* __restrict__ C, int R, float* __restrict__ Wp,
+                                                        const int* status) {
+  if (status[0]) return;
+  __shared__ __align__(16) float As[SK][LDP];
+  __shared__ __align__(16) float Bs[SK][LDP];
+  __shared__ int taus[kMaxTauLds];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t j0 = (int64_t)blockIdx.x * BM;
+  const int r0 = blockIdx.y * BN;
+  const int s = blockIdx.z, S2 = gridDim.z;
+  const int t0 = (int)((int64_t)s * eta / S2), t1 = (int)((int64_t)(s + 1) * eta / S2);
+  stage_tau(tau + t0, t1 - t0, taus);
+  __syncthreads();
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  att_mainloop(A, ld, n, taus, t1 - t0, C + (size_t)t0 * R, R, j0, r0, As, Bs, acc);
+  float* W = Wp + (size_t)s * n * R;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t jj = j0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int r = r0 + wn * 32 + j * 16 + (lane & 15);
+        if (jj < n && r < R) W[(size_t)jj * R + r] = acc[i][j][v];
+      }
+}
+
+// Epilogue of the row-split update: Zout = Zin - sum_s Wp[s] (s ascending), X = S_lambda(Zout),
+// four elements a thread (R % 4 == 0), all S2 partial loads issued before the sum.
+template <int S2>
+__global__ __launch_bounds__(NTH) void att_reduce_update(const float* __restrict__ Wp, int64_t nr4,
+                                                         const float* Zin, float* Zout, float* __restrict__ X,
+                                                         float lambda, const int* status) {
+  if (status[0]) return;
+  const float4* W4 = reinterpret_cast<const float4*>(Wp);
+  for (int64_t e = blockIdx.x * (int64_t)NTH + threadIdx.x; e < nr4; e += (int64_t)gridDim.x * NTH) {
+    float4 w[S2];
+#pragma unroll
+    for (int q = 0; q < S2; ++q) w[q] = W4[q * nr4 + e];
+    float4 z = reinterpret_cast<const float4*>(Zin)[e];
+    float4 t = w[0];
+#pragma unroll
+    for (int q = 1; q < S2; ++q) {
+      t.x += w[q].x;
+      t.y += w[q].y;
+      t.z += w[q].z;
+      t.w += w[q].w;
+    }
+    z.x -= t.x;
+    z.y -= t.y;
+    z.z -= t.z;
+    z.w -= t.w;
+    reinterpret_cast<float4*>(Zout)[e] = z;
+    reinterpret_cast<float4*>(X)[e] =
+        make_float4(shrink(z.x, lambda), shrink(z.y, lambda), shrink(z.z, lambda), shrink(z.w, lambda));
+  }
+}
+
 __global__ void init_multirhs(float* Xs, float* X, size_t total, float lambda, int warm) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const float z = warm ? Xs[e] : 0.f;
@@ -278,8 +347,21 @@ static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, fl
                      a.eta_pad, a.kspan, a.status);
   hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
                      a.row_w, a.alpha, a.alpha_k, k, a.C, rh, a.status);
-  hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R, zin,
-                     zout, a.x, a.lambda, a.status);
+  if (a.S2 > 1) {
+    hipLaunchKernelGGL(gemm_att_partial, dim3(gn, gr, a.S2), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C,
+                       a.R, a.Wp, a.status);
+    const int64_t nr4 = a.n * a.R / 4;
+    const dim3 rg((unsigned)((nr4 + NTH - 1) / NTH < 1024 ? (nr4 + NTH - 1) / NTH : 1024));
+    if (a.S2 == 2)
+      hipLaunchKernelGGL(att_reduce_update<2>, rg, dim3(NTH), 0, stream, a.Wp, nr4, zin, zout, a.x, a.lambda, a.status);
+    else if (a.S2 == 4)
+      hipLaunchKernelGGL(att_reduce_update<4>, rg, dim3(NTH), 0, stream, a.Wp, nr4, zin, zout, a.x, a.lambda, a.status);
+    else
+      hipLaunchKernelGGL(att_reduce_update<8>, rg, dim3(NTH), 0, stream, a.Wp, nr4, zin, zout, a.x, a.lambda, a.status);
+  } else {
+    hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
+                       zin, zout, a.x, a.lambda, a.status);
+  }
   const int32_t* tn = (k + 1 < a.K) ? tk + a.eta : tk;
   hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, tn, (k + 1 < a.K) ? a.eta : 0, a.m, a.status,
                      k + 1);
@@ -488,6 +570,63 @@ __global__ __launch_bounds__(NTH) void gemm_att_adj(const float* __restrict__ A,
   if (threadIdx.x == 0) lam_part[blk] = t;
 }
 
+// Epilogue of the row-split adjoint product: xbar = sum_s Wp[s] (s ascending), then as in
+// gemm_att_adj. grid = (ceil(n/64), R/64), the same blocks (and lambdabar partials) as gemm_att_adj;
+// each thread takes four float4 of the block's 64 x 64 tile, all loads issued before use.
+template <int S2>
+__global__ __launch_bounds__(NTH) void att_reduce_adj(const float* __restrict__ Wp, int64_t n, int R,
+                                                      const float* __restrict__ Zk, float* __restrict__ zbar,
+                                                      float lambda, double* __restrict__ lam_part, const int* status) {
+  __shared__ double red[4];
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  if (status[0]) {
+    if (threadIdx.x == 0) lam_part[blk] = 0.0;
+    return;
+  }
+  const int64_t j0 = (int64_t)blockIdx.x * BM;
+  const int r0 = blockIdx.y * BN;
+  const size_t nr = (size_t)n * R;
+  constexpr int kPer = BM * BN / (4 * NTH);
+  float4 w[kPer][S2], zk[kPer];
+  size_t off[kPer];
+  bool ok[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = 4 * (threadIdx.x + NTH * u);
+    const int64_t jj = j0 + e / BN;
+    const int r = r0 + e % BN;
+    ok[u] = jj < n && r < R;
+    off[u] = ok[u] ? (size_t)jj * R + r : 0;
+#pragma unroll
+    for (int q = 0; q < S2; ++q) w[u][q] = *reinterpret_cast<const float4*>(Wp + q * nr + off[u]);
+    zk[u] = *reinterpret_cast<const float4*>(Zk + off[u]);
+  }
+  double lp = 0.0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (!ok[u]) continue;
+    float4 xb = w[u][0];
+#pragma unroll
+    for (int q = 1; q < S2; ++q) {
+      xb.x += w[u][q].x;
+      xb.y += w[u][q].y;
+      xb.z += w[u][q].z;
+      xb.w += w[u][q].w;
+    }
+    const float zz[4] = {zk[u].x, zk[u].y, zk[u].z, zk[u].w};
+    const float xx[4] = {xb.x, xb.y, xb.z, xb.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (fabsf(zz[c]) > lambda) {
+        zbar[off[u] + c] += xx[c];
+        lp -= (zz[c] > 0.f ? 1.0 : -1.0) * (double)xx[c];
+      }
+    }
+  }
+  const double t = block_sum_d(lp, red);
+  if (threadIdx.x == 0) lam_part[blk] = t;
+}
+
 // alpha_bar[k] = sum of the step's partials; lambda_bar = seed partials, then steps 0..K-1, each in order.
 __global__ __launch_bounds__(256) void adj_finish(const double* __restrict__ abar_part,
                                                   const double* __restrict__ lam_part, int64_t K, int nblk_att,
@@ -566,9 +705,25 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
                          d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
       hipLaunchKernelGGL(adj_bbar, dim3((unsigned)(((size_t)a.eta * a.R + 255) / 256)), dim3(256),
                          adj_bbar_lds(a.eta), stream, tk, a.eta, a.C, a.R, d.Bbar, a.status);
-      hipLaunchKernelGGL(gemm_att_adj, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
-                         d.Zh + (size_t)j * total, d.zbar, a.lambda,
-                         d.lam_part + kAdjSeedBlocks + (size_t)k * nblk_att, a.status);
+      if (a.S2 > 1) {
+        hipLaunchKernelGGL(gemm_att_partial, dim3(gn, gr, a.S2), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta,
+                           a.C, a.R, a.Wp, a.status);
+        const float* zk = d.Zh + (size_t)j * total;
+        double* lp = d.lam_part + kAdjSeedBlocks + (size_t)k * nblk_att;
+        if (a.S2 == 2)
+          hipLaunchKernelGGL(att_reduce_adj<2>, dim3(gn, gr), dim3(NTH), 0, stream, a.Wp, a.n, a.R, zk, d.zbar,
+                             a.lambda, lp, a.status);
+        else if (a.S2 == 4)
+          hipLaunchKernelGGL(att_reduce_adj<4>, dim3(gn, gr), dim3(NTH), 0, stream, a.Wp, a.n, a.R, zk, d.zbar,
+                             a.lambda, lp, a.status);
+        else
+          hipLaunchKernelGGL(att_reduce_adj<8>, dim3(gn, gr), dim3(NTH), 0, stream, a.Wp, a.n, a.R, zk, d.zbar,
+                             a.lambda, lp, a.status);
+      } else {
+        hipLaunchKernelGGL(gemm_att_adj, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
+                           d.Zh + (size_t)j * total, d.zbar, a.lambda,
+                           d.lam_part + kAdjSeedBlocks + (size_t)k * nblk_att, a.status);
+      }
     }
   }
   hipLaunchKernelGGL(adj_finish, dim3(1), dim3(256), 0, stream, d.abar_part, d.lam_part, a.K, nblk_att, d.alpha_bar,
