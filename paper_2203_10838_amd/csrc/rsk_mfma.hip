@@ -474,7 +474,7 @@ __host__ __device__ inline int adj_hash_size(int eta) {
   while (h < 2 * eta) h <<= 1;
   return h;
 }
-size_t adj_bbar_lds(int eta) { return (size_t)adj_hash_size(eta) * 12 + (size_t)eta * 4; }
+size_t adj_bbar_lds(int eta) { return (size_t)adj_hash_size(eta) * 12 + (size_t)eta * 8 + 16; }
 
 __global__ __launch_bounds__(256) void adj_bbar(const int32_t* __restrict__ tau, int eta,
                                                 const float* __restrict__ Rbar, int R, float* __restrict__ Bbar,
@@ -486,11 +486,14 @@ __global__ __launch_bounds__(256) void adj_bbar(const int32_t* __restrict__ tau,
   int* hmin = hsm + H;
   int* hcnt = hsm + 2 * H;
   int* st = hsm + 3 * H;
+  int* dup = st + eta;   // positions of the repeated rows, in no particular order
+  int* ndup = dup + eta;
   for (int i = threadIdx.x; i < H; i += blockDim.x) {
     hkey[i] = -1;
     hmin[i] = INT_MAX;
     hcnt[i] = 0;
   }
+  if (threadIdx.x == 0) *ndup = 0;
   for (int t = threadIdx.x; t < eta; t += blockDim.x) st[t] = tau[t];
   __syncthreads();
   for (int t = threadIdx.x; t < eta; t += blockDim.x) {
@@ -505,6 +508,13 @@ __global__ __launch_bounds__(256) void adj_bbar(const int32_t* __restrict__ tau,
     atomicAdd(&hcnt[h], 1);
   }
   __syncthreads();
+  for (int t = threadIdx.x; t < eta; t += blockDim.x) {
+    const int key = st[t];
+    int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
+    while (hkey[h] != key) h = (h + 1) & (H - 1);
+    if (hcnt[h] > 1) dup[atomicAdd(ndup, 1)] = t;
+  }
+  __syncthreads();
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (e >= (size_t)eta * R) return;
   const int t = (int)(e / R), r = (int)(e % R);
@@ -513,9 +523,19 @@ __global__ __launch_bounds__(256) void adj_bbar(const int32_t* __restrict__ tau,
   while (hkey[h] != key) h = (h + 1) & (H - 1);
   if (hmin[h] != t) return;
   float sum = Rbar[(size_t)t * R + r];
-  if (hcnt[h] > 1)
-    for (int u = t + 1; u < eta; ++u)
-      if (st[u] == key) sum += Rbar[(size_t)u * R + r];
+  const int cnt = hcnt[h], nd = *ndup;
+  // the other occurrences of the row, in ascending position: each pass takes the smallest
+  // position above the last one among the repeated rows
+  for (int c = 1, last = t; c < cnt; ++c) {
+    int next = INT_MAX;
+    for (int i = 0; i < nd; ++i) {
+      const int u = dup[i];
+      if (u > last && u < next && st[u] == key) next = u;
+    }
+    if (next == INT_MAX) break;  // cannot happen: every occurrence of a repeated row is listed
+    sum += Rbar[(size_t)next * R + r];
+    last = next;
+  }
   Bbar[(int64_t)key * R + r] -= sum;
 }
 
