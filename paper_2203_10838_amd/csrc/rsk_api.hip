@@ -229,7 +229,7 @@ int32_t plan_csr(const rsk_csr* A, const rsk_params* p, CsrPlan* pl) {
     if (G < 1 || (maxres > 0 && G > maxres)) return RSK_ERR_UNSUPPORTED;
     if ((p->eta + rpp * G - 1) / (rpp * G) > rsk::kCsrGridMaxPasses) return RSK_ERR_UNSUPPORTED;
     pl->G = G;
-    pl->offBar = o; o += 64;
+    pl->offBar = o; o += 9 * 128;  // global barrier counter and 8 group counters, 128 bytes apart
     pl->offEmax = o; o += 64;
     pl->offM = o; o = align256(o + (size_t)G * 4 * sizeof(u64));
   }

@@ -307,14 +307,25 @@ __device__ __forceinline__ T sum32(T v) {
   return swap16f(v);
 }
 
-// Arrive at the grid barrier and wait for the counter to reach `target`.
-// Returns false if the bounded wait expired.
-__device__ __forceinline__ bool grid_sync(u64* bar, u64 target) {
+// Grid barrier number `nbar` (1, 2, ...; the counters only grow). Two levels, so that no
+// counter takes more than a group's worth of atomics: workgroup g arrives on the counter of
+// group g % 8 (workgroups are dispatched to the XCDs in turn), the last arriver of a group
+// moves the global counter on, and every workgroup waits for all groups. Counters are 128
+// bytes apart. Returns false if the bounded wait expired.
+constexpr int kBarGroups = 8;
+constexpr int kBarStride = 16;  // u64 words between counters
+__device__ __forceinline__ bool grid_sync(u64* bar, u64 nbar, int G) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's memory operations are complete
   __syncthreads();
   __shared__ int ok;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int grp = (int)(blockIdx.x % kBarGroups);
+    const int ngroups = G < kBarGroups ? G : kBarGroups;
+    const u64 members = (u64)((G - grp + kBarGroups - 1) / kBarGroups);
+    u64* gbar = bar + (size_t)kBarStride * (1 + grp);
+    const u64 old = __hip_atomic_fetch_add(gbar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == members * nbar) __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 target = (u64)ngroups * nbar;
     unsigned spins = 0;
     int good = 1;
     while (xload(bar) < target) {
@@ -350,7 +361,7 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
     if (!a.warm) st_ag(a.x_star + j, z);
     st_ag(a.x + j, shrink(z, a.lambda));
   }
-  if (!grid_sync(a.bar, (u64)G * ++nbar)) stop_code = ST_ABORTED;
+  if (!grid_sync(a.bar, ++nbar, G)) stop_code = ST_ABORTED;
 
   int64_t k_done = 0;
   for (int64_t k = 0; k < a.K && !stop_code; ++k) {
@@ -396,7 +407,7 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
       if (m > 0.0 && isfinite(m))
         __hip_atomic_fetch_max(a.emax + (k & 1), ilogb(m) + kEBias, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!grid_sync(a.bar, (u64)G * ++nbar)) { stop_code = ST_ABORTED; break; }
+    if (!grid_sync(a.bar, ++nbar, G)) { stop_code = ST_ABORTED; break; }
     if (ld_ag(a.status)) { stop_code = -1; break; }  // the fault was recorded by the workgroup that saw it
     const int eb = ld_ag(a.emax + (k & 1));
     if (g == 0 && tid == 0) st_ag(a.emax + ((k + 1) & 1), 0);  // read by everyone two barriers ago
@@ -416,7 +427,7 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
           }
         }
       }
-      if (!grid_sync(a.bar, (u64)G * ++nbar)) { stop_code = ST_ABORTED; break; }
+      if (!grid_sync(a.bar, ++nbar, G)) { stop_code = ST_ABORTED; break; }
       // C. apply each touched column once
       for (int ps = 0; ps < passes; ++ps) {
         const int t = ps * RPP * G + g * RPP + hw;
@@ -437,9 +448,9 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
       }
     } else {
       ++nbar;  // keep the barrier count of the skipped accumulation phase
-      if (!grid_sync(a.bar, (u64)G * nbar)) { stop_code = ST_ABORTED; break; }
+      if (!grid_sync(a.bar, nbar, G)) { stop_code = ST_ABORTED; break; }
     }
-    if (!grid_sync(a.bar, (u64)G * ++nbar)) { stop_code = ST_ABORTED; break; }
+    if (!grid_sync(a.bar, ++nbar, G)) { stop_code = ST_ABORTED; break; }
     k_done = k + 1;
 
     if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
