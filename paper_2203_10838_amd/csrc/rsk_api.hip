@@ -14,6 +14,10 @@ constexpr int kMaxEtaDense = 16384;
 constexpr size_t kTileCacheBytes = 96 * 1024;
 constexpr size_t kBytesPerWg = 96 * 1024;  // target row bytes per workgroup per step
 using rsk::kOneHopWords;
+// the automatic choice takes two row groups of the register-tile kernel for eta in this range
+// (1024-thread workgroups; below it the step is bound by the exchange, and at 512 threads the
+// third exchange hop costs more than the wider row pieces save)
+constexpr int kRtTwoGroupMinEta = 128, kRtTwoGroupMaxEta = 768;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t elem_size(int32_t dt) { return dt == RSK_F64 ? 8 : 4; }
@@ -41,7 +45,7 @@ int32_t check_params(const rsk_params* p, int64_t m) {
   if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
   if (!p->rownorm2 || !p->status_dev) return RSK_ERR_INVALID_ARG;
   if (p->check_every < 0 || !(p->tol >= 0.0) || p->grid < 0) return RSK_ERR_INVALID_ARG;
-  if (p->kernel < 0 || p->kernel > 2) return RSK_ERR_INVALID_ARG;
+  if (p->kernel < 0 || p->kernel > 3) return RSK_ERR_INVALID_ARG;
   if (p->x_ref && p->check_every > 0 && p->err_hist == nullptr && p->tol <= 0.0) return RSK_ERR_INVALID_ARG;
   (void)m;
   return RSK_OK;
@@ -49,17 +53,19 @@ int32_t check_params(const rsk_params* p, int64_t m) {
 
 struct DensePlan {
   int kernel;  // 1 general, 2 register tile
-  int nt, rp, cpl;
+  int nt, rp, cpl, rg;
   int vec, G, two_hop, tile_cache, wq_max, lpr, W;
   int64_t nchunks;
-  size_t offP, offC, offM, bytes;
+  size_t offP, offC, offM, offU, bytes;
 };
 
-size_t dense_ws_layout(int Gmax, int eta, int W, DensePlan* pl) {
+// uwords: words of the register-tile kernel's third exchange hop (0 with one row group)
+size_t dense_ws_layout(int Gmax, int eta, int W, size_t uwords, DensePlan* pl) {
   size_t o = 0;
   pl->offP = o; o = align256(o + 2 * (size_t)Gmax * eta * W * sizeof(u64));
   pl->offC = o; o = align256(o + (size_t)eta * W * sizeof(u64));
   pl->offM = o; o = align256(o + (size_t)Gmax * 4 * sizeof(u64));
+  pl->offU = o; o = align256(o + uwords * sizeof(u64));
   pl->bytes = o;
   return o;
 }
@@ -79,44 +85,55 @@ int32_t check_dense(const rsk_dense* A) {
   return RSK_OK;
 }
 
-// float32 register-tile plan: one 1024-thread workgroup per CU, slices of at
-// most 5 units of 16 floats, eta <= 1024. Returns false if it does not apply.
-bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
+// float32 register-tile plan: one 1024-thread workgroup per CU (512 for eta > 768), eta <= 1024,
+// rg row groups of G/rg column slices, each slice at most 5*rg units of 16 floats. Returns false if
+// it does not apply.
+bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, int rg, DensePlan* pl) {
   if (A->dtype != RSK_F32 || (A->n % 4) != 0 || (A->ld % 4) != 0 || (((uintptr_t)A->val) % 16) != 0) return false;
   const int64_t nchunks = (A->n + 3) / 4;
   const int64_t nunits = (nchunks + 3) / 4;
   const int cus = device_cus();
   int G = p->grid > 0 ? p->grid : cus;
-  if (G > nunits) G = (int)nunits;
+  if (G > nunits * rg) G = (int)(nunits * rg);
+  if (rg > 1 && G >= 16) G -= G % 8;  // whole XCD rounds keep a slice's groups on one XCD
+  G -= G % rg;
   if (G > 256) return false;
-  if (G < 1) return false;
-  const int cpl = (int)((nunits + G - 1) / G);
+  if (G < rg) return false;
+  const int C = G / rg;
+  const int64_t upm = (nunits + C - 1) / C;  // units of the widest slice
+  const int cpl = (int)((upm + rg - 1) / rg);
   if (cpl > rsk::kRtMaxCPL || p->eta > rsk::kRtMaxEta) return false;
   const int nt = p->eta <= 768 ? 1024 : 512;
-  const int rp = (p->eta + nt / 4 - 1) / (nt / 4);
-  if (rsk::dense_rt_max_grid(nt, rp, cpl) < G) return false;
-  pl->kernel = 2; pl->nt = nt; pl->rp = rp; pl->cpl = cpl;
+  const int etaR = (p->eta + rg - 1) / rg;
+  const int rpp = nt / (4 * rg);  // group rows of one pass
+  const int rp = (etaR + rpp - 1) / rpp;
+  if (rsk::dense_rt_max_grid(nt, rp, cpl, rg) < G) return false;
+  pl->kernel = 2; pl->nt = nt; pl->rp = rp; pl->cpl = cpl; pl->rg = rg;
   pl->vec = 4; pl->W = 1; pl->nchunks = nchunks; pl->G = G;
-  pl->wq_max = 4 * cpl; pl->lpr = 4; pl->tile_cache = 0;
-  pl->two_hop = ((int64_t)G * p->eta) > kOneHopWords;
+  pl->wq_max = 4 * rg * cpl; pl->lpr = 4; pl->tile_cache = 0;
+  pl->two_hop = ((int64_t)C * etaR) > kOneHopWords;
   // each wave reduces at most kRtOwnMax rows per step
-  const int waves = nt / 64;
-  if (!pl->two_hop && p->eta > rsk::kRtOwnMax * waves) pl->two_hop = 1;
-  if (pl->two_hop && (p->eta + G - 1) / G > rsk::kRtOwnMax * waves) return false;
+  const int own = rsk::kRtOwnMax * (nt / 64);
+  if (!pl->two_hop && etaR > own) pl->two_hop = 1;
+  if (pl->two_hop && (etaR + C - 1) / C > own) return false;
   const int cap = dense_grid_cap(A, p);
-  dense_ws_layout(cap > G ? cap : G, p->eta, 1, pl);
+  const size_t uwords = rg > 1 ? 2 * (size_t)G * 16 * rg * cpl : 0;
+  dense_ws_layout(cap > G ? cap : G, p->eta, 1, uwords, pl);
   return true;
 }
 
 template <typename T>
 int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   const size_t s = sizeof(T);
-  pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0;
+  pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0; pl->rg = 1;
   // the register-tile kernel pays one cross-CU exchange per step on a full
   // grid: worth it once a step moves more than a few hundred KB of rows
+  if (p->kernel == 3) return plan_dense_rt(A, p, 2, pl) ? RSK_OK : RSK_ERR_UNSUPPORTED;
   if (p->kernel == 2 || (p->kernel == 0 && A->dtype == RSK_F32 &&
                          (double)p->eta * (double)A->n * 4.0 >= 512.0 * 1024)) {
-    if (plan_dense_rt(A, p, pl)) return RSK_OK;
+    if (p->kernel == 0 && p->eta >= kRtTwoGroupMinEta && p->eta <= kRtTwoGroupMaxEta && plan_dense_rt(A, p, 2, pl))
+      return RSK_OK;
+    if (plan_dense_rt(A, p, 1, pl)) return RSK_OK;
     if (p->kernel == 2) return RSK_ERR_UNSUPPORTED;
   }
   const int vmax = (int)(16 / s);
@@ -158,7 +175,7 @@ int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
     if (p->grid > 0) return RSK_ERR_UNSUPPORTED;
     G = maxg;
   }
-  dense_ws_layout(cap > pl->G ? cap : pl->G, p->eta, pl->W, pl);
+  dense_ws_layout(cap > pl->G ? cap : pl->G, p->eta, pl->W, 0, pl);
   return RSK_OK;
 }
 
@@ -182,12 +199,14 @@ int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, vo
   a.xref = (const T*)p->x_ref; a.check_every = p->x_ref ? p->check_every : 0; a.tol = p->tol;
   a.err_hist = p->err_hist; a.status = p->status_dev;
   a.xP = (u64*)(w + pl.offP); a.xC = (u64*)(w + pl.offC); a.xM = (u64*)(w + pl.offM);
+  a.xU = pl.rg > 1 ? (u64*)(w + pl.offU) : nullptr;
   a.G = pl.G; a.two_hop = pl.two_hop; a.tile_cache = pl.tile_cache;
   a.nchunks = pl.nchunks; a.wq_max = pl.wq_max; a.lpr = pl.lpr;
   if (rsk::launch_zero_words((u64*)w, pl.bytes / sizeof(u64), stream) != hipSuccess) return RSK_ERR_HIP;
   if (zero_status && rsk::launch_zero_status(p->status_dev, stream) != hipSuccess) return RSK_ERR_HIP;
   if (pl.kernel == 2) {
-    if (rsk::launch_dense_rt(*reinterpret_cast<rsk::DenseArgs<float>*>(&a), pl.nt, pl.rp, pl.cpl, stream) != hipSuccess)
+    if (rsk::launch_dense_rt(*reinterpret_cast<rsk::DenseArgs<float>*>(&a), pl.nt, pl.rp, pl.cpl, pl.rg, stream) !=
+        hipSuccess)
       return RSK_ERR_HIP;
     return RSK_OK;
   }
@@ -217,6 +236,7 @@ template <typename T>
 int32_t plan_csr(const rsk_csr* A, const rsk_params* p, CsrPlan* pl) {
   const int cus = device_cus() > 0 ? device_cus() : 1;
   const int rpp = rsk::kCsrGridRowsPerPass;
+  if (p->kernel == 3) return RSK_ERR_INVALID_ARG;  // a dense kernel
   const bool grid = p->kernel == 2 || (p->kernel == 0 && p->eta >= 64);
   pl->kernel = grid ? 2 : 1;
   pl->G = 1;

@@ -3,12 +3,19 @@
 // Same iteration and exchange protocol as rska_dense_persistent, laid out for
 // HBM streaming on gfx950:
 //  * NT threads per workgroup (1024, or 512 for eta > 768), one workgroup per
-//    CU, each owning a column slice of at most 4*CPL float4 chunks (slices
-//    are whole 64-byte units).
-//  * Lane l of wave w holds row t = p*(NT/4) + 16*w + (l % 16) of pass p and
-//    chunks q = (l / 16) + 4r, r < CPL. The 16 lanes that hold one chunk
-//    column form one DPP row, so the column sums of the update reduce with
-//    four row_ror adds; the 4 lanes that hold one row reduce with two swaps.
+//    CU. The G workgroups form RG row groups of G/RG column slices: the
+//    workgroup of slice s and group h owns the slice's x (at most 4*RG*CPL
+//    float4 chunks, whole 64-byte units) and reads the slice of the rows
+//    h*etaR .. (h+1)*etaR - 1 of each step, etaR = ceil(eta/RG). Wider
+//    slices (RG = 2) make longer contiguous pieces of each row, which HBM
+//    serves faster; the RG workgroups of a slice then add their parts of the
+//    update in a third exchange hop, in a fixed order, so that they keep
+//    identical copies of x.
+//  * With RL = 16/RG, lane l of wave w holds group row p*(NT/64)*RL + RL*w +
+//    (l % RL) of pass p and chunks q = (l / RL) + 4*RG*r, r < CPL. The RL
+//    lanes that hold one chunk column are adjacent, so the column sums of the
+//    update reduce with DPP adds within a row; the lanes that hold one row
+//    reduce with swaps.
 //  * All RP*CPL float4 loads of a step are issued before the first is used
 //    (up to 20 KB in flight per CU). The addresses never depend on a
 //    predicate: a chunk outside the slice is clamped into the row and meets a
@@ -32,7 +39,6 @@ namespace rsk {
 namespace {
 
 constexpr int kMaxG = 256;  // workgroups the exchange code is unrolled for (4 slots per lane)
-constexpr int kOwnMax = kRtOwnMax;  // rows one wave reduces per step
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) {
   float s = a.x * b.x;
@@ -47,28 +53,44 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-// Sum over the 16 lanes of a DPP row; every lane of the row gets the sum.
-__device__ __forceinline__ float row16_sum(float v) {
-  v += dpp<0x128>(v);  // row_ror:8
-  v += dpp<0x124>(v);  // row_ror:4
-  v += dpp<0x122>(v);  // row_ror:2
-  v += dpp<0x121>(v);  // row_ror:1
+// Sum over aligned groups of RL adjacent lanes (RL = 16: a DPP row; 8: half a
+// row); every lane of the group gets the sum.
+template <int RL>
+__device__ __forceinline__ float lanes_sum(float v) {
+  if constexpr (RL == 16) {
+    v += dpp<0x128>(v);  // row_ror:8
+    v += dpp<0x124>(v);  // row_ror:4
+    v += dpp<0x122>(v);  // row_ror:2
+    v += dpp<0x121>(v);  // row_ror:1
+  } else {
+    static_assert(RL == 8, "row groups of 16 or 8 lanes");
+    v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);  // row_half_mirror: quad 0 <-> quad 1 of each half row
+  }
   return v;
 }
 
 }  // namespace
 
-template <int NT, int RP, int CPL>
+template <int NT, int RP, int CPL, int RG>
 __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   constexpr int kRtThreads = NT;
   constexpr int kRtWaves = NT / 64;
-  constexpr int kRtRowsPerPass = kRtWaves * 16;
-  __shared__ float4 xs4[4 * CPL];                 // x* slice
-  __shared__ float4 xv4[4 * CPL];                 // x slice
-  __shared__ float4 red[kRtWaves][4 * CPL];       // per-wave column sums
+  constexpr int RL = 16 / RG;                     // rows a wave holds per pass
+  constexpr int CL = 4 * RG;                      // lanes of one row
+  constexpr int kRtRowsPerPass = kRtWaves * RL;
+  constexpr int SW = 4 * CL * CPL;                // floats of the widest slice
+  constexpr int kOwnMax = kRtOwnMax;              // rows one wave reduces per step
+  constexpr int kPollWaves = RG > 1 ? (SW + 63) / 64 : 0;  // waves holding the third hop's pollers
+  static_assert(kPollWaves <= kRtWaves / 2, "the pollers of the third hop do not issue the LDS prefetch");
+  __shared__ float4 xs4[CL * CPL];                // x* slice
+  __shared__ float4 xv4[CL * CPL];                // x slice
+  __shared__ float4 red[kRtWaves][CL * CPL];      // per-wave column sums
   __shared__ float cs[RP * kRtRowsPerPass];        // step coefficients
   __shared__ double mon[2 * kRtWaves + 2];
   __shared__ int orflag[2];  // step-parity flag words of the block OR
+  __shared__ int hop3_bad[2];  // step-parity: a non-finite sum of the slice's update parts
   // next-step tile slots prefetched into LDS: (p, r) with s = p * CPL + r < NPF; LDS slot s * NT + tid
   // holds tile[p][r] of thread tid. PL passes hold prefetched slots.
   constexpr int kPfBudget = 147456 / (NT * 16);
@@ -84,12 +106,19 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
 
   const int g = blockIdx.x, G = a.G, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int eta = a.eta;
-  const int sl = lane >> 4, ri = lane & 15;
+  const int sl = lane / RL, ri = lane % RL;
 
+  // column slice s of C = G / RG and row group h (the RG workgroups of a slice are adjacent in
+  // the XCD-aware order); the group's rows of a step are h * etaR .. h * etaR + etaH - 1
+  const int C = G / RG;
+  const int sx = xcd_slice(g, G);
+  const int s = sx / RG, h = sx % RG;
+  const int etaR = (eta + RG - 1) / RG;
+  const int hr0 = h * etaR;
+  const int etaH = hr0 >= eta ? 0 : (eta - hr0 < etaR ? eta - hr0 : etaR);
   // slice in 4-chunk (64-byte) units
-  const int s = xcd_slice(g, G);
   const int64_t nunits = (a.nchunks + 3) / 4;
-  const int64_t u0 = (int64_t)s * nunits / G, u1 = (int64_t)(s + 1) * nunits / G;
+  const int64_t u0 = (int64_t)s * nunits / C, u1 = (int64_t)(s + 1) * nunits / C;
   const int64_t q0 = u0 * 4;
   int64_t q1 = u1 * 4;
   if (q1 > a.nchunks) q1 = a.nchunks;
@@ -100,13 +129,13 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   float* xs = reinterpret_cast<float*>(xs4);
   float* xv = reinterpret_cast<float*>(xv4);
 
-  // rows this workgroup reduces: a contiguous block (two hops) or all (one hop)
-  const int per = a.two_hop ? (eta + G - 1) / G : eta;
-  const int ot0 = a.two_hop ? g * per : 0;
-  const int ot1 = (ot0 + per < eta) ? ot0 + per : eta;
+  // group rows this workgroup reduces: a contiguous block (two hops) or all (one hop)
+  const int per = a.two_hop ? (etaR + C - 1) / C : etaR;
+  const int ot0 = a.two_hop ? s * per : 0;
+  const int ot1 = (ot0 + per < etaH) ? ot0 + per : etaH;
 
-  if (tid < 2) orflag[tid] = 0;
-  for (int j = tid; j < 16 * CPL; j += kRtThreads) {
+  if (tid < 2) orflag[tid] = hop3_bad[tid] = 0;
+  for (int j = tid; j < SW; j += kRtThreads) {
     const int64_t c = c0 + j;
     const float z = (a.warm && j < wq * 4 && c < a.n) ? a.x_star[c] : 0.f;
     xs[j] = z;
@@ -114,7 +143,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   }
 
   // Prefetched per-step inputs: the lane's rows of the step (tile rows), and
-  // for the rows this wave reduces, b and ||a||^2 of the sampled rows.
+  // for the rows this wave reduces, b and ||a||^2 (over w) of the sampled rows.
   int rowi[RP];
   float ob[kOwnMax], orn[kOwnMax];
   int lerr = 0;
@@ -122,17 +151,28 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     const int32_t* tk = a.idx + k * (int64_t)eta;
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
-      const int t = p * kRtRowsPerPass + 16 * wave + ri;
+      const int t = p * kRtRowsPerPass + RL * wave + ri;
       int i = -1;
-      if (t < eta) {
-        i = tk[t];
+      if (t < etaH) {
+        i = tk[hr0 + t];
         if (i < 0 || (int64_t)i >= a.m) { err = ST_INDEX; i = -1; }
+      }
+      if constexpr (RG > 1) {
+        // the other groups' rows are checked too: every workgroup stops at the same step
+#pragma unroll
+        for (int hh = 0; hh < RG; ++hh) {
+          const int tt = hh * etaR + t;
+          if (hh != h && t < etaR && tt < eta) {
+            const int j = tk[tt];
+            if (j < 0 || (int64_t)j >= a.m) err = ST_INDEX;
+          }
+        }
       }
       ri_out[p] = i;
     }
   };
   auto fetch_owned = [&](int64_t k) {
-    const int32_t* tk = a.idx + k * (int64_t)eta;
+    const int32_t* tk = a.idx + k * (int64_t)eta + hr0;
 #pragma unroll
     for (int j = 0; j < kOwnMax; ++j) {
       const int t = ot0 + wave + kRtWaves * j;
@@ -160,7 +200,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     if constexpr (NPF > 0) {
 #pragma unroll
       for (int p = 0; p < PL; ++p)
-        if (sl == 0) nrow[p * kRtRowsPerPass + 16 * wave + ri] = rows[p];
+        if (sl == 0) nrow[p * kRtRowsPerPass + RL * wave + ri] = rows[p];
     }
   };
   auto issue_prefetch = [&]() {
@@ -168,8 +208,8 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       if (wave >= kRtWaves / 2) {
         for (int I = wave - kRtWaves / 2; I < NPF * kRtWaves; I += kRtWaves / 2) {
           const int j = I % kRtWaves, sp = I / kRtWaves, r = sp % CPL, p = sp / CPL;
-          const int row = nrow[p * kRtRowsPerPass + 16 * j + ri];
-          const int q = sl + 4 * r;
+          const int row = nrow[p * kRtRowsPerPass + RL * j + ri];
+          const int q = sl + CL * r;
           const float* gp = a.A + (int64_t)(row < 0 ? 0 : row) * a.ld + c0 + 4 * (q < qlast ? q : qlast);
           __builtin_amdgcn_global_load_lds(gp, (__attribute__((address_space(3))) void*)&pf[(p * CPL + r) * NT + 64 * j],
                                            16, 0, 0);
@@ -198,7 +238,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
 #pragma unroll
       for (int r = 0; r < CPL; ++r) {
         if (p * CPL + r < NPF) continue;
-        const int q = sl + 4 * r;  // clamped into the row: past the slice it meets x = 0
+        const int q = sl + CL * r;  // clamped into the row: past the slice it meets x = 0
         tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
       }
     }
@@ -210,7 +250,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     // the loop and keeps it in VGPRs that the register tile needs.
     int tidl = threadIdx.x;
     asm volatile("" : "+v"(tidl));
-    const int tid = tidl, lane = tidl & 63, wave = tidl >> 6, sl = lane >> 4, ri = lane & 15;
+    const int tid = tidl, lane = tidl & 63, wave = tidl >> 6, sl = lane / RL, ri = lane % RL;
     const unsigned tag = (unsigned)(k + 1);
     const float ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
     u64* xP = a.xP + (size_t)(k & 1) * G * eta;
@@ -232,11 +272,11 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     for (int p = 0; p < RP; ++p) {
       float acc = 0.f;
 #pragma unroll
-      for (int r = 0; r < CPL; ++r) acc += dot4(tile[p][r], xv4[sl + 4 * r]);
-      acc += __shfl_xor(acc, 16);
-      acc += __shfl_xor(acc, 32);
-      const int t = p * kRtRowsPerPass + 16 * wave + ri;
-      if (sl == 0 && t < eta) put_tagged(&xP[(size_t)g * eta + t], acc, tag);
+      for (int r = 0; r < CPL; ++r) acc += dot4(tile[p][r], xv4[sl + CL * r]);
+#pragma unroll
+      for (int o = RL; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+      const int t = p * kRtRowsPerPass + RL * wave + ri;
+      if (sl == 0 && t < etaH) put_tagged(&xP[(size_t)s * eta + hr0 + t], acc, tag);
       __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (NPF > 0) {
@@ -248,23 +288,24 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       }
     }
     int bad = 0;
-    // reduce the owned rows over the G workgroups; c_t = (alpha/eta)(r_t - b)/||a||^2
+    // reduce the owned rows over the C slices; c_t = (alpha/eta)(r_t - b)/||a||^2
 #pragma unroll
     for (int j = 0; j < kOwnMax; ++j) {
       const int t = ot0 + wave + kRtWaves * j;
       if (t < ot1) {
         float v[kMaxG / 64];
-        wait_tagged_batch(&xP[(size_t)lane * eta + t], (size_t)64 * eta, (G - lane + 63) / 64, tag, v, lerr);
+        wait_tagged_batch(&xP[(size_t)lane * eta + hr0 + t], (size_t)64 * eta, (C - lane + 63) / 64, tag, v, lerr);
         float sum = 0.f;
 #pragma unroll
         for (int i = 0; i < kMaxG / 64; ++i) sum += v[i];
         sum = wave_sum(sum);
         if (lane == 0) {
           float c;
-          if (orn[j] == 0.f) { c = NAN; set_status(a.status, ST_ZERO_ROW); }
-          else c = (ak / (float)eta) * (sum - ob[j]) / orn[j];
+          const float rn = orn[j];
+          if (rn == 0.f) { c = NAN; set_status(a.status, ST_ZERO_ROW); }
+          else c = (ak / (float)eta) * (sum - ob[j]) / rn;
           if (a.two_hop) {
-            put_tagged(&a.xC[t], c, tag);
+            put_tagged(&a.xC[hr0 + t], c, tag);
           } else {
             cs[t] = c;
             bad |= !isfinite(c);
@@ -275,11 +316,11 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     if (has_next) fetch_owned(k + 1);
     if (a.two_hop && tid < kRtRowsPerPass) {
       float v[RP];
-      wait_tagged_batch(&a.xC[tid], kRtRowsPerPass, (eta - tid + kRtRowsPerPass - 1) / kRtRowsPerPass, tag, v,
-                        lerr);
+      wait_tagged_batch(&a.xC[hr0 + tid], kRtRowsPerPass, (etaH - tid + kRtRowsPerPass - 1) / kRtRowsPerPass, tag,
+                        v, lerr);
 #pragma unroll
       for (int i = 0; i < RP; ++i)
-        if (tid + kRtRowsPerPass * i < eta) {
+        if (tid + kRtRowsPerPass * i < etaH) {
           cs[tid + kRtRowsPerPass * i] = v[i];
           bad |= !isfinite(v[i]);
         }
@@ -295,9 +336,18 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     if (flag) atomicOr(&orflag[k & 1], flag);
     __syncthreads();
     const int fl = orflag[k & 1];
-    if (tid == 0) orflag[(k + 1) & 1] = 0;
+    if (tid == 0) orflag[(k + 1) & 1] = hop3_bad[(k + 1) & 1] = 0;
     if (fl & 1) { stop_code = ST_ABORTED; break; }
-    if (fl & 2) { stop_code = ST_NONFINITE; break; }
+    if (fl & 2) {
+      if constexpr (RG > 1) {
+        // the other groups of the slice (whose coefficients may be finite) take a NaN update
+        // part from this one and stop at their next step
+        if (tid < 4 * wq)
+          put_tagged(&a.xU[(((size_t)(k & 1) * C + s) * RG + h) * SW + tid], __builtin_nanf(""), tag);
+      }
+      stop_code = ST_NONFINITE;
+      break;
+    }
     const int next_bad = fl & 4;
 
     // transposed update: per chunk slot, sum over own rows, then the 16 lanes
@@ -305,12 +355,12 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     float cp[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
-      const int t = p * kRtRowsPerPass + 16 * wave + ri;
-      cp[p] = t < eta ? cs[t] : 0.f;
+      const int t = p * kRtRowsPerPass + RL * wave + ri;
+      cp[p] = t < etaH ? cs[t] : 0.f;
     }
     const bool load_next = has_next && !next_bad;
-    if (a.y && g == 0)
-      for (int t = tid; t < eta; t += kRtThreads) atomicAdd(&a.y[a.idx[k * (int64_t)eta + t]], -cs[t]);
+    if (a.y && s == 0)
+      for (int t = tid; t < etaH; t += kRtThreads) atomicAdd(&a.y[a.idx[k * (int64_t)eta + hr0 + t]], -cs[t]);
 #pragma unroll
     for (int r = 0; r < CPL; ++r) {
       float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -321,26 +371,28 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
         d.z += cp[p] * tile[p][r].z;
         d.w += cp[p] * tile[p][r].w;
       }
-      d.x = row16_sum(d.x);
-      d.y = row16_sum(d.y);
-      d.z = row16_sum(d.z);
-      d.w = row16_sum(d.w);
-      if (ri == 0) red[wave][sl + 4 * r] = d;
+      d.x = lanes_sum<RL>(d.x);
+      d.y = lanes_sum<RL>(d.y);
+      d.z = lanes_sum<RL>(d.z);
+      d.w = lanes_sum<RL>(d.w);
+      if (ri == 0) red[wave][sl + CL * r] = d;
     }
     // the tile is used up: the next step's HBM slots load now, row by row (a row's chunks issued
-    // back to back keep the DRAM pages open), and stay in flight across the plain barriers
-    if (load_next) {
+    // back to back keep the DRAM pages open), and stay in flight across the plain barriers. The
+    // waves that poll the third hop issue theirs after it: a poll waits for all of its wave's loads.
+    auto load_tile = [&]() {
 #pragma unroll
       for (int p = 0; p < RP; ++p) {
         const float* rowp = a.A + (int64_t)(rown[p] < 0 ? 0 : rown[p]) * a.ld + c0;
 #pragma unroll
         for (int r = 0; r < CPL; ++r) {
           if (p * CPL + r < NPF) continue;
-          const int q = sl + 4 * r;
+          const int q = sl + CL * r;
           tile[p][r] = *reinterpret_cast<const float4*>(rowp + 4 * (q < qlast ? q : qlast));
         }
       }
-    }
+    };
+    if (load_next && wave >= kPollWaves) load_tile();
     __syncthreads();  // publishes red[]
     if (tid < 4 * wq) {  // chunks past the slice carry clamped data: discarded
       const int q = tid >> 2, e = tid & 3;
@@ -349,9 +401,24 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
         const float4 v = red[w][q];
         dsum += e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
       }
+      if constexpr (RG > 1) {
+        // third hop: the slice's RG groups add their parts in group order, so every copy of the
+        // slice gets the same x (the next step's HBM loads are in flight meanwhile)
+        u64* xU = a.xU + ((size_t)(k & 1) * C + s) * RG * SW;
+        put_tagged(&xU[(size_t)h * SW + tid], dsum, tag);
+        float tot = 0.f;
+#pragma unroll
+        for (int hh = 0; hh < RG; ++hh) tot += hh == h ? dsum : wait_tagged<float>(&xU[(size_t)hh * SW + tid], tag, lerr);
+        if (lerr) set_status(a.status, ST_ABORTED);
+        if (!isfinite(tot)) atomicOr(&hop3_bad[k & 1], 1);
+        dsum = tot;
+      }
       const float z = xs[tid] - dsum;
       xs[tid] = z;
       xv[tid] = shrink(z, a.lambda);
+    }
+    if constexpr (RG > 1) {
+      if (load_next && wave < kPollWaves) load_tile();
     }
     k_done = k + 1;
     if constexpr (NPF > 0) {
@@ -363,13 +430,17 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
       }
     }
     __syncthreads();
+    if constexpr (RG > 1) {
+      // a group that stopped on a non-finite coefficient sent NaN parts: every copy stops here
+      if (hop3_bad[k & 1]) { stop_code = ST_NONFINITE; break; }
+    }
 
     if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
       const unsigned mtag = (unsigned)((k + 1) / a.check_every);
       double e2 = 0.0, r2s = 0.0;
       for (int j = tid; j < wq * 4; j += kRtThreads) {
         const int64_t c = c0 + j;
-        if (c < a.n) {
+        if (c < a.n && h == 0) {  // one copy of each slice counts
           const double rf = (double)a.xref[c];
           const double d = (double)xv[j] - rf;
           e2 += d * d;
@@ -412,10 +483,11 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
   if (stop_code && tid == 0) set_status(a.status, stop_code);
   __builtin_amdgcn_s_waitcnt(0);  // no load of a step that will not run stays in flight
   __syncthreads();
-  for (int j = tid; j < wq * 4; j += kRtThreads) {
-    const int64_t c = c0 + j;
-    if (c < a.n) { a.x_star[c] = xs[j]; a.x[c] = xv[j]; }
-  }
+  if (h == 0)
+    for (int j = tid; j < wq * 4; j += kRtThreads) {
+      const int64_t c = c0 + j;
+      if (c < a.n) { a.x_star[c] = xs[j]; a.x[c] = xv[j]; }
+    }
   if (g == 0 && tid == 0) a.status[1] = (int)k_done;
 }
 
@@ -423,24 +495,26 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
 // host side
 // ---------------------------------------------------------------------------
 
-template <int NT, int RP, int CPL>
+template <int NT, int RP, int CPL, int RG>
 static void* rt_ptr() {
-  return reinterpret_cast<void*>(&rska_dense_rt<NT, RP, CPL>);
+  return reinterpret_cast<void*>(&rska_dense_rt<NT, RP, CPL, RG>);
 }
 
 // 1024 threads for eta <= 768 (RP <= 3), 512 threads (256 VGPRs a lane) for 768 < eta <= 1024.
-static void* rt_kernel(int nt, int rp, int cpl) {
-#define RT_CASE(N, R, C) if (nt == N && rp == R && cpl == C) return rt_ptr<N, R, C>();
-#define RT_CPL(N, R) RT_CASE(N, R, 1) RT_CASE(N, R, 2) RT_CASE(N, R, 3) RT_CASE(N, R, 4) RT_CASE(N, R, 5)
-  RT_CPL(1024, 1) RT_CPL(1024, 2) RT_CPL(1024, 3)
-  RT_CPL(512, 7) RT_CPL(512, 8)
+static void* rt_kernel(int nt, int rp, int cpl, int rg) {
+#define RT_CASE(N, R, C, H) if (nt == N && rp == R && cpl == C && rg == H) return rt_ptr<N, R, C, H>();
+#define RT_CPL(N, R, H) RT_CASE(N, R, 1, H) RT_CASE(N, R, 2, H) RT_CASE(N, R, 3, H) RT_CASE(N, R, 4, H) RT_CASE(N, R, 5, H)
+  RT_CPL(1024, 1, 1) RT_CPL(1024, 2, 1) RT_CPL(1024, 3, 1)
+  RT_CPL(512, 7, 1) RT_CPL(512, 8, 1)
+  RT_CPL(1024, 1, 2) RT_CPL(1024, 2, 2) RT_CPL(1024, 3, 2)
+  RT_CPL(512, 7, 2) RT_CPL(512, 8, 2)
 #undef RT_CPL
 #undef RT_CASE
   return nullptr;
 }
 
-int dense_rt_max_grid(int nt, int rp, int cpl) {
-  void* fn = rt_kernel(nt, rp, cpl);
+int dense_rt_max_grid(int nt, int rp, int cpl, int rg) {
+  void* fn = rt_kernel(nt, rp, cpl, rg);
   if (!fn) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) != hipSuccess) return 0;
@@ -450,10 +524,11 @@ int dense_rt_max_grid(int nt, int rp, int cpl) {
   return per_cu * cus;
 }
 
-hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, hipStream_t stream) {
-  void* fn = rt_kernel(nt, rp, cpl);
+hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, int rg, hipStream_t stream) {
+  void* fn = rt_kernel(nt, rp, cpl, rg);
   if (!fn) return hipErrorInvalidValue;
-  if (a.G > kMaxG || dense_rt_max_grid(nt, rp, cpl) < a.G) return hipErrorCooperativeLaunchTooLarge;
+  if (a.G % rg != 0 || (rg > 1 && !a.xU)) return hipErrorInvalidValue;
+  if (a.G > kMaxG || dense_rt_max_grid(nt, rp, cpl, rg) < a.G) return hipErrorCooperativeLaunchTooLarge;
   void* args[] = {&a};
   return hipLaunchCooperativeKernel(fn, dim3(a.G), dim3(nt), args, 0, stream);
 }

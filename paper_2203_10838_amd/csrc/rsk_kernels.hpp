@@ -34,6 +34,7 @@ struct DenseArgs {
   u64* xP;                // partial dots  [2][G][eta][words] (step parity)
   u64* xC;                // coefficients  [eta][words]
   u64* xM;                // monitor sums  [G][2][2]
+  u64* xU = nullptr;      // register-tile kernel with RG > 1 row groups: update parts [2][G][slice floats]
   int G;
   int two_hop;            // 1: owners reduce rows, then everyone gathers; 0: everyone reduces everything
   int tile_cache;         // 1: keep the step's row tile in LDS between dot and scatter
@@ -250,9 +251,11 @@ hipError_t launch_rownorm2_csr(const int64_t* row_ptr, const T* val, int64_t m, 
 
 hipError_t launch_zero_words(u64* p, size_t nwords, hipStream_t stream);
 
-// float32 register-tile kernel: NT threads, RP row passes of NT/4 rows, CPL float4 chunks per lane
-int dense_rt_max_grid(int nt, int rp, int cpl);
-hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, hipStream_t stream);
+// float32 register-tile kernel: NT threads, RP row passes of NT/(4 RG) rows, CPL float4 chunks
+// per lane, RG row groups (1 or 2) of G/RG column slices
+int dense_rt_max_grid(int nt, int rp, int cpl, int rg);
+hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, int rg, hipStream_t stream);
+// kRtOwnMax: rows of a step one wave of the register-tile kernel reduces
 constexpr int kRtMaxEta = 1024, kRtMaxCPL = 5, kRtOwnMax = 4;
 hipError_t launch_zero_status(int* status, hipStream_t stream);
 
