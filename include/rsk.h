@@ -94,7 +94,9 @@ typedef struct {
   void *y_out;                 /* nullable device array (m, dtype of A), in/out: y[tau_t] -= c_t, so x* = A^T y */
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
-  int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register tile */
+  int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register
+                                  tile, 3 = float32 register tile over two row groups (see
+                                  rsk_avg_solve_dense); CSR: 0, 1 or 2 */
   const void *row_w;           /* nullable device array (m, dtype of A): per-row weights w_i, the diagonal W of
                                   Definition 1 (variants v3/v4 of Sec. 5); row i is relaxed by alpha (or
                                   alpha_k[k]) times w_i. Dense, CSR and multi-RHS solves; not the adjoint or
@@ -245,6 +247,17 @@ int32_t rsk_workspace_size_csr(const rsk_csr *A, const rsk_params *p, size_t *by
  *   x       device, n entries, out: S_lambda(x*_K).
  * Resuming: a call with warm_start = 1, the x_star of a previous call and
  * stream_offset advanced by K*eta continues that run exactly.
+ * Kernels (p->kernel): 1 = general (float32 and float64, any alignment);
+ * 2 = float32 register tile (n and ld multiples of 4, A 16-byte aligned,
+ * eta <= 1024, slices of at most 80 columns); 3 = the register tile over two
+ * row groups: each workgroup reads half of a step's rows over a slice twice
+ * as wide (at most 160 columns), and the two workgroups of a slice add their
+ * parts of the x* update in a third exchange (same requirements as 2, an
+ * even number of workgroups). 0 = the
+ * library's choice: 3 for 128 <= eta <= 768, else 2, when a step moves at
+ * least 512 KB and the register tile applies; else 1. Kernels 2 and 3 sum in
+ * different orders (results agree to rounding); each is bitwise reproducible.
+ * A kernel that does not apply to the shape returns RSK_ERR_UNSUPPORTED.
  */
 int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
                             void *workspace, size_t ws_bytes, void *stream);

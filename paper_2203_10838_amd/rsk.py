@@ -123,6 +123,9 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
     ``row_w`` (m, optional): per-row weights w_i of Definition 1 (variants v3/v4 of Sec. 5);
     row i is then relaxed by alpha (or alpha_k[k]) times w_i.
 
+    ``kernel``: 0 library's choice, 1 general, 2 float32 register tile, 3 register tile over two
+    row groups (half of a step's rows per workgroup over slices twice as wide).
+
     ``x_star`` (optional, in/out) receives x*_K; with ``warm_start`` it is also x*_0.
     With ``check`` the call synchronises, reads the device status and raises
     ``RskError`` on a device-side fault.
