@@ -144,6 +144,9 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
 
   // Prefetched per-step inputs: the lane's rows of the step (tile rows), and
   // for the rows this wave reduces, b and ||a||^2 (over w) of the sampled rows.
+  // The row indices load at fixed in-range positions with no branch, all before
+  // the first is checked: a load inside a branch is waited for at once, one
+  // round trip each.
   int rowi[RP];
   float ob[kOwnMax], orn[kOwnMax];
   int lerr = 0;
@@ -152,23 +155,28 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
       const int t = p * kRtRowsPerPass + RL * wave + ri;
-      int i = -1;
-      if (t < etaH) {
-        i = tk[hr0 + t];
-        if (i < 0 || (int64_t)i >= a.m) { err = ST_INDEX; i = -1; }
-      }
-      if constexpr (RG > 1) {
-        // the other groups' rows are checked too: every workgroup stops at the same step
+      ri_out[p] = tk[t < etaH ? hr0 + t : 0];
+    }
+    int xo[RG > 1 ? RP : 1];
+    if constexpr (RG > 1) {
 #pragma unroll
-        for (int hh = 0; hh < RG; ++hh) {
-          const int tt = hh * etaR + t;
-          if (hh != h && t < etaR && tt < eta) {
-            const int j = tk[tt];
-            if (j < 0 || (int64_t)j >= a.m) err = ST_INDEX;
-          }
-        }
+      for (int p = 0; p < RP; ++p) {
+        const int t = p * kRtRowsPerPass + RL * wave + ri;
+        const int tt = (1 - h) * etaR + t;
+        xo[p] = tk[(t < etaR && tt < eta) ? tt : 0];
       }
+    }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const int t = p * kRtRowsPerPass + RL * wave + ri;
+      int i = ri_out[p];
+      if (t >= etaH) i = -1;
+      else if (i < 0 || (int64_t)i >= a.m) { err = ST_INDEX; i = -1; }
       ri_out[p] = i;
+      if constexpr (RG > 1) {
+        // the other group's rows are checked too: every workgroup stops at the same step
+        if (xo[p] < 0 || (int64_t)xo[p] >= a.m) err = ST_INDEX;
+      }
     }
   };
   auto fetch_owned = [&](int64_t k) {
