@@ -499,8 +499,11 @@ class BskResult:
 def bsk_solve(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, w: float, K: int,
               index_stream: torch.Tensor, stream_offset: int = 0, x_star: Optional[torch.Tensor] = None,
               warm_start: bool = False, x_ref: Optional[torch.Tensor] = None, check_every: int = 0,
-              block_norms: bool = False, workspace: Optional[torch.Tensor] = None, check: bool = True) -> BskResult:
-    """K block sparse Kaczmarz steps, eq. (bsk): x* -= w A_tau^T(A_tau x - b_tau)/||A_tau||_2^2, x = S_lambda(x*)."""
+              block_norms: bool = False, grid: int = 0, kernel: int = 0,
+              workspace: Optional[torch.Tensor] = None, check: bool = True) -> BskResult:
+    """K block sparse Kaczmarz steps, eq. (bsk): x* -= w A_tau^T(A_tau x - b_tau)/||A_tau||_2^2, x = S_lambda(x*).
+
+    ``grid`` and ``kernel`` select the dense kernel of the steps as in ``solve_dense``."""
     m, n = A.shape
     dt = A.dtype
     _dev(b, "b", dt, m)
@@ -519,7 +522,7 @@ def bsk_solve(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, w: floa
     p = _abi.RskParams(float(lam), int(eta), float(w), None, int(K),
                        _dev(index_stream, "index_stream") if index_stream is not None else None, int(stream_offset),
                        None, 1 if warm_start else 0, _dev(x_ref, "x_ref", dt, n), int(check_every), 0.0,
-                       _dev(err_hist, "err_hist"), None, status_dev.data_ptr(), 0, 0)
+                       _dev(err_hist, "err_hist"), None, status_dev.data_ptr(), int(grid), int(kernel))
     d = dense_desc(A)
     nbytes = ctypes.c_size_t(0)
     st = _lib().rsk_workspace_size_bsk_dense(ctypes.byref(d), ctypes.byref(p), ctypes.byref(nbytes))

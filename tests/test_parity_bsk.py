@@ -44,6 +44,19 @@ def test_bsk_matches_oracle(cuda, rsk_lib, dtype, tol, m, n, eta, K, lam, w):
     assert np.allclose(s2, ref["s2"], rtol=1e-5 if dtype == "f32" else 1e-12, atol=0)
 
 
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_bsk_each_dense_kernel(cuda, rsk_lib, kernel):
+    """The block step runs on any dense kernel (unit row norms, alpha_k = eta w / s2)."""
+    from paper_2203_10838_amd import rsk
+    c = inputs.dense_system(1500, 1280, 30, seed=57, noise_rel=0.01)
+    idx = _stream(c["A"], 120, 48, 58)
+    res = rsk.bsk_solve(_t(c["A"], cuda), _t(c["b"], cuda), lam=0.5, eta=48, w=1.0, K=120,
+                        index_stream=_t(idx, cuda), grid=16, kernel=kernel)
+    assert res.status == 0
+    ref = oracle.bsk_dense(c["A"], c["b"], 0.5, 1.0, 120, idx, 48)
+    assert _rel(res.x.cpu().numpy(), ref["x"]) <= 1e-4
+
+
 def test_bsk_all_rows_matches_full_batch_oracle(cuda, rsk_lib):
     """eta = m = 64 rows, each once per step: the linearized Bregman step with w / ||A||_2^2."""
     from paper_2203_10838_amd import rsk

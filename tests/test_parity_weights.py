@@ -29,11 +29,12 @@ def _streams(A, w, K, eta, seed, variant):
     return inputs.index_stream(p, K, eta, seed)
 
 
-# general kernel (f32, f64: one- and two-hop exchanges) and the float32 register-tile kernel
+# general kernel (f32, f64: one- and two-hop exchanges), the float32 register-tile kernel and its
+# two-row-group layout
 @pytest.mark.parametrize("variant", ["v3", "v4"])
 @pytest.mark.parametrize("dtype,kernel,m,n,eta,K,grid", [
     ("f32", 1, 3000, 2000, 64, 300, 0), ("f64", 1, 2000, 1500, 256, 100, 0), ("f32", 1, 1200, 777, 1, 2000, 0),
-    ("f32", 2, 3000, 1280, 300, 60, 16), ("f32", 2, 2000, 1280, 40, 200, 20)])
+    ("f32", 2, 3000, 1280, 300, 60, 16), ("f32", 2, 2000, 1280, 40, 200, 20), ("f32", 3, 3000, 1280, 300, 60, 16)])
 def test_weighted_dense_matches_oracle(cuda, rsk_lib, variant, dtype, kernel, m, n, eta, K, grid):
     from paper_2203_10838_amd import rsk
     c = inputs.dense_system(m, n, max(1, n // 40), dtype=dtype, seed=m + eta, noise_rel=0.01)
