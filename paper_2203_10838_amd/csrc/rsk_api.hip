@@ -302,6 +302,7 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   const int tiles = (pl->eta_pad / 64) * ((R + 63) / 64);
   const int cus = device_cus() > 0 ? device_cus() : 256;
   int S = (3 * cus + tiles - 1) / tiles;  // about three workgroups per CU for the n-long products
+  if (S >= 8) S = (S + 7) / 8 * 8;        // whole XCD rounds: the tiles of a split share one L2
   const int64_t max_s = (A->n + 255) / 256;  // at least 256 columns a split
   if (S > max_s) S = (int)max_s;
   if (S < 1) S = 1;

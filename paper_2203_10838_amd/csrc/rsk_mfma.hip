@@ -101,17 +101,31 @@ __device__ __forceinline__ void stage_tau(const int32_t* __restrict__ tau, int e
 
 }  // namespace
 
-// Y[s][t][r] = sum_{j in split s} A[tau_t, j] X[j, r]. grid = (ceil(eta/64), R/64, S).
+// Y[s][t][r] = sum_{j in split s} A[tau_t, j] X[j, r]. One-dimensional grid of gt * gr * S
+// workgroups (gt = ceil(eta/64) row tiles, gr = ceil(R/64) column tiles, S splits of n). With S a
+// multiple of 8 the gt * gr tiles of one split run on one XCD (workgroup i goes to XCD i % 8), so
+// that XCD's L2 fetches A_tau[:, K_s] and X[K_s, :] once and serves their re-reads by the other
+// tiles (A_tau by the gr column tiles, X by the gt row tiles).
 __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, int64_t ld, int64_t n,
                                                   const int32_t* __restrict__ tau, int eta, const float* __restrict__ X,
                                                   int R, float* __restrict__ Y, int eta_pad, int64_t kspan,
-                                                  const int* status) {
+                                                  int gt, int gr, int S, const int* status) {
   if (status[0]) return;
   __shared__ __align__(16) float As[SK][LDP];
   __shared__ __align__(16) float Bs[SK][LDP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int t0 = blockIdx.x * BM, r0 = blockIdx.y * BN, s = blockIdx.z;
+  const int id = blockIdx.x, T = gt * gr;
+  int tile, s;
+  if (S % 8 == 0) {
+    const int q = id / 8;
+    tile = q % T;
+    s = id % 8 + 8 * (q / T);
+  } else {
+    tile = id % T;
+    s = id / T;
+  }
+  const int t0 = (tile % gt) * BM, r0 = (tile / gt) * BN;
   const int64_t j_begin = (int64_t)s * kspan;
   int64_t j_end = j_begin + kspan;
   if (j_end > n) j_end = n;
@@ -343,8 +357,8 @@ static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, fl
   const int gr = (a.R + BN - 1) / BN;
   const int gn = (int)((a.n + BM - 1) / BM);
   const int32_t* tk = a.idx + k * (int64_t)a.eta;
-  hipLaunchKernelGGL(gemm_at_x, dim3(gt, gr, a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R, a.Y,
-                     a.eta_pad, a.kspan, a.status);
+  hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R,
+                     a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status);
   hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
                      a.row_w, a.alpha, a.alpha_k, k, a.C, rh, a.status);
   if (a.S2 > 1) {
@@ -719,8 +733,8 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
     for (int64_t k = k1 - 1; k >= k0; --k) {
       const int64_t j = k - k0;
       const int32_t* tk = a.idx + k * (int64_t)a.eta;
-      hipLaunchKernelGGL(gemm_at_x, dim3(gt, gr, a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, d.zbar, a.R,
-                         a.Y, a.eta_pad, a.kspan, a.status);
+      hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, d.zbar,
+                         a.R, a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status);
       hipLaunchKernelGGL(adj_coef, dim3(kAdjCoefBlocks), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta,
                          d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
       hipLaunchKernelGGL(adj_bbar, dim3((unsigned)(((size_t)a.eta * a.R + 255) / 256)), dim3(256),
