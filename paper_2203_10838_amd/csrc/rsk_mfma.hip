@@ -32,24 +32,32 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
 }
 
 // Pipelined main loop. K advances SK = 64 per stage through LDS tiles stored
-// k-major (rows padded to BM + 4 floats); every thread moves four float4 of
-// each operand per stage, and the next stage's loads are issued before the
-// current stage's MFMAs, so one memory latency overlaps one stage of compute.
-constexpr int SK = 64, LDP = BM + 4;
+// k-major, rows padded to BM + 16 floats: a fragment read (16 consecutive
+// floats in each of 4 k rows) then hits 64 distinct banks. Every thread moves
+// four float4 of each operand per stage, and the next stage's loads are issued
+// before the current stage's MFMAs, so one memory latency overlaps one stage
+// of compute. The A_tau X product keeps its A tile row-major (rows padded to
+// SK + 4 floats, again 64 distinct banks per fragment read), so that tile is
+// stored with float4 writes instead of a transpose.
+constexpr int SK = 64, LDP = BM + 16, LDA = SK + 4;
 constexpr int kMaxTauLds = 4096;  // sampled rows staged in LDS by the A^T GEMMs
 
 struct Stage {
   float4 a[4], b[4];
 };
 
-__device__ __forceinline__ void mma_stage(const float (*As)[LDP], const float (*Bs)[LDP], int wm, int wn, int lane,
-                                          f4 (&acc)[2][2]) {
+template <bool A_ROWS>
+__device__ __forceinline__ void mma_stage_t(const float* As, const float (*Bs)[LDP], int wm, int wn, int lane,
+                                            f4 (&acc)[2][2]) {
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int k0 = 0; k0 < SK; k0 += 4) {
     float a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = As[k0 + lk][wm * 32 + i * 16 + li];
+    for (int i = 0; i < 2; ++i) {
+      const int m = wm * 32 + i * 16 + li;
+      a[i] = A_ROWS ? As[m * LDA + k0 + lk] : As[(k0 + lk) * LDP + m];
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) b[j] = Bs[k0 + lk][wn * 32 + j * 16 + li];
 #pragma unroll
@@ -57,6 +65,11 @@ __device__ __forceinline__ void mma_stage(const float (*As)[LDP], const float (*
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
   }
+}
+
+__device__ __forceinline__ void mma_stage(const float (*As)[LDP], const float (*Bs)[LDP], int wm, int wn, int lane,
+                                          f4 (&acc)[2][2]) {
+  mma_stage_t<false>(&As[0][0], Bs, wm, wn, lane, acc);
 }
 
 // acc = A_tau[:, k-range]^T-free product for the A^T GEMMs: acc(m = column j0 + m, n = r0 + n) =
@@ -111,7 +124,7 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
                                                   int R, float* __restrict__ Y, int eta_pad, int64_t kspan,
                                                   int gt, int gr, int S, const int* status) {
   if (status[0]) return;
-  __shared__ __align__(16) float As[SK][LDP];
+  __shared__ __align__(16) float Ar[BM][LDA];
   __shared__ __align__(16) float Bs[SK][LDP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -165,15 +178,12 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = lr + 16 * i;
-      As[lc + 0][m] = st.a[i].x;
-      As[lc + 1][m] = st.a[i].y;
-      As[lc + 2][m] = st.a[i].z;
-      As[lc + 3][m] = st.a[i].w;
+      *reinterpret_cast<float4*>(&Ar[m][lc]) = st.a[i];
       *reinterpret_cast<float4*>(&Bs[m][lc]) = st.b[i];
     }
     __syncthreads();
     if (jb + SK < j_end) load(jb + SK, st);
-    mma_stage(As, Bs, wm, wn, lane, acc);
+    mma_stage_t<true>(&Ar[0][0], Bs, wm, wn, lane, acc);
   }
   // D layout: column lane%16, rows 4*(lane/16) + v
   float* Ys = Y + (size_t)s * eta_pad * R;
