@@ -94,6 +94,25 @@ def test_two_row_groups_resume_dual_and_monitor(cuda, rsk_lib):
     assert np.allclose(rm.err_hist.cpu().numpy(), ref["hist"], rtol=1e-3, atol=1e-6)
 
 
+def test_two_row_groups_tolerance_stop(cuda, rsk_lib):
+    """The monitor's early stop ends both groups at the same check: the result is bitwise the run
+    of exactly that many steps."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    sysd, idx = _case(3000, 1280, 400, 400, 75)
+    alpha = _alpha_star(sysd["A"], 400)
+    A, b, ix, xr = _to(sysd["A"], cuda), _to(sysd["b"], cuda), _to(idx, cuda), _to(sysd["xhat"], cuda)
+    kw = dict(lam=0.05, eta=400, alpha=alpha, grid=32, kernel=3, index_stream=ix)
+    full = rsk.solve_dense(A, b, K=400, x_ref=xr, check_every=10, **kw)
+    h = full.err_hist.cpu().numpy()
+    tol = float(h[len(h) // 3])
+    early = rsk.solve_dense(A, b, K=400, x_ref=xr, check_every=10, tol=tol, **kw)
+    assert early.status == 0 and early.k_done < 400 and early.k_done % 10 == 0
+    assert h[early.k_done // 10 - 1] <= tol
+    same = rsk.solve_dense(A, b, K=early.k_done, **kw)
+    assert torch.equal(same.x_star, early.x_star)
+
+
 @pytest.mark.parametrize("group", [0, 1])
 def test_two_row_groups_stop_together(cuda, rsk_lib, group):
     """A bad index, a zero row or a blow-up in either group's rows ends the launch with its code,
