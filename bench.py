@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -71,9 +72,14 @@ def step_bytes(eta, n):
 
 
 def source_hash():
+    """Hash of the register-tile kernel's code (comments and blank space removed), so that the
+    recorded HBM counters stay valid across comment edits but not across code changes."""
     h = hashlib.sha256()
     for f in ("rsk_dense_rt.hip", "rsk_device.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2203_10838_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_2203_10838_amd", "csrc", f)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(line.strip() for line in src.splitlines() if line.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -348,8 +348,8 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     if (fl & 1) { stop_code = ST_ABORTED; break; }
     if (fl & 2) {
       if constexpr (RG > 1) {
-        // the other groups of the slice (whose coefficients may be finite) take a NaN update
-        // part from this one and stop at their next step
+        // the other group of the slice (whose coefficients may be finite) takes a NaN update
+        // part from this one and stops at the end of this step
         if (tid < 4 * wq)
           put_tagged(&a.xU[(((size_t)(k & 1) * C + s) * RG + h) * SW + tid], __builtin_nanf(""), tag);
       }
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(NT) void rska_dense_rt(DenseArgs<float> a) {
     }
     const int next_bad = fl & 4;
 
-    // transposed update: per chunk slot, sum over own rows, then the 16 lanes
+    // transposed update: per chunk slot, sum over own rows, then the RL lanes
     // holding that chunk, then the waves
     float cp[RP];
 #pragma unroll
