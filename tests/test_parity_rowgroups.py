@@ -202,3 +202,30 @@ def test_library_choice_of_row_groups(cuda, rsk_lib):
         auto = rsk.solve_dense(A, b, lam=1.0, eta=eta, alpha=0.5 * eta, K=12, index_stream=idx, kernel=0)
         same = rsk.solve_dense(A, b, lam=1.0, eta=eta, alpha=0.5 * eta, K=12, index_stream=idx, kernel=twin)
         assert torch.equal(auto.x_star, same.x_star), eta
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_register_tiles_random_shapes(cuda, rsk_lib, case):
+    """Seeded random shapes (ragged slices, ragged row groups, both thread counts): kernels 2 and 3
+    against the oracle; shapes a kernel does not take must be refused with RSK_ERR_UNSUPPORTED."""
+    from paper_2203_10838_amd import rsk
+    rng = np.random.default_rng(9000 + case)
+    n = 4 * int(rng.integers(40, 500))
+    m = int(rng.integers(n // 2, 3 * n))
+    eta = int(rng.choice([int(rng.integers(130, 768)), int(rng.integers(769, 1025))]))
+    K = int(max(4, min(40, 3e7 // (eta * n))))
+    grid = int(rng.choice([0, 64, 128, 200, 256]))
+    sysd, idx = _case(m, n, eta, K, 9100 + case)
+    alpha = _alpha_star(sysd["A"], eta)
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 0.5, eta, alpha, K, idx)
+    ran = 0
+    for kern in (2, 3):
+        try:
+            res = _solve(sysd, idx, cuda, lam=0.5, eta=eta, alpha=alpha, K=K, grid=grid, kernel=kern)
+        except rsk.RskError as e:
+            assert e.name == "RSK_ERR_UNSUPPORTED", (kern, m, n, eta, grid)
+            continue
+        ran += 1
+        assert res.status == 0 and res.k_done == K
+        assert _rel(res.x_star.cpu().numpy(), ref["z"]) <= TOL, (kern, m, n, eta, grid)
+    assert ran >= 1
