@@ -199,6 +199,22 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
       }
 }
 
+// sum_s Y[s * total + e] in ascending s; eight loads are issued before their adds, so the
+// partials' latencies overlap instead of adding up (same sum, same order)
+__device__ __forceinline__ float split_sum(const float* __restrict__ Y, int S, size_t total, size_t e) {
+  float y = 0.f;
+  int s = 0;
+  for (; s + 8 <= S; s += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = Y[(size_t)(s + u) * total + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y += v[u];
+  }
+  for (; s < S; ++s) y += Y[(size_t)s * total + e];
+  return y;
+}
+
 // C[t][r] = (alpha_k/eta) (sum_s Y[s][t][r] - B[tau_t, r]) / ||a_tau_t||^2; checks the step's
 // indices and coefficients, marks the step done. grid-stride over eta_pad x R.
 // With Rh non-null the residuals R_tau = sum_s Y_s - B_tau are stored as well (the adjoint's recompute).
@@ -214,8 +230,7 @@ __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, con
     float c = 0.f;
     if (t < eta) {
       const int i = tau[t];
-      float y = 0.f;
-      for (int s = 0; s < S; ++s) y += Y[(size_t)s * total + e];
+      const float y = split_sum(Y, S, total, e);
       const float rn = weighted_rn(r2, row_w, i);
       if (rn == 0.f) set_status(status, ST_ZERO_ROW);
       const float res = y - B[(int64_t)i * R + r];
@@ -471,8 +486,7 @@ __global__ __launch_bounds__(256) void adj_coef(const float* __restrict__ Y, int
       const int t = (int)(e / R);
       float rb = 0.f;
       if (t < eta) {
-        float y = 0.f;
-        for (int s = 0; s < S; ++s) y += Y[(size_t)s * total + e];
+        const float y = split_sum(Y, S, total, e);
         const float cbar = -y;
         const float rn = r2[tau[t]];
         rb = (ak / (float)eta) * cbar / rn;
