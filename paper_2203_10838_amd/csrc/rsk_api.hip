@@ -12,7 +12,13 @@ namespace {
 
 constexpr int kMaxEtaDense = 16384;
 constexpr size_t kTileCacheBytes = 96 * 1024;
-constexpr size_t kBytesPerWg = 96 * 1024;  // target row bytes per workgroup per step
+// General-kernel grid for grid = 0. A step is a chain of dependent round trips, so below a few MB
+// it is bound by latency, not bytes: one workgroup (no exchange) while the step and its rows are
+// small, else about 4 KB of rows per workgroup on 16..128 workgroups, the whole chip for big steps.
+constexpr size_t kOneWgStepBytes = 32 * 1024, kOneWgRowBytes = 16 * 1024;
+constexpr size_t kBytesPerWg = 4 * 1024;
+constexpr int kMinSpreadG = 16, kMaxSpreadG = 128;
+constexpr size_t kFullGridStepBytes = size_t(8) << 20;
 using rsk::kOneHopWords;
 // the automatic choice takes two row groups of the register-tile kernel for eta in this range
 // (1024-thread workgroups; below it the step is bound by the exchange, and at 512 threads the
@@ -145,9 +151,15 @@ int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   if (p->grid > 0) {
     G = p->grid;
   } else {
-    const double step_bytes = (double)p->eta * (double)A->n * (double)s;
-    G = (int)ceil(step_bytes / (double)kBytesPerWg);
-    if (G < 1) G = 1;
+    const double row_bytes = (double)A->n * (double)s, step_bytes = (double)p->eta * row_bytes;
+    if (step_bytes <= kOneWgStepBytes && row_bytes <= kOneWgRowBytes) {
+      G = 1;
+    } else if (step_bytes >= kFullGridStepBytes) {
+      G = cap;
+    } else {
+      const double g = ceil(step_bytes / (double)kBytesPerWg);
+      G = g < kMinSpreadG ? kMinSpreadG : g > kMaxSpreadG ? kMaxSpreadG : (int)g;
+    }
     if (G >= 16) G -= G % 8;
   }
   if (G > cap) G = cap;
