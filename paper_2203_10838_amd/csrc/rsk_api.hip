@@ -117,7 +117,7 @@ bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, int rg, DensePlan* p
   pl->kernel = 2; pl->nt = nt; pl->rp = rp; pl->cpl = cpl; pl->rg = rg;
   pl->vec = 4; pl->W = 1; pl->nchunks = nchunks; pl->G = G;
   pl->wq_max = 4 * rg * cpl; pl->lpr = 4; pl->tile_cache = 0;
-  pl->two_hop = ((int64_t)C * etaR) > kOneHopWords;
+  pl->two_hop = ((int64_t)C * etaR) > rsk::kRtOneHopWords;
   // each wave reduces at most kRtOwnMax rows per step
   const int own = rsk::kRtOwnMax * (nt / 64);
   if (!pl->two_hop && etaR > own) pl->two_hop = 1;
@@ -132,11 +132,10 @@ template <typename T>
 int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   const size_t s = sizeof(T);
   pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0; pl->rg = 1;
-  // the register-tile kernel pays one cross-CU exchange per step on a full
-  // grid: worth it once a step moves more than a few hundred KB of rows
+  // float32: the register-tile kernel wherever its shape limits allow; its exchange is cheaper
+  // than the general kernel's at every step size measured, one row per step included
   if (p->kernel == 3) return plan_dense_rt(A, p, 2, pl) ? RSK_OK : RSK_ERR_UNSUPPORTED;
-  if (p->kernel == 2 || (p->kernel == 0 && A->dtype == RSK_F32 &&
-                         (double)p->eta * (double)A->n * 4.0 >= 512.0 * 1024)) {
+  if (p->kernel == 2 || (p->kernel == 0 && A->dtype == RSK_F32)) {
     if (p->kernel == 0 && p->eta >= kRtTwoGroupMinEta && p->eta <= kRtTwoGroupMaxEta && plan_dense_rt(A, p, 2, pl))
       return RSK_OK;
     if (plan_dense_rt(A, p, 1, pl)) return RSK_OK;

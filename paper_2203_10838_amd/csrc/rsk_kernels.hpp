@@ -82,6 +82,11 @@ __host__ __device__ inline int64_t onehop_lds_elems(int64_t G, int64_t eta) {
 // thread of a 256-thread workgroup, then per-row sums in LDS).
 constexpr int64_t kOneHopWords = 4096;
 
+// The register-tile kernel gathers all C*eta partials in one hop only up to this many words per
+// step: above it the flat poll costs more than the two-hop exchange (measured on 8000- and
+// 20000-column slices over 256 workgroups).
+constexpr int64_t kRtOneHopWords = 2048;
+
 // One CSR persistent solve (single workgroup).
 constexpr int kCsrMaxEta = 4096;  // rows per step of the CSR kernel
 template <typename T>

@@ -59,7 +59,7 @@ def _gpu_solve(sysd, idx, dev, **kw):
 def test_dense_matches_oracle(cuda, rsk_lib, dtype, m, n, eta, K, grid, lam):
     sysd, idx = _case(m, n, max(1, n // 20), dtype, 1234 + m, eta, K, lam)
     alpha = _alpha_star(sysd["A"], eta)
-    res = _gpu_solve(sysd, idx, cuda, lam=lam, eta=eta, alpha=alpha, K=K, grid=grid)
+    res = _gpu_solve(sysd, idx, cuda, lam=lam, eta=eta, alpha=alpha, K=K, grid=grid, kernel=1)
     assert res.status == 0 and res.k_done == K
     ref = oracle.rska_dense(sysd["A"], sysd["b"], lam, eta, alpha, K, idx)
     xs = res.x_star.cpu().numpy()
@@ -72,29 +72,34 @@ def test_dense_matches_oracle(cuda, rsk_lib, dtype, m, n, eta, K, grid, lam):
     assert np.array_equal(x, expect)
 
 
-def test_dense_deterministic_and_resume(cuda, rsk_lib):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_dense_deterministic_and_resume(cuda, rsk_lib, kernel):
     import torch
     sysd, idx = _case(900, 256, 12, "f32", 77, 24, 200, 1.0)
     alpha = _alpha_star(sysd["A"], 24)
-    r1 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=200, grid=8)
-    r2 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=200, grid=8)
+    kw = dict(lam=1.0, eta=24, alpha=alpha, grid=8, kernel=kernel)
+    r1 = _gpu_solve(sysd, idx, cuda, K=200, **kw)
+    r2 = _gpu_solve(sysd, idx, cuda, K=200, **kw)
     assert torch.equal(r1.x_star, r2.x_star) and torch.equal(r1.x, r2.x)
     # resume: 120 + 80 steps == 200 steps, bitwise
-    h = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=120, grid=8)
+    h = _gpu_solve(sysd, idx, cuda, K=120, **kw)
     xs = h.x_star.clone()
-    r3 = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=24, alpha=alpha, K=80, grid=8, x_star=xs, warm_start=True,
-                    stream_offset=120 * 24)
+    r3 = _gpu_solve(sysd, idx, cuda, K=80, x_star=xs, warm_start=True, stream_offset=120 * 24, **kw)
     assert torch.equal(r3.x_star, r1.x_star) and torch.equal(r3.x, r1.x)
 
 
-def test_dense_one_hop_equals_two_hop(cuda, rsk_lib):
+@pytest.mark.parametrize("kernel,eta", [
+    (1, 80),   # general kernel: 48*80 <= 4096 words, one hop; 56*80 > 4096, two hops
+    (2, 40),   # register tile: 48*40 <= 2048 words, one hop; 56*40 > 2048, two hops
+])
+def test_dense_one_hop_equals_two_hop(cuda, rsk_lib, kernel, eta):
     """Both cross-workgroup reductions (every workgroup gathers all partials; row owners reduce) match the oracle."""
     import torch
-    sysd, idx = _case(3000, 2048, 40, "f32", 5, 80, 50, 1.0)
-    alpha = _alpha_star(sysd["A"], 80)
-    a = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=80, alpha=alpha, K=50, grid=48)   # 48*80 <= 4096: one hop
-    b = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=80, alpha=alpha, K=50, grid=56)   # 56*80 > 4096: two hops
-    ref = oracle.rska_dense(sysd["A"], sysd["b"], 1.0, 80, alpha, 50, idx)
+    sysd, idx = _case(3000, 2048, 40, "f32", 5, eta, 50, 1.0)
+    alpha = _alpha_star(sysd["A"], eta)
+    a = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=eta, alpha=alpha, K=50, grid=48, kernel=kernel)
+    b = _gpu_solve(sysd, idx, cuda, lam=1.0, eta=eta, alpha=alpha, K=50, grid=56, kernel=kernel)
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 1.0, eta, alpha, 50, idx)
     assert _rel(a.x.cpu().numpy(), ref["x"]) <= 1e-4
     assert _rel(b.x.cpu().numpy(), ref["x"]) <= 1e-4
 
@@ -141,8 +146,8 @@ def test_dense_k0_and_rk_special_case(cuda, rsk_lib):
     assert _rel(res.x.cpu().numpy(), ref["x"]) <= 1e-10
 
 
-@pytest.mark.parametrize("grid", [1, 6])
-def test_dense_device_errors(cuda, rsk_lib, grid):
+@pytest.mark.parametrize("grid,kernel", [(1, 1), (6, 1), (0, 0)])
+def test_dense_device_errors(cuda, rsk_lib, grid, kernel):
     import torch
     from paper_2203_10838_amd import rsk
     sysd, idx = _case(200, 64, 4, "f32", 11, 4, 30, 0.5)
@@ -150,19 +155,19 @@ def test_dense_device_errors(cuda, rsk_lib, grid):
     bad = idx.copy()
     bad[7 * 4 + 2] = 200
     with pytest.raises(rsk.RskError) as e:
-        _gpu_solve(sysd, bad, cuda, lam=0.5, eta=4, alpha=1.0, K=30, grid=grid)
+        _gpu_solve(sysd, bad, cuda, lam=0.5, eta=4, alpha=1.0, K=30, grid=grid, kernel=kernel)
     assert e.value.name == "RSK_ERR_INDEX_RANGE"
     # a referenced zero row
     z = dict(sysd)
     z["A"] = sysd["A"].copy()
     z["A"][idx[5 * 4 + 1]] = 0.0
     with pytest.raises(rsk.RskError) as e:
-        _gpu_solve(z, idx, cuda, lam=0.5, eta=4, alpha=1.0, K=30, grid=grid)
+        _gpu_solve(z, idx, cuda, lam=0.5, eta=4, alpha=1.0, K=30, grid=grid, kernel=kernel)
     assert e.value.name == "RSK_ERR_ZERO_ROW"
     # relaxation far beyond the stability bound: the iterate blows up
     with pytest.raises(rsk.RskError) as e:
         _gpu_solve(sysd, inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), 3000, 4, 5), cuda,
-                   lam=0.5, eta=4, alpha=1e6, K=3000, grid=grid)
+                   lam=0.5, eta=4, alpha=1e6, K=3000, grid=grid, kernel=kernel)
     assert e.value.name == "RSK_ERR_NONFINITE"
 
 
