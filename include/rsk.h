@@ -268,7 +268,7 @@ int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
  * selects the kernel: 1 = one persistent workgroup (no cross-CU exchange),
  * 2 = the multi-workgroup kernel (one lane per nonzero, p->grid workgroups or
  * eta/8 up to the CU count, three grid barriers per step), 0 = 2 when
- * eta >= 64, else 1. Columns hit by several sampled rows of a step are summed
+ * eta >= 4, else 1. Columns hit by several sampled rows of a step are summed
  * in int64 fixed point with a per-step power-of-two quantum (2^-41 of the
  * step's largest contribution), so results are bitwise reproducible for a
  * given kernel. eta <= 4096.

@@ -248,7 +248,7 @@ int32_t plan_csr(const rsk_csr* A, const rsk_params* p, CsrPlan* pl) {
   const int cus = device_cus() > 0 ? device_cus() : 1;
   const int rpp = rsk::kCsrGridRowsPerPass;
   if (p->kernel == 3) return RSK_ERR_INVALID_ARG;  // a dense kernel
-  const bool grid = p->kernel == 2 || (p->kernel == 0 && p->eta >= 64);
+  const bool grid = p->kernel == 2 || (p->kernel == 0 && p->eta >= 4);
   pl->kernel = grid ? 2 : 1;
   pl->G = 1;
   size_t o = align256((size_t)(A->n + 1) * sizeof(long long));

@@ -55,6 +55,8 @@ def _gpu_solve(sysd, idx, dev, **kw):
     ("f32", 600, 333, 9, 300, 3, 0.3),        # odd n, 3 slices
     ("f32", 2000, 1024, 130, 60, 64, 1.0),    # two-hop reduce (G*eta > 4096)
     ("f32", 1500, 600, 64, 80, 1, 2.0),       # single workgroup
+    ("f32", 3000, 2001, 20, 100, 0, 1.0),     # default grid: 160 KB a step over 40 workgroups
+    ("f64", 2000, 8192, 128, 30, 0, 1.0),     # default grid at 8 MB a step: every CU
 ])
 def test_dense_matches_oracle(cuda, rsk_lib, dtype, m, n, eta, K, grid, lam):
     sysd, idx = _case(m, n, max(1, n // 20), dtype, 1234 + m, eta, K, lam)
