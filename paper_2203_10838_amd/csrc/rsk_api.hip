@@ -92,8 +92,8 @@ int32_t check_dense(const rsk_dense* A) {
 }
 
 // float32 register-tile plan: one 1024-thread workgroup per CU (512 for eta > 768), eta <= 1024,
-// rg row groups of G/rg column slices, each slice at most 5*rg units of 16 floats. Returns false if
-// it does not apply.
+// rg row groups of G/rg column slices, each slice at most 5*rg units of 16 floats. Returns false,
+// with *pl unchanged, if it does not apply.
 bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, int rg, DensePlan* pl) {
   if (A->dtype != RSK_F32 || (A->n % 4) != 0 || (A->ld % 4) != 0 || (((uintptr_t)A->val) % 16) != 0) return false;
   const int64_t nchunks = (A->n + 3) / 4;
@@ -114,14 +114,17 @@ bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, int rg, DensePlan* p
   const int rpp = nt / (4 * rg);  // group rows of one pass
   const int rp = (etaR + rpp - 1) / rpp;
   if (rsk::dense_rt_max_grid(nt, rp, cpl, rg) < G) return false;
+  int two_hop = ((int64_t)C * etaR) > rsk::kRtOneHopWords;
+  // each wave reduces at most kRtOwnMax rows per step
+  const int own = rsk::kRtOwnMax * (nt / 64);
+  if (!two_hop && etaR > own) two_hop = 1;
+  if (two_hop && (etaR + C - 1) / C > own) return false;
+  // the plan is written only once the kernel applies: a caller falls back to the general
+  // kernel with *pl as it was
   pl->kernel = 2; pl->nt = nt; pl->rp = rp; pl->cpl = cpl; pl->rg = rg;
   pl->vec = 4; pl->W = 1; pl->nchunks = nchunks; pl->G = G;
   pl->wq_max = 4 * rg * cpl; pl->lpr = 4; pl->tile_cache = 0;
-  pl->two_hop = ((int64_t)C * etaR) > rsk::kRtOneHopWords;
-  // each wave reduces at most kRtOwnMax rows per step
-  const int own = rsk::kRtOwnMax * (nt / 64);
-  if (!pl->two_hop && etaR > own) pl->two_hop = 1;
-  if (pl->two_hop && (etaR + C - 1) / C > own) return false;
+  pl->two_hop = two_hop;
   const int cap = dense_grid_cap(A, p);
   const size_t uwords = rg > 1 ? 2 * (size_t)G * 16 * rg * cpl : 0;
   dense_ws_layout(cap > G ? cap : G, p->eta, 1, uwords, pl);

@@ -137,6 +137,18 @@ def test_dense_monitor_and_early_stop(cuda, rsk_lib):
     assert res2.k_done == kstar
 
 
+@pytest.mark.parametrize("m,n,eta,K", [(5, 4, 1, 40), (10, 8, 3, 50), (33, 20, 7, 60), (64, 16, 70, 30)])
+def test_tiny_float32_library_choice(cuda, rsk_lib, m, n, eta, K):
+    """Tiny aligned float32 systems through the library's choice (the register tile on one or two
+    workgroups), more rows a step than the system has included."""
+    sysd, idx = _case(m, n, max(1, n // 4), "f32", 300 + m, eta, K, 0.2)
+    res = _gpu_solve(sysd, idx, cuda, lam=0.2, eta=eta, alpha=1.0, K=K)
+    assert res.status == 0 and res.k_done == K
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 0.2, eta, 1.0, K, idx)
+    assert _rel(res.x_star.cpu().numpy(), ref["z"]) <= TOL["f32"]
+    assert _rel(res.x.cpu().numpy(), ref["x"]) <= TOL["f32"]
+
+
 def test_dense_k0_and_rk_special_case(cuda, rsk_lib):
     import torch
     sysd, idx = _case(60, 40, 5, "f64", 3, 1, 500, 0.0)
