@@ -149,6 +149,30 @@ def test_tiny_float32_library_choice(cuda, rsk_lib, m, n, eta, K):
     assert _rel(res.x.cpu().numpy(), ref["x"]) <= TOL["f32"]
 
 
+@pytest.mark.parametrize("m,n,eta,K,ld,off", [
+    (300, 130, 16, 50, 130, 0),      # n % 4 != 0: the general kernel
+    (300, 128, 16, 50, 132, 0),      # padded rows, ld % 4 == 0: the register tile
+    (300, 128, 16, 50, 131, 0),      # ld % 4 != 0: the general kernel, scalar loads
+    (300, 128, 16, 50, 129, 1),      # base not 16-byte aligned: the general kernel
+    (2000, 256, 1025, 8, 256, 0),    # eta above the register tile's 1024
+    (300, 20544, 8, 30, 20544, 0),   # slices wider than 80 columns on 256 workgroups
+])
+def test_float32_library_choice_layouts(cuda, rsk_lib, m, n, eta, K, ld, off):
+    """The library's choice over row pitches, offsets and sizes on both sides of the register
+    tile's limits: every case matches the oracle."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    sysd, idx = _case(m, n, max(1, n // 20), "f32", 700 + n + ld, eta, K, 0.5)
+    full = torch.zeros((m, ld), dtype=torch.float32, device=cuda)
+    full[:, off:off + n] = _to(sysd["A"], cuda)
+    A = full[:, off:off + n]
+    res = rsk.solve_dense(A, _to(sysd["b"], cuda), lam=0.5, eta=eta, alpha=1.0, K=K, index_stream=_to(idx, cuda))
+    assert res.status == 0 and res.k_done == K
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], 0.5, eta, 1.0, K, idx)
+    assert _rel(res.x_star.cpu().numpy(), ref["z"]) <= TOL["f32"]
+    assert _rel(res.x.cpu().numpy(), ref["x"]) <= TOL["f32"]
+
+
 def test_dense_k0_and_rk_special_case(cuda, rsk_lib):
     import torch
     sysd, idx = _case(60, 40, 5, "f64", 3, 1, 500, 0.0)
