@@ -20,7 +20,7 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-KERNELS = pytest.mark.parametrize("kernel", [1, 2], ids=["one_workgroup", "grid"])
+KERNELS = pytest.mark.parametrize("kernel", [1, 2, 0], ids=["one_workgroup", "grid", "library_choice"])
 
 
 def _solve(c, idx, dev, **kw):
