@@ -254,7 +254,7 @@ int32_t rsk_workspace_size_csr(const rsk_csr *A, const rsk_params *p, size_t *by
  * as wide (at most 160 columns), and the two workgroups of a slice add their
  * parts of the x* update in a third exchange (same requirements as 2, an
  * even number of workgroups). 0 = the
- * library's choice: for float32, 3 for 128 <= eta <= 768, else 2, where the
+ * library's choice: for float32, 3 for 88 <= eta <= 800, else 2, where the
  * register tile applies; else 1. Kernels 2 and 3 sum in
  * different orders (results agree to rounding); each is bitwise reproducible.
  * A kernel that does not apply to the shape returns RSK_ERR_UNSUPPORTED.

@@ -21,9 +21,9 @@ constexpr int kMinSpreadG = 16, kMaxSpreadG = 128;
 constexpr size_t kFullGridStepBytes = size_t(8) << 20;
 using rsk::kOneHopWords;
 // the automatic choice takes two row groups of the register-tile kernel for eta in this range
-// (1024-thread workgroups; below it the step is bound by the exchange, and at 512 threads the
-// third exchange hop costs more than the wider row pieces save)
-constexpr int kRtTwoGroupMinEta = 128, kRtTwoGroupMaxEta = 768;
+// (measured on 20000 columns: below it one group is as fast, the step being bound by the
+// exchange; above it the third exchange hop costs more than the wider row pieces save)
+constexpr int kRtTwoGroupMinEta = 88, kRtTwoGroupMaxEta = 800;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t elem_size(int32_t dt) { return dt == RSK_F64 ? 8 : 4; }

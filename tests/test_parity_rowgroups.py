@@ -191,13 +191,13 @@ def test_two_row_groups_headline_workload(cuda, rsk_lib):
 
 
 def test_library_choice_of_row_groups(cuda, rsk_lib):
-    """kernel = 0 takes two row groups for 128 <= eta <= 768 (bitwise the kernel = 3 result) and one
-    group for eta = 1024 (bitwise kernel = 2) on the same 20000-column float32 system."""
+    """kernel = 0 takes two row groups for 88 <= eta <= 800 (bitwise the kernel = 3 result) and one
+    group outside that range (bitwise kernel = 2) on the same 20000-column float32 system."""
     import torch
     from paper_2203_10838_amd import rsk
     sysd = inputs.dense_system_device(6000, 20000, 100, seed=77, noise_rel=0.01, device=cuda)
     A, b = sysd["A"], torch.from_numpy(sysd["b"]).to(cuda)
-    for eta, twin in ((128, 3), (300, 3), (768, 3), (1024, 2), (64, 2)):
+    for eta, twin in ((88, 3), (300, 3), (800, 3), (801, 2), (1024, 2), (87, 2), (64, 2)):
         idx = _to(inputs.index_stream(sysd["weights"], 12, eta, 78 + eta), cuda)
         auto = rsk.solve_dense(A, b, lam=1.0, eta=eta, alpha=0.5 * eta, K=12, index_stream=idx, kernel=0)
         same = rsk.solve_dense(A, b, lam=1.0, eta=eta, alpha=0.5 * eta, K=12, index_stream=idx, kernel=twin)
