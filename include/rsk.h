@@ -263,6 +263,17 @@ int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
                             void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * The launch rsk_avg_solve_dense would make for A and p, without making it
+ * (nothing is queued; A->val is only inspected for its alignment). out:
+ * host int32[8] = { kernel (1 general, 2 register tile, 3 register tile over
+ * two row groups), workgroups G, threads per workgroup, row passes and float4
+ * chunks per lane of the register tile (0 for the general kernel), row groups,
+ * exchange hops per step (1 or 2), elements per vector load }. Returns what
+ * rsk_avg_solve_dense would return for an unsupported shape or bad argument.
+ */
+int32_t rsk_plan_dense(const rsk_dense *A, const rsk_params *p, int32_t *out);
+
+/*
  * The same iteration with A in CSR form (eq. (rska) with sparse rows).
  * A sparse step moves a few hundred KB and is bound by latency. p->kernel
  * selects the kernel: 1 = one persistent workgroup (no cross-CU exchange),
@@ -331,6 +342,15 @@ int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item 
 int32_t rsk_workspace_size_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, size_t *bytes);
 int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p, void *X_star,
                                void *X, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * The split of rsk_avg_solve_multirhs's two products for A, R and p, without
+ * running it. out: host int32[4] = { S: splits of the n columns in A_tau X
+ * (fixed-order sum of S partials), columns per split, S2: splits of a step's
+ * rows in A_tau^T C (1: one workgroup per 64 x 64 output tile over all rows),
+ * eta rounded up to a multiple of 64 }.
+ */
+int32_t rsk_plan_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, int32_t *out);
 
 /*
  * rsk_avg_solve_multirhs that also writes the x* checkpoints the adjoint

@@ -62,10 +62,11 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (-O2, no BLAS, no fast-math)."""
+    """Compile the C oracle with gcc (-O2, no BLAS, no fast-math; OpenMP only spreads independent
+    rows and column blocks of a step over threads, never reorders a sum)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
                                "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -82,6 +83,7 @@ def _load():
             lib.oracle_rownorm2_csr.argtypes = [i64, vp, vp, vp]
             lib.oracle_rska_dense.argtypes = [i64, i64, i64, vp, vp, dbl, i32, dbl, vp, vp, i64, vp, i64,
                                               vp, vp, vp, i64, vp, vp, vp]
+            lib.oracle_rska_dense_threads.argtypes = lib.oracle_rska_dense.argtypes + [i32]
             lib.oracle_rska_csr.argtypes = [i64, i64, vp, vp, vp, vp, dbl, i32, dbl, vp, vp, i64, vp, i64,
                                             vp, vp, vp, i64, vp, vp, vp]
             lib.oracle_rska_dense_adjoint.argtypes = [i64, i64, i64, vp, vp, dbl, i32, vp, i64, vp, i64,
@@ -93,6 +95,7 @@ def _load():
             lib.oracle_lb_dense.argtypes = [i64, i64, i64, vp, vp, dbl, dbl, i64, vp, vp, i64, vp, vp, vp]
             lib.oracle_power_ata.argtypes = [i64, i64, i64, vp, i64, vp, vp]
             for f in (lib.oracle_rownorm2_dense, lib.oracle_rownorm2_csr, lib.oracle_rska_dense,
+                      lib.oracle_rska_dense_threads,
                       lib.oracle_rska_csr, lib.oracle_rska_dense_adjoint, lib.oracle_sampling_cdf,
                       lib.oracle_sample_stream, lib.oracle_lb_dense, lib.oracle_power_ata):
                 f.restype = ctypes.c_int
@@ -167,6 +170,7 @@ def sampling_matrix(A, tau, weights):
 # ---------------------------------------------------------------------------
 
 def rownorm2_dense(A):
+    """||a_i||^2 of every row (j ascending, FP64): the squared diagonal of D in Definition 1."""
     A = _f64(A)
     m, n = A.shape
     r2 = np.empty(m)
@@ -177,6 +181,7 @@ def rownorm2_dense(A):
 
 
 def rownorm2_csr(row_ptr, val):
+    """||a_i||^2 of every CSR row (stored order, FP64)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
     val = _f64(val)
     m = len(row_ptr) - 1
@@ -199,7 +204,7 @@ def _common_out(n, m, z0, want_y, y0, K, check_every):
 
 
 def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None, z0=None, want_y=False,
-               y0=None, check_every=0, xref=None, raise_on_error=True):
+               y0=None, check_every=0, xref=None, raise_on_error=True, threads=1):
     """Dense RSKA, eq. (rska) / Algorithm 1, in FP64 (see ``rska_oracle.c``).
 
     A (m x n) and b are upcast exactly to float64. ``row_w`` (m, optional) are
@@ -207,6 +212,9 @@ def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None
     row i is relaxed by alpha (or alpha_k[k]) times w_i. Returns a dict with
     z (= x*_K), x (= S_lambda(z)), y (dual, if want_y), hist (relative errors
     every ``check_every`` steps if xref is given), k_done and status.
+
+    ``threads`` > 1 computes a step's eta residuals, and blocks of the columns of delta_k, on
+    several threads; every sum keeps its order, so the result is the same bits.
     """
     A = _f64(A)
     b = _f64(b)
@@ -217,9 +225,10 @@ def rska_dense(A, b, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None
     z, x, y, hist, nh = _common_out(n, m, z0, want_y, y0, K, check_every)
     xr = None if xref is None else _f64(xref)
     kd = np.zeros(1, dtype=np.int64)
-    st = _load().oracle_rska_dense(m, n, n, _p(A), _p(b), float(lam), int(eta), float(alpha), _p(ak), _p(rw),
-                                   int(K), _p(idx), int(off), _p(z), _p(x), _p(y),
-                                   int(check_every) if xr is not None else 0, _p(xr), _p(hist), _p(kd))
+    st = _load().oracle_rska_dense_threads(m, n, n, _p(A), _p(b), float(lam), int(eta), float(alpha), _p(ak),
+                                           _p(rw), int(K), _p(idx), int(off), _p(z), _p(x), _p(y),
+                                           int(check_every) if xr is not None else 0, _p(xr), _p(hist), _p(kd),
+                                           int(threads))
     if st and raise_on_error:
         raise OracleError(st, "rska_dense")
     return {"z": z, "x": x, "y": y, "hist": hist[:nh], "k_done": int(kd[0]), "status": st}
@@ -247,7 +256,8 @@ def rska_csr(row_ptr, col, val, n, b, lam, eta, alpha, K, idx, *, off=0, alpha_k
     return {"z": z, "x": x, "y": y, "hist": hist[:nh], "k_done": int(kd[0]), "status": st}
 
 
-def rska_dense_rows(rows_of, b, m, n, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None, z0=None):
+def rska_dense_rows(rows_of, b, m, n, lam, eta, alpha, K, idx, *, off=0, alpha_k=None, row_w=None, z0=None,
+                    threads=1):
     """Dense RSKA on a matrix too large to hand over whole.
 
     Only the rows that the stream references enter the iteration, so the
@@ -263,7 +273,8 @@ def rska_dense_rows(rows_of, b, m, n, lam, eta, alpha, K, idx, *, off=0, alpha_k
     Asub = _f64(rows_of(uniq))
     bsub = _f64(np.asarray(b)[uniq]) if not callable(b) else _f64(b(uniq))
     rw = None if row_w is None else _f64(np.asarray(row_w)[uniq])
-    return rska_dense(Asub, bsub, lam, eta, alpha, K, inv.astype(np.int32), alpha_k=alpha_k, row_w=rw, z0=z0)
+    return rska_dense(Asub, bsub, lam, eta, alpha, K, inv.astype(np.int32), alpha_k=alpha_k, row_w=rw, z0=z0,
+                      threads=threads)
 
 
 def rska_multirhs(A, B, lam, eta, alpha, K, idx, **kw):

@@ -30,6 +30,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_INVALID 1
@@ -99,41 +102,66 @@ static double rel_err(int64_t n, const double *x, const double *xref) {
  * If check_every > 0 and xref/err_hist are given, err_hist[q] receives the
  * relative error after step (q+1)*check_every.
  * *k_done receives the number of completed steps (nullable).
+ *
+ * nthreads > 1 spreads the eta residuals of a step (independent of each
+ * other: Algorithm 1 computes them "in parallel" at the same x_k) and the
+ * columns of delta_k over threads. No sum changes its order: every dot runs j
+ * ascending inside one thread, and every delta_j runs t ascending inside the
+ * thread that owns column j. The result is the same bits for any nthreads.
  */
-int oracle_rska_dense(int64_t m, int64_t n, int64_t ld, const double *A, const double *b,
-                      double lambda, int32_t eta, double alpha, const double *alpha_k,
-                      const double *row_w, int64_t K, const int32_t *idx, int64_t off,
-                      double *z, double *x, double *y,
-                      int64_t check_every, const double *xref, double *err_hist,
-                      int64_t *k_done) {
+int oracle_rska_dense_threads(int64_t m, int64_t n, int64_t ld, const double *A, const double *b,
+                              double lambda, int32_t eta, double alpha, const double *alpha_k,
+                              const double *row_w, int64_t K, const int32_t *idx, int64_t off,
+                              double *z, double *x, double *y,
+                              int64_t check_every, const double *xref, double *err_hist,
+                              int64_t *k_done, int32_t nthreads) {
   int st = check_common(m, n, lambda, eta, alpha, alpha_k, K, idx, b, z, x);
   if (st) return st;
   if (!A || ld < n) return OR_INVALID;
+  if (nthreads < 1) nthreads = 1;
   if (k_done) *k_done = 0;
   double *c = (double *)malloc(sizeof(double) * (size_t)eta);
+  double *rn = (double *)malloc(sizeof(double) * (size_t)eta);
   double *delta = (double *)malloc(sizeof(double) * (size_t)n);
-  if (!c || !delta) { free(c); free(delta); return OR_INVALID; }
+  if (!c || !rn || !delta) { free(c); free(rn); free(delta); return OR_INVALID; }
 
   for (int64_t j = 0; j < n; ++j) x[j] = shrink(z[j], lambda);
   for (int64_t k = 0; k < K; ++k) {
     const int32_t *tau = idx + off + k * (int64_t)eta;
     double ak = alpha_k ? alpha_k[k] : alpha;
     /* residuals of all eta rows at the same x_k, then the coefficients */
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 4) if (nthreads > 1)
     for (int32_t t = 0; t < eta; ++t) {
       int64_t i = tau[t];
-      if (i < 0 || i >= m) { st = OR_INDEX; goto done; }
+      rn[t] = -1.0;
+      if (i < 0 || i >= m) continue;
       const double *ai = A + i * ld;
       double r2 = 0.0, dot = 0.0;
       for (int64_t j = 0; j < n; ++j) r2 += ai[j] * ai[j];
-      if (r2 == 0.0) { st = OR_ZERO_ROW; goto done; }
       for (int64_t j = 0; j < n; ++j) dot += ai[j] * x[j];
-      c[t] = ((row_w ? ak * row_w[i] : ak) / (double)eta) * (dot - b[i]) / r2;
+      rn[t] = r2;
+      if (r2 != 0.0) c[t] = ((row_w ? ak * row_w[i] : ak) / (double)eta) * (dot - b[i]) / r2;
+    }
+    /* the first bad row in t order decides the error */
+    for (int32_t t = 0; t < eta; ++t) {
+      if (tau[t] < 0 || tau[t] >= m) { st = OR_INDEX; goto done; }
+      if (rn[t] == 0.0) { st = OR_ZERO_ROW; goto done; }
     }
     /* delta_k = sum_t c_t a_{tau_t}, formed first, then subtracted */
-    for (int64_t j = 0; j < n; ++j) delta[j] = 0.0;
-    for (int32_t t = 0; t < eta; ++t) {
-      const double *ai = A + (int64_t)tau[t] * ld;
-      for (int64_t j = 0; j < n; ++j) delta[j] += c[t] * ai[j];
+#pragma omp parallel num_threads(nthreads) if (nthreads > 1)
+    {
+#ifdef _OPENMP
+      const int nth = omp_get_num_threads(), me = omp_get_thread_num();
+#else
+      const int nth = 1, me = 0;
+#endif
+      const int64_t per = ((n + nth - 1) / nth + 7) / 8 * 8;
+      const int64_t j0 = per * me < n ? per * me : n, j1 = j0 + per < n ? j0 + per : n;
+      for (int64_t j = j0; j < j1; ++j) delta[j] = 0.0;
+      for (int32_t t = 0; t < eta; ++t) {
+        const double *ai = A + (int64_t)tau[t] * ld;
+        for (int64_t j = j0; j < j1; ++j) delta[j] += c[t] * ai[j];
+      }
     }
     int finite = 1;
     for (int64_t j = 0; j < n; ++j) {
@@ -150,8 +178,19 @@ int oracle_rska_dense(int64_t m, int64_t n, int64_t ld, const double *A, const d
   }
 done:
   free(c);
+  free(rn);
   free(delta);
   return st;
+}
+
+int oracle_rska_dense(int64_t m, int64_t n, int64_t ld, const double *A, const double *b,
+                      double lambda, int32_t eta, double alpha, const double *alpha_k,
+                      const double *row_w, int64_t K, const int32_t *idx, int64_t off,
+                      double *z, double *x, double *y,
+                      int64_t check_every, const double *xref, double *err_hist,
+                      int64_t *k_done) {
+  return oracle_rska_dense_threads(m, n, ld, A, b, lambda, eta, alpha, alpha_k, row_w, K, idx, off, z, x, y,
+                                   check_every, xref, err_hist, k_done, 1);
 }
 
 /*

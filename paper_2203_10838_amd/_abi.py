@@ -54,6 +54,7 @@ SIGNATURES = {
                                          ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                     c_vp, c_sz, c_vp]),
+    "rsk_plan_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(RskParams), ctypes.POINTER(c_i32)]),
     "rsk_rownorm2_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, c_vp]),
     "rsk_avg_solve_multirhs_ckpt": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_i32,
                                             c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
@@ -80,6 +81,7 @@ SIGNATURES = {
                                             ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_vp, c_vp,
                                        c_vp, c_sz, c_vp]),
+    "rsk_plan_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams), ctypes.POINTER(c_i32)]),
     "rsk_workspace_size_csr": (c_i32, [ctypes.POINTER(RskCsr), ctypes.POINTER(RskParams), ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                   c_vp, c_sz, c_vp]),

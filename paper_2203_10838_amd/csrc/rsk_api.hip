@@ -604,6 +604,22 @@ int32_t rsk_workspace_size_multirhs(const rsk_dense* A, int32_t R, const rsk_par
   return RSK_OK;
 }
 
+int32_t rsk_plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t* out) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!out) return RSK_ERR_INVALID_ARG;
+  st = check_params(p, A->m);
+  if (st) return st;
+  MultiPlan pl;
+  st = plan_multirhs(A, R, p, &pl);
+  if (st) return st;
+  out[0] = pl.S;
+  out[1] = (int32_t)pl.kspan;
+  out[2] = pl.S2;
+  out[3] = pl.eta_pad;
+  return RSK_OK;
+}
+
 int32_t rsk_avg_solve_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_params* p, void* X_star,
                                void* X, void* workspace, size_t ws_bytes, void* stream) {
   int32_t st = check_dense(A);
@@ -887,6 +903,28 @@ int32_t rsk_workspace_size_dense(const rsk_dense* A, const rsk_params* p, size_t
   st = A->dtype == RSK_F64 ? plan_dense<double>(A, p, &pl) : plan_dense<float>(A, p, &pl);
   if (st) return st;
   *bytes = pl.bytes;
+  return RSK_OK;
+}
+
+int32_t rsk_plan_dense(const rsk_dense* A, const rsk_params* p, int32_t* out) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (!out) return RSK_ERR_INVALID_ARG;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (p->eta > kMaxEtaDense) return RSK_ERR_UNSUPPORTED;
+  DensePlan pl;
+  st = A->dtype == RSK_F64 ? plan_dense<double>(A, p, &pl) : plan_dense<float>(A, p, &pl);
+  if (st) return st;
+  const bool rt = pl.kernel == 2;
+  out[0] = rt ? (pl.rg > 1 ? 3 : 2) : 1;
+  out[1] = pl.G;
+  out[2] = rt ? pl.nt : rsk::kDenseThreads;
+  out[3] = rt ? pl.rp : 0;
+  out[4] = rt ? pl.cpl : 0;
+  out[5] = pl.rg;
+  out[6] = pl.two_hop ? 2 : 1;
+  out[7] = pl.vec;
   return RSK_OK;
 }
 

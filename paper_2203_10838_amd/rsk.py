@@ -106,6 +106,39 @@ def workspace_size_dense(A: torch.Tensor, params: _abi.RskParams) -> int:
     return int(nbytes.value)
 
 
+PLAN_FIELDS = ("kernel", "G", "threads", "row_passes", "chunks_per_lane", "row_groups", "hops", "vec")
+
+
+def plan_dense(A: torch.Tensor, *, eta: int, K: int = 1, grid: int = 0, kernel: int = 0, lam: float = 0.0,
+               alpha: float = 1.0) -> dict:
+    """The launch rsk_avg_solve_dense would make for A, eta, grid and kernel (nothing is queued):
+    the kernel (1 general, 2 register tile, 3 register tile over two row groups), its workgroups,
+    threads, row passes and chunks per lane, row groups, exchange hops and vector width."""
+    d = dense_desc(A)
+    dummy = torch.empty(2, dtype=torch.int32, device=A.device)
+    params = _abi.RskParams(float(lam), int(eta), float(alpha), None, int(K), dummy.data_ptr(), 0,
+                            A.data_ptr(), 0, None, 0, 0.0, None, None, dummy.data_ptr(), int(grid), int(kernel), None)
+    out = (ctypes.c_int32 * 8)()
+    st = _lib().rsk_plan_dense(ctypes.byref(d), ctypes.byref(params), out)
+    if st:
+        raise RskError(st, "rsk_plan_dense")
+    return dict(zip(PLAN_FIELDS, [int(v) for v in out]))
+
+
+def plan_multirhs(A: torch.Tensor, R: int, *, eta: int, K: int = 1) -> dict:
+    """The split rsk_avg_solve_multirhs would use (nothing is queued): S column splits of A_tau X
+    (and the columns per split), S2 row splits of A_tau^T C, eta padded to a multiple of 64."""
+    d = dense_desc(A)
+    dummy = torch.empty(2, dtype=torch.int32, device=A.device)
+    params = _abi.RskParams(0.0, int(eta), 1.0, None, int(K), dummy.data_ptr(), 0, A.data_ptr(), 0, None, 0, 0.0,
+                            None, None, dummy.data_ptr(), 0, 0, None)
+    out = (ctypes.c_int32 * 4)()
+    st = _lib().rsk_plan_multirhs(ctypes.byref(d), int(R), ctypes.byref(params), out)
+    if st:
+        raise RskError(st, "rsk_plan_multirhs")
+    return dict(zip(("S", "kspan", "S2", "eta_pad"), [int(v) for v in out]))
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     # torch's caching allocator returns blocks aligned to at least 512 bytes
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)

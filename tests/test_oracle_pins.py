@@ -633,3 +633,85 @@ def test_v4_coupling_and_convergence():
     assert np.abs(counts - p).max() <= 6 * np.sqrt(p.max() / idx.size)
     out = oracle.rska_dense(A, c["b"], 0.5, eta, 1.0, K, idx, row_w=rho)
     assert _rel(out["x"], c["xhat"]) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Row norms, rows-in-stream selection, threaded steps
+# ---------------------------------------------------------------------------
+
+def test_rownorm2_closed_forms():
+    """||a_i||^2 (the squared diagonal of D, Definition 1) on matrices whose row norms are known
+    exactly: a +-1 Hadamard matrix (every row n), a scaled permutation (the scale squared), and
+    small-integer rows (sums of squares of integers are exact in FP64)."""
+    H = np.array([[1.0]])
+    while H.shape[0] < 64:
+        H = np.block([[H, H], [H, -H]])
+    assert np.array_equal(oracle.rownorm2_dense(H), np.full(64, 64.0))
+    P = np.zeros((7, 9))
+    scales = np.array([0.5, 3.0, -2.0, 1.25, 7.0, -0.75, 1.0])
+    P[np.arange(7), [8, 3, 0, 5, 1, 7, 2]] = scales
+    assert np.array_equal(oracle.rownorm2_dense(P), scales ** 2)
+    rng = _rng(41)
+    I = rng.integers(-9, 10, size=(50, 33)).astype(np.float64)
+    want = np.array([sum(int(v) * int(v) for v in row) for row in I.astype(np.int64)], dtype=np.float64)
+    assert np.array_equal(oracle.rownorm2_dense(I), want)
+    # a zero row has norm 0 (the case Algorithm 1 excludes); CSR of the same rows agrees
+    I[4] = 0.0
+    assert oracle.rownorm2_dense(I)[4] == 0.0
+    rp = np.concatenate([[0], np.cumsum(np.full(50, 33))]).astype(np.int64)
+    assert np.array_equal(oracle.rownorm2_csr(rp, I.ravel()), oracle.rownorm2_dense(I))
+
+
+def test_threaded_steps_are_the_same_bits():
+    """The eta residuals of a step are independent (Algorithm 1 computes them at the same x_k), and
+    each column of delta_k is its own sum: spreading them over threads changes no bit, with
+    weights, per-step alpha, the dual and the monitor."""
+    A = _rng(42).normal(size=(400, 333))
+    xh = np.zeros(333)
+    xh[_rng(43).choice(333, 12, replace=False)] = _rng(44).normal(size=12)
+    b = A @ xh
+    idx = _stream(A, 120, 37, 45)
+    w = inputs.row_weights(400, 46, "f64", lo=0.1)
+    ak = np.linspace(3.0, 20.0, 120)
+    kw = dict(alpha_k=ak, row_w=w, want_y=True, check_every=10, xref=xh)
+    one = oracle.rska_dense(A, b, 0.4, 37, 1.0, 120, idx, **kw)
+    for th in (2, 5, 8):
+        many = oracle.rska_dense(A, b, 0.4, 37, 1.0, 120, idx, threads=th, **kw)
+        for key in ("z", "x", "y", "hist"):
+            assert np.array_equal(one[key], many[key]), (th, key)
+    assert np.count_nonzero(one["x"]) > 0
+    # the first bad row in t order decides the error, as in the sequential loop
+    bad = idx.copy()
+    bad[5 * 37 + 30] = 400
+    Az = A.copy()
+    Az[bad[5 * 37 + 10]] = 0.0
+    for th in (1, 4):
+        r = oracle.rska_dense(Az, b, 0.4, 37, 8.0, 120, bad, threads=th, raise_on_error=False)
+        assert r["status"] == oracle.ZERO_ROW and r["k_done"] == 5
+
+
+def test_rows_in_stream_equals_the_whole_matrix():
+    """A step reads only its sampled rows (eq. (rska)): the oracle on the rows a stream references,
+    renumbered, gives the bits of the oracle on the whole matrix, whose other rows are NaN here
+    (any read of them would show)."""
+    A = _rng(47).normal(size=(900, 120))
+    xh = np.zeros(120)
+    xh[:6] = 1.5
+    b = A @ xh
+    K, eta = 30, 8
+    idx = _stream(A, K, eta, 48)
+    used = np.unique(idx)
+    assert used.size < 900
+    An = np.full_like(A, np.nan)
+    An[used] = A[used]
+    full = oracle.rska_dense(An, b, 0.3, eta, 5.0, K, idx)
+    sub = oracle.rska_dense_rows(lambda rows: A[rows], b, 900, 120, 0.3, eta, 5.0, K, idx)
+    assert np.array_equal(full["z"], sub["z"]) and np.array_equal(full["x"], sub["x"])
+    assert np.all(np.isfinite(full["z"])) and np.count_nonzero(full["x"]) > 0
+    # with an offset into the stream and a warm start (the resumed run)
+    half = oracle.rska_dense(A, b, 0.3, eta, 5.0, 12, idx)
+    rest = oracle.rska_dense_rows(lambda rows: A[rows], b, 900, 120, 0.3, eta, 5.0, K - 12, idx, off=12 * eta,
+                                  z0=half["z"])
+    assert np.array_equal(rest["z"], oracle.rska_dense(A, b, 0.3, eta, 5.0, K, idx)["z"])
+    with pytest.raises(oracle.OracleError):
+        oracle.rska_dense_rows(lambda rows: A[rows], b, 900, 120, 0.3, eta, 5.0, K, np.where(idx == idx[3], 900, idx))

@@ -1,9 +1,11 @@
-"""GPU parity of the multi-RHS (matrix-core) RSKA path: every column against the single-RHS FP64 oracle."""
+"""GPU parity of the multi-RHS (matrix-core) RSKA path: every column against the single-RHS FP64
+oracle on the shared stream, element by element (tests/parity.py)."""
 import numpy as np
 import pytest
 
 import oracle
-from paper_2203_10838_amd import inputs
+from paper_2203_10838_amd import inputs, params
+from parity import check_columns
 
 pytestmark = pytest.mark.gpu
 
@@ -11,12 +13,6 @@ pytestmark = pytest.mark.gpu
 def _t(a, dev):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-
-
-def _colrel(X, Z):
-    X = np.asarray(X, dtype=np.float64)
-    Z = np.asarray(Z, dtype=np.float64)
-    return max(np.linalg.norm(X[:, r] - Z[:, r]) / max(np.linalg.norm(Z[:, r]), 1e-30) for r in range(Z.shape[1]))
 
 
 @pytest.mark.parametrize("m,n,R,eta,K", [(3000, 1000, 64, 100, 40), (2000, 516, 12, 37, 60), (5000, 2048, 128, 300, 15),
@@ -32,8 +28,7 @@ def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K):
     res = rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda))
     assert res.status == 0 and res.k_done == K
     ref = oracle.rska_multirhs(A, B, 0.5, eta, alpha, K, idx)
-    assert _colrel(res.x_star.cpu().numpy(), ref["z"]) <= 1e-4
-    assert _colrel(res.x.cpu().numpy(), ref["x"]) <= 1e-4
+    check_columns(res.x_star, res.x, ref, 0.5, 1e-4, min_support=R)
 
 
 def test_multirhs_per_step_alpha_and_errors(cuda, rsk_lib):
@@ -47,7 +42,7 @@ def test_multirhs_per_step_alpha_and_errors(cuda, rsk_lib):
     res = rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.3, eta=eta, alpha=1.0, K=K, index_stream=_t(idx, cuda),
                              alpha_k=_t(ak, cuda))
     ref = oracle.rska_multirhs(A, B, 0.3, eta, 1.0, K, idx, alpha_k=ak.astype(np.float64))
-    assert _colrel(res.x.cpu().numpy(), ref["x"]) <= 1e-4
+    check_columns(res.x_star, res.x, ref, 0.3, 1e-4, min_support=8)
     bad = idx.copy()
     bad[5 * eta + 3] = 1200
     with pytest.raises(rsk.RskError) as e:
@@ -57,3 +52,48 @@ def test_multirhs_per_step_alpha_and_errors(cuda, rsk_lib):
                            check=False)
     torch.cuda.synchronize()
     assert r.status_dev.cpu().tolist() == [6, 5]
+
+
+@pytest.mark.timeout(300)
+def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib):
+    """The shared-A workload at its own shape: A 32768 x 8192 float32 N(0,1) drawn on the device,
+    R = 256 right-hand sides B = A X_hat (5% N(0,1) nonzeros a column), eta = 820, alpha = alpha*,
+    lambda = 1, 20 steps. Its 512 output tiles of 64 x 64 run the A_tau^T C update without a row
+    split over 13 stages of 64 rows. Eight seeded columns against the FP64 oracle on the rows the
+    stream touches."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    m, n, R, eta, K, lam, seed = 32768, 8192, 256, 820, 20, 1.0, 20310838 + 300 + 7
+    g = torch.Generator(device=cuda)
+    g.manual_seed(seed)
+    A = torch.randn((m, n), generator=g, device=cuda, dtype=torch.float32)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    Xh = np.stack([inputs.sparse_vector(n, int(round(0.05 * n)), rng, np.float32) for _ in range(R)], axis=1)
+    Xd = torch.from_numpy(Xh.astype(np.float64)).to(cuda)
+    B = torch.empty((m, R), dtype=torch.float32, device=cuda)
+    w = torch.empty(m, dtype=torch.float64, device=cuda)
+    for r0 in range(0, m, 4096):
+        blk = A[r0:r0 + 4096].double()
+        B[r0:r0 + 4096] = (blk @ Xd).float()
+        w[r0:r0 + 4096] = (blk * blk).sum(1)
+    del Xd, blk
+    wn = w.cpu().numpy()
+    v = torch.ones(n, dtype=torch.float32, device=cuda)
+    for _ in range(30):  # sigma_max^2 by power iteration (only to set alpha*)
+        v = A.t().mv(A.mv(v))
+        s2 = float(v.double().norm())
+        v = v / v.norm()
+    alpha = params.optimal_alpha(eta, float(wn.sum()), s2)
+    plan = rsk.plan_multirhs(A, R, eta=eta, K=K)
+    assert plan["S2"] == 1 and plan["eta_pad"] == 832, plan
+    idx = inputs.index_stream(wn, K, eta, seed + 1)
+    res = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda))
+    assert res.status == 0 and res.k_done == K
+    cols = sorted(np.random.default_rng(seed + 2).choice(R, 8, replace=False).tolist())
+    uniq, local = np.unique(idx, return_inverse=True)
+    sub = A[torch.from_numpy(uniq.astype(np.int64)).to(cuda)].double().cpu().numpy()
+    Bs = B[torch.from_numpy(uniq.astype(np.int64)).to(cuda)][:, cols].double().cpu().numpy()
+    refs = [oracle.rska_dense(sub, Bs[:, q], lam, eta, alpha, K, local.astype(np.int32), threads=8)
+            for q in range(len(cols))]
+    ref = {"z": np.stack([r_["z"] for r_ in refs], 1), "x": np.stack([r_["x"] for r_ in refs], 1)}
+    check_columns(res.x_star[:, cols], res.x[:, cols], ref, lam, 1e-4, min_support=40)

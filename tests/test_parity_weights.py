@@ -1,20 +1,19 @@
-"""GPU parity of per-row weights W = diag(w_i) (Definition 1; variants v3/v4 of Sec. 5)."""
+"""GPU parity of per-row weights W = diag(w_i) (Definition 1; variants v3/v4 of Sec. 5).
+
+Row i is relaxed by alpha w_i. With w_i <= 1 and alpha = alpha* of the uniform case every row's
+relaxation stays below alpha*, which keeps the iteration stable and lets x gain support within
+the tests' few steps (element-wise checks of tests/parity.py, non-vacuous by construction).
+"""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2203_10838_amd import inputs
+from parity import alpha_star, check_columns, check_iterate
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"f32": 1e-4, "f64": 1e-10}
-
-
-def _rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def _t(a, dev):
@@ -40,13 +39,12 @@ def test_weighted_dense_matches_oracle(cuda, rsk_lib, variant, dtype, kernel, m,
     c = inputs.dense_system(m, n, max(1, n // 40), dtype=dtype, seed=m + eta, noise_rel=0.01)
     w = inputs.row_weights(m, m + 1, dtype, lo=0.05)
     idx = _streams(c["A"], w, K, eta, m + 2, variant)
-    alpha = 1.0 if variant == "v4" else 2.0
+    alpha = alpha_star(c["A"], eta)
     res = rsk.solve_dense(_t(c["A"], cuda), _t(c["b"], cuda), lam=0.5, eta=eta, alpha=alpha, K=K,
                           index_stream=_t(idx, cuda), row_w=_t(w, cuda), kernel=kernel, grid=grid)
     assert res.status == 0 and res.k_done == K
     ref = oracle.rska_dense(c["A"], c["b"], 0.5, eta, alpha, K, idx, row_w=w)
-    assert _rel(res.x_star.cpu().numpy(), ref["z"]) <= TOL[dtype]
-    assert _rel(res.x.cpu().numpy(), ref["x"]) <= TOL[dtype]
+    check_iterate(res.x_star, res.x, ref, 0.5, TOL[dtype], min_support=5)
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
@@ -72,13 +70,16 @@ def test_weighted_zero_weight_row_and_zero_row(cuda, rsk_lib):
     res = rsk.solve_dense(_t(c["A"], cuda), _t(c["b"], cuda), lam=0.2, eta=8, alpha=1.0, K=100,
                           index_stream=_t(idx, cuda), row_w=_t(w, cuda))
     ref = oracle.rska_dense(c["A"], c["b"], 0.2, 8, 1.0, 100, idx, row_w=w)
-    assert _rel(res.x_star.cpu().numpy(), ref["z"]) <= 1e-10
+    check_iterate(res.x_star, res.x, ref, 0.2, 1e-10, min_support=0)
     Az = c["A"].copy()
     Az[idx[20]] = 0.0
     with pytest.raises(rsk.RskError) as e:
         rsk.solve_dense(_t(Az, cuda), _t(c["b"], cuda), lam=0.2, eta=8, alpha=1.0, K=100,
                         index_stream=_t(idx, cuda), row_w=_t(w, cuda))
     assert e.value.name == "RSK_ERR_ZERO_ROW"
+
+
+CSR_ALPHA = 32.0  # half of eta = 64: 10 nonzeros a row of 2500 columns are nearly orthogonal (alpha* ~ eta)
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
@@ -91,11 +92,11 @@ def test_weighted_csr_matches_oracle(cuda, rsk_lib, kernel, dtype):
     K, eta = 300, 64
     idx = inputs.index_stream(r2 / w.astype(np.float64), K, eta, 68)
     res = rsk.solve_csr(_t(c["row_ptr"], cuda), _t(c["col"], cuda), _t(c["val"], cuda), c["n"], _t(c["b"], cuda),
-                        lam=0.5, eta=eta, alpha=1.0, K=K, index_stream=_t(idx, cuda), row_w=_t(w, cuda),
+                        lam=0.5, eta=eta, alpha=CSR_ALPHA, K=K, index_stream=_t(idx, cuda), row_w=_t(w, cuda),
                         kernel=kernel)
     assert res.status == 0
-    ref = oracle.rska_csr(c["row_ptr"], c["col"], c["val"], c["n"], c["b"], 0.5, eta, 1.0, K, idx, row_w=w)
-    assert _rel(res.x.cpu().numpy(), ref["x"]) <= TOL[dtype]
+    ref = oracle.rska_csr(c["row_ptr"], c["col"], c["val"], c["n"], c["b"], 0.5, eta, CSR_ALPHA, K, idx, row_w=w)
+    check_iterate(res.x_star, res.x, ref, 0.5, TOL[dtype], min_support=5)
 
 
 def test_weighted_multirhs_matches_oracle(cuda, rsk_lib):
@@ -104,13 +105,15 @@ def test_weighted_multirhs_matches_oracle(cuda, rsk_lib):
     w = inputs.row_weights(2048, 70, "f32", lo=0.05)
     K, eta = 60, 128
     idx = _streams(c["A"], w, K, eta, 71, "v4")
-    res = rsk.solve_multirhs(_t(c["A"], cuda), _t(c["B"], cuda), lam=0.5, eta=eta, alpha=1.0, K=K,
+    alpha = alpha_star(c["A"], eta)
+    res = rsk.solve_multirhs(_t(c["A"], cuda), _t(c["B"], cuda), lam=0.5, eta=eta, alpha=alpha, K=K,
                              index_stream=_t(idx, cuda), row_w=_t(w, cuda))
     assert res.status == 0
-    X = res.x.cpu().numpy()
-    for r in (0, 7, 15):
-        ref = oracle.rska_dense(c["A"], c["B"][:, r], 0.5, eta, 1.0, K, idx, row_w=w)
-        assert _rel(X[:, r], ref["x"]) <= 1e-4
+    cols = [0, 7, 15]
+    refs = [oracle.rska_dense(c["A"], c["B"][:, r], 0.5, eta, alpha, K, idx, row_w=w) for r in cols]
+    check_columns(res.x_star[:, cols], res.x[:, cols], {"z": np.stack([q["z"] for q in refs], 1),
+                                                        "x": np.stack([q["x"] for q in refs], 1)},
+                  0.5, 1e-4, min_support=5)
 
 
 def test_weights_rejected_where_unsupported(cuda, rsk_lib):
@@ -155,20 +158,26 @@ def test_weighted_device_cdf_and_stream(cuda, rsk_lib):
     assert np.allclose(cq, np.cumsum(q), rtol=1e-13, atol=1e-12)
 
 
+@pytest.mark.timeout(300)
 def test_weighted_headline_workload_v4(cuda, rsk_lib):
-    """100000 x 20000 float32 system, v4 (w_i ~ U[0,1] clipped at 0.05, p_i ~ ||a_i||^2 / w_i,
-    alpha = 1), eta = 1024, 40 steps with the register-tile kernel; the oracle runs on the rows
-    the stream touches (a step reads no others), indices remapped."""
+    """100000 x 20000 float32 system, v4 (w_i ~ U[0,1] clipped at 0.05, p_i ~ ||a_i||^2 / w_i),
+    eta = 1024, 60 steps through the library's choice (the benchmarked register-tile launch);
+    alpha = alpha*(1024) of the uniform case (about 925 at this shape; the Bai-Yin estimate of
+    sigma_max suffices for a relaxation that w_i <= 1 keeps below it) and lambda = 1, so x has
+    support. The oracle runs on the rows the stream touches (a step reads no others)."""
     import torch
-    from paper_2203_10838_amd import rsk
-    sysd = inputs.dense_system_device(100000, 20000, 200, seed=20310838 + 500, noise_rel=0.01, device=cuda)
-    w = inputs.row_weights(100000, 20310838 + 501, "f32", lo=0.05)
-    K, eta = 40, 1024
+    from paper_2203_10838_amd import params, rsk
+    m, n, eta, K, lam = 100000, 20000, 1024, 60, 1.0
+    sysd = inputs.dense_system_device(m, n, 200, seed=20310838 + 500, noise_rel=0.01, device=cuda)
+    w = inputs.row_weights(m, 20310838 + 501, "f32", lo=0.05)
     idx = inputs.index_stream(sysd["weights"] / w.astype(np.float64), K, eta, 20310838 + 502)
-    res = rsk.solve_dense(sysd["A"], torch.from_numpy(sysd["b"]).to(cuda), lam=2.0, eta=eta, alpha=1.0, K=K,
+    alpha = params.optimal_alpha(eta, float(sysd["weights"].sum()), float(sysd["weights"].sum()) / (m * n) *
+                                 (np.sqrt(m) + np.sqrt(n)) ** 2)
+    A = sysd["A"]
+    assert rsk.plan_dense(A, eta=eta)["chunks_per_lane"] == 5
+    res = rsk.solve_dense(A, torch.from_numpy(sysd["b"]).to(cuda), lam=lam, eta=eta, alpha=alpha, K=K,
                           index_stream=_t(idx, cuda), row_w=_t(w, cuda))
     assert res.status == 0
-    rows, local = np.unique(idx, return_inverse=True)
-    sub = sysd["A"][torch.from_numpy(rows).to(cuda)].cpu().numpy()
-    ref = oracle.rska_dense(sub, sysd["b"][rows], 2.0, eta, 1.0, K, local.astype(np.int32), row_w=w[rows])
-    assert _rel(res.x.cpu().numpy(), ref["x"]) <= 1e-4
+    ref = oracle.rska_dense_rows(lambda rows: A[torch.from_numpy(rows).to(cuda)].cpu().numpy(), sysd["b"], m, n,
+                                 lam, eta, alpha, K, idx, row_w=w, threads=8)
+    check_iterate(res.x_star, res.x, ref, lam, 1e-4, min_support=10)
