@@ -263,6 +263,27 @@ int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
                             void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * rsk_avg_solve_dense for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same plan, kernels and results as rsk_avg_solve_dense, with
+ * the cross-workgroup exchange words in a static device array of the library
+ * (RSK_NOALLOC_SCRATCH_BYTES, 8 MiB, one copy per GPU, held until the process
+ * ends) instead of a caller workspace. The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); its scratch is cleared
+ * by a fill kernel on `stream` before the solve. Arguments, device status and
+ * errors as rsk_avg_solve_dense; a plan whose exchange needs more than the
+ * static array (rsk_workspace_size_dense > RSK_NOALLOC_SCRATCH_BYTES) returns
+ * RSK_ERR_WORKSPACE and queues nothing. Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (concurrent streams or host
+ * threads) race and give undefined results; calls ordered on one stream are
+ * safe. The address of the array is looked up on the first call on each device
+ * (hipGetSymbolAddress, with that device current).
+ */
+#define RSK_NOALLOC_SCRATCH_BYTES (8u << 20)
+int32_t rsk_avg_solve_dense_noalloc(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
+                                    void *stream);
+
+/*
  * The launch rsk_avg_solve_dense would make for A and p, without making it
  * (nothing is queued; A->val is only inspected for its alignment). out:
  * host int32[8] = { kernel (1 general, 2 register tile, 3 register tile over

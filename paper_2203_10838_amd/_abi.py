@@ -8,6 +8,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librsk.so")
 
 RSK_F32, RSK_F64 = 0, 1
+NOALLOC_SCRATCH_BYTES = 8 << 20
 STATUS_NAMES = {
     0: "RSK_OK", 1: "RSK_ERR_INVALID_ARG", 2: "RSK_ERR_UNSUPPORTED", 3: "RSK_ERR_WORKSPACE",
     4: "RSK_ERR_HIP", 5: "RSK_ERR_ZERO_ROW", 6: "RSK_ERR_INDEX_RANGE", 7: "RSK_ERR_NONFINITE",
@@ -54,6 +55,8 @@ SIGNATURES = {
                                          ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
                                     c_vp, c_sz, c_vp]),
+    "rsk_avg_solve_dense_noalloc": (c_i32, [ctypes.POINTER(RskDense), c_vp, ctypes.POINTER(RskParams), c_vp, c_vp,
+                                            c_vp]),
     "rsk_plan_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(RskParams), ctypes.POINTER(c_i32)]),
     "rsk_rownorm2_csr": (c_i32, [ctypes.POINTER(RskCsr), c_vp, c_vp]),
     "rsk_avg_solve_multirhs_ckpt": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_i32,

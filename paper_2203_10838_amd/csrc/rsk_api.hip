@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "rsk.h"
 #include "rsk_kernels.hpp"
 
@@ -551,6 +553,31 @@ int32_t bsk_solve_t(const rsk_dense* A, const void* b, const rsk_params* p, void
   return solve_dense_t<T>(A, b, &L.p2, x_star, x, w + L.offSolve, ws_bytes - L.offSolve, s, false);
 }
 
+// Static exchange scratch of rsk_avg_solve_dense_noalloc: one copy per GPU (each device holds its
+// own instance of this array until the process ends). Host code never uses the array's name as a
+// device address: the address is looked up once per device with hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = size_t(RSK_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array (set up on the first call on that device).
+int32_t noalloc_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RSK_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return RSK_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RSK_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RSK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -904,6 +931,26 @@ int32_t rsk_workspace_size_dense(const rsk_dense* A, const rsk_params* p, size_t
   if (st) return st;
   *bytes = pl.bytes;
   return RSK_OK;
+}
+
+int32_t rsk_avg_solve_dense_noalloc(const rsk_dense* A, const void* b, const rsk_params* p, void* x_star, void* x,
+                                    void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  st = check_params(p, A->m);
+  if (st) return st;
+  if (!b || !x_star || !x) return RSK_ERR_INVALID_ARG;
+  if (p->eta > kMaxEtaDense) return RSK_ERR_UNSUPPORTED;
+  DensePlan pl;
+  st = A->dtype == RSK_F64 ? plan_dense<double>(A, p, &pl) : plan_dense<float>(A, p, &pl);
+  if (st) return st;
+  if (pl.bytes > kNoAllocScratchBytes) return RSK_ERR_WORKSPACE;
+  void* ws = nullptr;
+  st = noalloc_scratch(&ws);
+  if (st) return st;
+  return A->dtype == RSK_F64
+      ? solve_dense_t<double>(A, b, p, x_star, x, ws, kNoAllocScratchBytes, (hipStream_t)stream)
+      : solve_dense_t<float>(A, b, p, x_star, x, ws, kNoAllocScratchBytes, (hipStream_t)stream);
 }
 
 int32_t rsk_plan_dense(const rsk_dense* A, const rsk_params* p, int32_t* out) {

@@ -150,8 +150,11 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
                 warm_start: bool = False, x_ref: Optional[torch.Tensor] = None, check_every: int = 0,
                 tol: float = 0.0, y_out: Optional[torch.Tensor] = None, grid: int = 0, kernel: int = 0,
                 row_w: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-                check: bool = True) -> SolveResult:
+                check: bool = True, noalloc: bool = False) -> SolveResult:
     """K steps of RSKA (eq. (rska), Algorithm 1) on a dense system, one persistent launch.
+
+    ``noalloc``: call rsk_avg_solve_dense_noalloc, whose exchange scratch is the library's static
+    per-GPU array (no workspace; calls that overlap on one GPU race).
 
     ``row_w`` (m, optional): per-row weights w_i of Definition 1 (variants v3/v4 of Sec. 5);
     row i is then relaxed by alpha (or alpha_k[k]) times w_i.
@@ -186,13 +189,19 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, *, lam: float, eta: int, alpha
     if y_out is not None:
         _dev(y_out, "y_out", dt, m)
     d = dense_desc(A)
-    need = workspace_size_dense(A, params)
-    if workspace is None or workspace.numel() < need:
-        workspace = _workspace(need, A.device)
-    st = _lib().rsk_avg_solve_dense(ctypes.byref(d), b.data_ptr(), ctypes.byref(params), x_star.data_ptr(),
-                                    x.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
-    if st:
-        raise RskError(st, "rsk_avg_solve_dense")
+    if noalloc:
+        st = _lib().rsk_avg_solve_dense_noalloc(ctypes.byref(d), b.data_ptr(), ctypes.byref(params),
+                                                x_star.data_ptr(), x.data_ptr(), _stream())
+        if st:
+            raise RskError(st, "rsk_avg_solve_dense_noalloc")
+    else:
+        need = workspace_size_dense(A, params)
+        if workspace is None or workspace.numel() < need:
+            workspace = _workspace(need, A.device)
+        st = _lib().rsk_avg_solve_dense(ctypes.byref(d), b.data_ptr(), ctypes.byref(params), x_star.data_ptr(),
+                                        x.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream())
+        if st:
+            raise RskError(st, "rsk_avg_solve_dense")
     status = k_done = None
     if check:
         s = status_dev.cpu().tolist()
