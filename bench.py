@@ -72,10 +72,11 @@ def step_bytes(eta, n):
 
 
 def source_hash():
-    """Hash of the register-tile kernel's code (comments and blank space removed), so that the
-    recorded HBM counters stay valid across comment edits but not across code changes."""
+    """Hash of the code that decides the headline launch's traffic (the register-tile kernel, the
+    shared device header, the kernel constants and the planner; comments and blank space removed),
+    so that the recorded HBM counters stay valid across comment edits but not across code changes."""
     h = hashlib.sha256()
-    for f in ("rsk_dense_rt.hip", "rsk_device.hpp"):
+    for f in ("rsk_dense_rt.hip", "rsk_device.hpp", "rsk_kernels.hpp", "rsk_api.hip"):
         src = open(os.path.join(ROOT, "paper_2203_10838_amd", "csrc", f)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)
@@ -83,18 +84,82 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(bytes_per_launch_alg):
-    """HBM bytes per launch measured by rocprofv3 counters (committed summary), if it matches this kernel."""
-    p = os.path.join(ROOT, "profiles", "dense_rt_traffic.json")
-    if not os.path.exists(p):
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "dense_rt_traffic.json")
+
+
+def traffic_from_profile(plan):
+    """HBM bytes per launch measured by rocprofv3 counters (committed summary), if it was taken on
+    this code and this launch plan."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
     try:
-        d = json.load(open(p))
+        d = json.load(open(TRAFFIC_JSON))
     except Exception:
         return None
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash() or d.get("plan") != plan:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def _rocprof_counter_kib(csv_path, kernel_prefix, counter):
+    """Per-dispatch values (KiB) of one counter for the kernels whose name starts with the prefix."""
+    import csv
+    vals = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+            if row.get("Counter_Name") != counter or not name.startswith(kernel_prefix):
+                continue
+            vals.setdefault(row.get("Dispatch_Id"), 0.0)
+            vals[row.get("Dispatch_Id")] += float(row["Counter_Value"])
+    return list(vals.values())
+
+
+def record_traffic(fetch_csv, write_csv, out_json, plan, iters=100):
+    """Write the traffic summary from two rocprofv3 --pmc runs of `bench.py --no-sweep --no-cpu
+    --copy-probe` (FETCH_SIZE, then WRITE_SIZE): the solver's counters per launch, each scaled by
+    what the same counter reads for the 1 GiB device copy of the probe."""
+    kern = "void rsk::rska_dense_rt" if plan["kernel"] in (2, 3) else "void rsk::rska_dense_persistent"
+    f_s = _rocprof_counter_kib(fetch_csv, kern, "FETCH_SIZE")
+    w_s = _rocprof_counter_kib(write_csv, kern, "WRITE_SIZE")
+    f_c = _rocprof_counter_kib(fetch_csv, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    w_c = _rocprof_counter_kib(write_csv, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    known_kib = COPY_PROBE_BYTES / 1024
+    fs = known_kib / max(f_c) if f_c else 1.0
+    ws = known_kib / max(w_c) if w_c else 1.0
+    rd = float(np.mean(f_s)) * 1024 * fs
+    wr = float(np.mean(w_s)) * 1024 * ws
+    alg = iters * step_bytes(1024, N)
+    d = {"source_hash": source_hash(), "plan": plan, "workload": f"dense {M}x{N} float32, eta=1024, "
+         f"{iters} iterations per launch", "dispatches": len(f_s),
+         "fetch_size_kib_per_launch_raw": float(np.mean(f_s)), "write_size_kib_per_launch_raw": float(np.mean(w_s)),
+         "copy_probe_bytes": COPY_PROBE_BYTES, "fetch_scale": fs, "write_scale": ws,
+         "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr, "hbm_bytes_per_launch": rd + wr,
+         "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (rd + wr) / alg}
+    with open(out_json, "w") as f:
+        json.dump(d, f, indent=1)
+    return d
+
+
+def host_info():
+    """CPU model, logical CPUs and RAM of the host the oracle runs on."""
+    model, ram = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity, "ram_gib": ram}
 
 
 def cpu_baseline(A, b, weights, lam, eta, alpha, seconds=12.0, K=200):
@@ -119,7 +184,8 @@ def cpu_baseline(A, b, weights, lam, eta, alpha, seconds=12.0, K=200):
     gbs = done * step_bytes(eta, A.shape[1]) / dt / 1e9
     return {"value": gbs, "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} RSKA iterations at eta={eta} on the same 100000x20000 system "
-                      f"(FP64 C loops, one thread, {dt:.1f} s; {done / dt:.2f} iterations/s)"}
+                      f"(FP64 C loops, one thread, {dt:.1f} s; {done / dt:.2f} iterations/s)",
+            "host": host_info()}
 
 
 def torch_index(np_idx, device):
@@ -136,11 +202,17 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="RSKA iterations per benchmark step")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb", "bsk", "variants"],
+    ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb", "bsk", "variants", "config0",
+                                       "floor"],
                     default=None,
                     help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library built-in choices)")
+    ap.add_argument("--record-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"), default=None,
+                    help="write the traffic summary (profiles/dense_rt_traffic.json's format) from two rocprofv3 "
+                         "--pmc counter_collection.csv files of `bench.py --no-sweep --no-cpu --copy-probe` "
+                         "(FETCH_SIZE, then WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
@@ -164,11 +236,20 @@ def main():
         else:
             out = variants_run(sysd["A"], b, xhat, dev, stream)
         print(json.dumps({args.only: out}), flush=True)
+        teardown()
         return
     if args.only:
         stream = torch.cuda.current_stream()
-        fn = {"batched": batched_run, "multirhs": multirhs_run, "adjoint": adjoint_run, "csr": csr_run}[args.only]
-        print(json.dumps({args.only: fn(dev, stream)}), flush=True)
+        fn = {"batched": batched_run, "multirhs": multirhs_run, "adjoint": adjoint_run, "csr": csr_run,
+              "config0": config0_run}.get(args.only)
+        if args.only == "floor":
+            sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
+            out = floor_run(sysd["A"], torch.from_numpy(sysd["b"]).to(dev), dev, stream)
+        else:
+            out = (fn(dev, stream, tune=not args.no_tune) if args.only in ("batched", "multirhs", "config0")
+                   else fn(dev, stream))
+        print(json.dumps({args.only: out}), flush=True)
+        teardown()
         return
     t0 = time.time()
     sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
@@ -191,6 +272,20 @@ def main():
     nstream = (args.warmup + args.steps) * iters
     idx = torch.from_numpy(inputs.index_stream(weights, nstream, eta, SEED + 1)).to(dev)
     stream = torch.cuda.current_stream()
+    tune_info = None
+    if not args.no_tune:
+        # the tuner times every launch the library accepts on 20 iterations of the stream's start and
+        # installs the fastest; the headline then runs the library's (tuned) choice
+        from paper_2203_10838_amd import autotune
+        t = autotune.tune_dense(A, b, eta=eta, lam=LAM, alpha=params.optimal_alpha(eta, fro2, smax2), index_stream=idx,
+                                steps=20, reps=3, rownorm2_t=r2)
+        tune_info = {"default_plan": t["default"]["plan"], "default_us_per_iteration": round(t["default"]["us_per_step"], 3),
+                     "tuned_choice": {"kernel": t["choice"][0], "grid": t["choice"][1]},
+                     "tuned_us_per_iteration": round(t["us_per_step"], 3),
+                     "candidates": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+                                    for r in t["table"]]}
+        log(f"[bench] tuned eta={eta}: default {tune_info['default_us_per_iteration']} us, "
+            f"tuned {tune_info['tuned_choice']} {tune_info['tuned_us_per_iteration']} us")
     if args.copy_probe:
         # a plain device copy of known size, so that HBM byte counters read for
         # the solver can be scaled by what they read for a known transfer
@@ -247,11 +342,15 @@ def main():
         "us_per_iteration": round(launch_ms * 1e3 / iters, 3),
         "device": device_info(dev),
     }
-    traffic = traffic_from_profile(bytes_launch)
+    plan = rsk.plan_dense(A, eta=eta)
+    traffic = traffic_from_profile(plan)
+    kname = ("rska_dense_rt<{threads}, {row_passes}, {chunks_per_lane}, {row_groups}>".format(**plan)
+             if plan["kernel"] in (2, 3) else "rska_dense_persistent (general kernel)")
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                       "kernel": "rska_dense_rt (register-tile persistent kernel)",
-                       "bytes_per_launch": bytes_launch}
+                       "kernel": kname, "plan": plan, "bytes_per_launch": bytes_launch}
+    if tune_info is not None:
+        out["tuning"] = {"headline_eta1024": tune_info}
 
     # ---------------- eta sweep and time to plateau
     if not args.no_sweep:
@@ -278,17 +377,123 @@ def main():
         out["variants"] = variants_run(A, b, xhat, dev, stream)
 
     if not args.no_sweep:
+        out["floor"] = floor_run(A, b, dev, stream, r2=r2)
         out["sampler"] = sampler_run(A, dev, stream)
+        out["config0"] = config0_run(dev, stream, tune=not args.no_tune)
         out["csr"] = csr_run(dev, stream)
-        out["batched"] = batched_run(dev, stream)
+        out["batched"] = batched_run(dev, stream, tune=not args.no_tune)
         torch.cuda.empty_cache()
-        out["multirhs"] = multirhs_run(dev, stream)
+        out["multirhs"] = multirhs_run(dev, stream, tune=not args.no_tune)
         out["adjoint"] = adjoint_run(dev, stream)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, sysd["b"], weights, LAM, eta, params.optimal_alpha(eta, fro2, smax2))
+    if args.record_traffic:
+        out["traffic_recorded"] = record_traffic(*args.record_traffic, plan, iters)
     print(json.dumps(out), flush=True)
+    del A, b, xhat, idx, r2, sysd
+    teardown()
+
+
+def teardown():
+    """Wait for the device, drop the cached device memory and flush, before the interpreter exits."""
+    import gc
+    import torch
+    torch.cuda.synchronize()
+    gc.collect()
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    sys.stdout.flush()
+    sys.stderr.flush()
+
+
+def floor_run(A, b, dev, stream, K=400, r2=None):
+    """The step-latency floor of the headline launch: per eta of the sweep, the library's launch on
+    the same 100000x20000 matrix with a stream that names row 0 at every position. The kernel,
+    plan and exchange are those of the real run, but every step gathers the same 80 KB row, which
+    the caches serve after the first step, so HBM moves next to nothing: the time per step is the
+    exchange, the on-chip work and the cache round trips. Reported beside each eta's real time and
+    the time its algorithmic bytes need at 8 TB/s."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    out = []
+    r2 = r2 if r2 is not None else rsk.rownorm2(A)
+    for e in ETAS:
+        ix = torch.zeros(K * e, dtype=torch.int32, device=dev)
+        # alpha = 1: every step is the exact projection onto row 0's hyperplane (eta copies of one row
+        # average to that row), so the iterate stays finite and every step runs
+        run = lambda: rsk.solve_dense(A, b, lam=LAM, eta=e, alpha=1.0, K=K, index_stream=ix, rownorm2_t=r2,
+                                      check=False)
+        chk = rsk.solve_dense(A, b, lam=LAM, eta=e, alpha=1.0, K=K, index_stream=ix, rownorm2_t=r2)
+        assert chk.status == 0 and chk.k_done == K, (e, chk.status, chk.k_done)
+        ms = _median_ms(run, stream, reps=3)
+        out.append({"eta": e, "floor_us_per_iteration": round(ms * 1e3 / K, 3),
+                    "hbm_bound_us_per_iteration": round(step_bytes(e, N) / (PEAK_HBM_GBS * 1e3), 3),
+                    "plan": rsk.plan_dense(A, eta=e)})
+        log(f"[bench] floor eta={e}: {out[-1]['floor_us_per_iteration']} us/iteration")
+    return {"workload": f"{M}x{N} float32, the library's launch per eta, every stream index = row 0, {K} steps",
+            "runs": out}
+
+
+C0_M, C0_N, C0_S, C0_ETA, C0_K, C0_LAM, C0_SEED, C0_KCAL = 1000, 500, 25, 10, 3000, 1.0, 20310838, 20000
+
+
+def config0_run(dev, stream, tune=True):
+    """The plain FP64 workload: A 1000x500 N(0,1) float64, x_hat with 25 N(0,1) nonzeros, b = A x_hat,
+    lambda = 1, eta = 10, alpha = min(alpha*, 2 eta), rows sampled with p ~ ||a_i||^2, K = 3000.
+    Reports microseconds and steps per second at K = 3000, the time to rel.err 1e-5 (a calibration
+    run with the monitor every 10 steps on a longer stream, at most 20000 steps, finds k*; a run of
+    exactly k* steps with the monitor off is timed), the relative difference of x_K from the FP64
+    oracle on the same stream, and the oracle's own time for the 3000 steps on one host thread.
+    With ``tune`` the autotuner first picks the launch (the built-in one is reported beside it)."""
+    import torch
+    import oracle
+    from paper_2203_10838_amd import inputs, rsk
+    sysd = inputs.dense_system(C0_M, C0_N, C0_S, dtype="f64", seed=C0_SEED)
+    idx_np = inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), C0_KCAL, C0_ETA, C0_SEED + 1)
+    A64 = sysd["A"]
+    smax2 = float(np.linalg.svd(A64, compute_uv=False)[0] ** 2)
+    alpha = min(oracle.optimal_alpha(C0_ETA, float((A64 * A64).sum()), smax2), 2.0 * C0_ETA)
+    A = torch.from_numpy(A64).to(dev)
+    b = torch.from_numpy(sysd["b"]).to(dev)
+    xh = torch.from_numpy(sysd["xhat"]).to(dev)
+    ix = torch.from_numpy(idx_np).to(dev)
+    r2 = rsk.rownorm2(A)
+    kw = dict(lam=C0_LAM, eta=C0_ETA, alpha=alpha, index_stream=ix, rownorm2_t=r2)
+    tuned = None
+    if tune:
+        from paper_2203_10838_amd import autotune
+        t = autotune.tune_dense(A, b, eta=C0_ETA, lam=C0_LAM, alpha=alpha, index_stream=ix, steps=C0_K, reps=3,
+                                rownorm2_t=r2)
+        tuned = {"default_plan": t["default"]["plan"], "default_us_per_step": round(t["default"]["us_per_step"], 3),
+                 "tuned": {"kernel": t["choice"][0], "grid": t["choice"][1]},
+                 "tuned_us_per_step": round(t["us_per_step"], 3), "candidates": len(t["table"])}
+    cal = rsk.solve_dense(A, b, K=C0_KCAL, x_ref=xh, check_every=10, tol=1e-5, **kw)
+    kstar = int(cal.k_done)
+    reached = bool(cal.err_hist.cpu().numpy()[kstar // 10 - 1] <= 1e-5) if kstar >= 10 else False
+    t_full = _median_ms(lambda: rsk.solve_dense(A, b, K=C0_K, check=False, **kw), stream, reps=5)
+    t_star = _median_ms(lambda: rsk.solve_dense(A, b, K=kstar, check=False, **kw), stream, reps=5)
+    full = rsk.solve_dense(A, b, K=C0_K, **kw)
+    t0 = time.perf_counter()
+    ref = oracle.rska_dense(A64, sysd["b"], C0_LAM, C0_ETA, alpha, C0_K, idx_np[:C0_K * C0_ETA])
+    t_oracle = time.perf_counter() - t0
+    z = full.x_star.cpu().numpy()
+    plan = rsk.plan_dense(A, eta=C0_ETA)
+    out = {"workload": "plain RSK-avg, dense 1000x500 float64, consistent, 25 nonzeros, lambda=1, eta=10, "
+                       f"alpha=min(alpha*, 2 eta)={alpha:.4f}, K=3000", "plan": plan,
+           "us_per_step": round(t_full * 1e3 / C0_K, 3), "steps_per_s": round(C0_K / (t_full * 1e-3), 1),
+           "k_star_rel_err_1e-5": kstar if reached else None, "ms_to_rel_err_1e-5": round(t_star, 3) if reached else None,
+           "rel_diff_vs_oracle_x_star": float(np.linalg.norm(z - ref["z"]) / np.linalg.norm(ref["z"])),
+           "max_abs_diff_vs_oracle_over_inf_norm": float(np.abs(z - ref["z"]).max() / np.abs(ref["z"]).max()),
+           "oracle_seconds_3000_steps_one_thread": round(t_oracle, 3),
+           "oracle_steps_per_s": round(C0_K / t_oracle, 1),
+           "speedup_vs_oracle": round(t_oracle / (t_full * 1e-3), 1),
+           "algorithmic_GBps": round(C0_K * C0_ETA * (C0_N * 8 + 20) / (t_full * 1e-3) / 1e9, 2)}
+    if tuned is not None:
+        out["tuning"] = tuned
+    log(f"[bench] config0: {out}")
+    return out
 
 
 BATCH_NSYS, BATCH_SEED, BATCH_TOL, BATCH_CHECK, BATCH_KMAX = 512, 20310838 + 300, 1e-5, 10, 20000
@@ -334,7 +539,7 @@ def _median_ms(fn, stream, reps=3):
     return float(np.median(ts))
 
 
-def batched_run(dev, stream, plain=True, wg_bytes=0):
+def batched_run(dev, stream, plain=True, wg_bytes=0, tune=False):
     """Time to rel.err 1e-5 of every system: one batched launch vs 512 sequential plain solves.
 
     A calibration launch with the monitor on (every 10 steps, tol 1e-5, at most 20000 steps) finds
@@ -372,6 +577,25 @@ def batched_run(dev, stream, plain=True, wg_bytes=0):
            "batched_early_stop_ms": round(t_early, 3)}
     log(f"[bench] batched: K_i=k*_i {t_b:.1f} ms ({gbs:.0f} GB/s), early-stop {t_early:.1f} ms, "
         f"converged {conv}/{len(systems)}, k median {out['k_median']} max {out['k_max']}")
+    if tune and wg_bytes == 0:
+        # per size class of the step bytes, the target of row bytes per workgroup that runs the
+        # class's systems fastest (each class timed on its own, at K_i = min(k*_i, 2000)); then the
+        # whole batch again with the tuned classes
+        from paper_2203_10838_amd import autotune
+        short = [dataclasses.replace(s_, K=int(min(s_.K, 2000))) for s_ in fixed]
+        tt = autotune.tune_batched(short, candidates_kib=(16, 32, 56, 96), reps=1)
+        res_t = rsk.solve_batched(fixed)
+        errs_t = [int(st) for st in res_t.status]
+        if any(errs_t):
+            raise RuntimeError(f"batched (tuned) status {errs_t}")
+        same = all(bool(torch.equal(a_, b_)) for a_, b_ in zip(res_t.x_star, res.x_star))
+        t_bt = _median_ms(lambda: rsk.solve_batched(fixed, check=False), stream)
+        out["tuned"] = {"classes": [{k: v for k, v in c.items() if k != "table"} for c in tt["classes"]],
+                        "batched_ms": round(t_bt, 3), "batched_GBps": round(byts / (t_bt * 1e-3) / 1e9, 2),
+                        "batched_frac_hbm": round(byts / (t_bt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                        "same_bits_as_default": same}
+        out["default_wg_kib"] = 56
+        log(f"[bench] batched tuned: {out['tuned']}")
     if plain:
         ws = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
 
@@ -391,7 +615,7 @@ def batched_run(dev, stream, plain=True, wg_bytes=0):
 MRHS_M, MRHS_N, MRHS_R, MRHS_ETA, MRHS_SEED = 32768, 8192, 256, 820, 20310838 + 300 + 7
 
 
-def multirhs_run(dev, stream, K=40):
+def multirhs_run(dev, stream, K=40, tune=False):
     """Shared-A multi-RHS: A 32768x8192 float32 N(0,1) drawn on the device, R = 256 right-hand sides
     B = A X_hat (5% N(0,1) nonzeros per column), one shared stream, eta = 820, alpha = alpha*, lambda = 1.
     Per-step time and TFLOP/s (4 eta n R flop) against the float32 MFMA peak, and the same work as
@@ -416,6 +640,15 @@ def multirhs_run(dev, stream, K=40):
     alpha = params.optimal_alpha(eta, float(wn.sum()), spectral_norm_sq(A))
     r2 = rsk.rownorm2(A)
     idx = inputs.index_stream_device(wn, K, eta, MRHS_SEED + 1, dev)
+    tune_info = None
+    if tune:
+        from paper_2203_10838_amd import autotune
+        t = autotune.tune_multirhs(A, B, eta=eta, lam=1.0, alpha=alpha, index_stream=idx, steps=4, reps=3,
+                                   rownorm2_t=r2)
+        tune_info = {"default_plan": t["default"]["plan"], "default_us_per_step": round(t["default"]["us_per_step"], 2),
+                     "tuned": {"S": t["choice"][0], "S2": t["choice"][1]},
+                     "tuned_us_per_step": round(t["us_per_step"], 2), "candidates": len(t["table"])}
+        log(f"[bench] multirhs tuned: {tune_info}")
     rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=alpha, K=2, index_stream=idx, rownorm2_t=r2)
     t_m = _median_ms(lambda: rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=alpha, K=K, index_stream=idx,
                                                 rownorm2_t=r2, check=False), stream)
@@ -429,8 +662,58 @@ def multirhs_run(dev, stream, K=40):
            "frac_fp32_mfma": round(fl * K / (t_m * 1e-3) / 1e12 / 157.3, 4),
            "plain_one_column_us_per_step": round(t_1 * 1e3 / K, 2),
            "plain_R_columns_us_per_step": round(t_1 * 1e3 / K * R, 1),
-           "speedup_vs_R_plain": round(t_1 * R / t_m, 2)}
+           "speedup_vs_R_plain": round(t_1 * R / t_m, 2), "plan": rsk.plan_multirhs(A, R, eta=eta)}
+    if tune_info is not None:
+        out["tuning"] = tune_info
+    out["time_to_rel_err_1e-5"] = multirhs_time_to_tol(A, B, Xh, r2, alpha, eta, stream)
     log(f"[bench] multirhs: {out}")
+    return out
+
+
+def multirhs_time_to_tol(A, B, Xh, r2, alpha, eta, stream, tol=1e-5, C=20, kmax=4000):
+    """Time to rel.err 1e-5, multi-RHS against R plain single-RHS solves, on the shared stream.
+
+    Multi-RHS: segments of C steps (resumed from x*, bitwise the uninterrupted run), at most kmax
+    steps; after each, every column's ||x - x_hat|| / ||x_hat|| is checked on the device, which gives
+    each column's k*_r (the first checkpoint at tol). P = the columns that reach tol within kmax.
+    The multi-RHS run of max_P k*_r steps is timed (it brings every column of P to tol); the plain
+    side is the R solves of P, each of exactly its k*_r steps (the in-kernel monitor gives the same
+    k*_r: same iteration, same stream), timed back to back."""
+    import torch
+    from paper_2203_10838_amd import inputs, rsk
+    m, n = A.shape
+    R = B.shape[1]
+    idx = inputs.index_stream_device(rsk.rownorm2(A).double().cpu().numpy(), kmax, eta, MRHS_SEED + 3, A.device)
+    Xht = torch.from_numpy(Xh).to(A.device).double()
+    nx = Xht.norm(dim=0)
+    Xs = torch.zeros((n, R), dtype=torch.float32, device=A.device)
+    kr = torch.full((R,), -1, dtype=torch.int64, device=A.device)
+    k = 0
+    while k < kmax:
+        r = rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=alpha, K=C, index_stream=idx, stream_offset=k * eta,
+                               rownorm2_t=r2, X_star=Xs, warm_start=k > 0, check=False)
+        k += C
+        err = (r.x.double() - Xht).norm(dim=0) / nx
+        kr = torch.where((kr < 0) & (err <= tol), torch.full_like(kr, k), kr)
+        if bool((kr > 0).all()):
+            break
+    kr = kr.cpu().numpy()
+    P = [int(c) for c in np.nonzero(kr > 0)[0]]
+    out = {"tol": tol, "check_every": C, "kmax": kmax, "columns": R, "columns_reaching_tol": len(P)}
+    if not P:
+        return out
+    kall = int(kr[P].max())
+    t_m = _median_ms(lambda: rsk.solve_multirhs(A, B, lam=1.0, eta=eta, alpha=alpha, K=kall, index_stream=idx,
+                                                rownorm2_t=r2, check=False), stream)
+    cols = {c: B[:, c].contiguous() for c in P}
+
+    def plain_all():
+        for c in P:
+            rsk.solve_dense(A, cols[c], lam=1.0, eta=eta, alpha=alpha, K=int(kr[c]), index_stream=idx,
+                            rownorm2_t=r2, check=False)
+    t_p = _median_ms(plain_all, stream, reps=1)
+    out.update({"k_star_median": int(np.median(kr[P])), "k_star_max": kall, "multirhs_ms": round(t_m, 3),
+                "plain_columns_ms": round(t_p, 3), "speedup_multirhs_vs_plain": round(t_p / t_m, 2)})
     return out
 
 

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RSK_ABI_VERSION 2
+#define RSK_ABI_VERSION 3
 
 typedef enum { RSK_F32 = 0, RSK_F64 = 1 } rsk_dtype;
 
@@ -221,6 +221,45 @@ int32_t rsk_spectral_norm2_dense(const rsk_dense *A, int64_t iters, void *v, dou
 int32_t rsk_workspace_size_bsk_dense(const rsk_dense *A, const rsk_params *p, size_t *bytes);
 int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
                             double *block_norm2, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Tuning table. The choices a solve makes when the caller leaves them to the
+ * library (rsk_avg_solve_dense with kernel = 0 and grid = 0, the two product
+ * splits of rsk_avg_solve_multirhs and rsk_avg_adjoint, the per-system
+ * workgroup targets of rsk_avg_solve_batched with wg_bytes = 0) are read from
+ * a process-global table that a tuner fills with measured winners; where the
+ * table has no entry, the built-in rules apply. The table only selects among
+ * launches the library supports: results are those of the explicit choice,
+ * bit for bit, and a tuned choice that does not apply to a matrix (alignment,
+ * leading dimension) falls back to the built-in rule.
+ *   path RSK_TUNE_DENSE:    key (dtype, m, n, eta);    v0 = kernel (1..3), v1 = grid.
+ *   path RSK_TUNE_MULTIRHS: key (dtype, m, n, eta, R); v0 = S (splits of the n columns in
+ *                           A_tau X), v1 = S2 (row splits of A_tau^T C: 1, 2, 4 or 8).
+ *   path RSK_TUNE_BATCHED:  key (dtype, m = the class's upper bound on a system's step bytes
+ *                           eta * n * element size; n = eta = R = 0); v0 = row bytes per
+ *                           workgroup for systems of that class (a system takes the class
+ *                           with the smallest bound >= its step bytes; at most 8 classes).
+ * `us` is the measured time of the choice (informational). The cache file
+ * (rsk_tune_save / rsk_tune_load) is text, one entry per line:
+ * "path dtype m n eta R v0 v1 us". If the environment variable RSK_TUNE_CACHE
+ * names a file, it is loaded at the first lookup. All calls are thread-safe;
+ * a table changed between a workspace query and its solve can make the solve
+ * return RSK_ERR_WORKSPACE.
+ */
+enum { RSK_TUNE_DENSE = 0, RSK_TUNE_MULTIRHS = 1, RSK_TUNE_BATCHED = 2 };
+typedef struct {
+  int32_t path, dtype;
+  int64_t m, n;
+  int32_t eta, R;
+  int64_t v0, v1;
+  double us;
+} rsk_tune_entry;
+int32_t rsk_tune_set(const rsk_tune_entry *e);                                   /* install or replace */
+int32_t rsk_tune_get(const rsk_tune_entry *key, rsk_tune_entry *out, int32_t *found);
+int32_t rsk_tune_erase(const rsk_tune_entry *key);                               /* one key, if present */
+int32_t rsk_tune_clear(int32_t path);                                            /* path < 0: every entry */
+int32_t rsk_tune_load(const char *path);                                         /* merge a cache file */
+int32_t rsk_tune_save(const char *path);
 
 /* Version of this ABI (RSK_ABI_VERSION). */
 int32_t rsk_abi_version(void);

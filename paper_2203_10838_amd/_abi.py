@@ -41,6 +41,14 @@ class RskBatchItem(ctypes.Structure):
                 ("tol", c_dbl), ("err_hist", c_vp), ("status_dev", c_vp)]
 
 
+class RskTuneEntry(ctypes.Structure):
+    _fields_ = [("path", c_i32), ("dtype", c_i32), ("m", c_i64), ("n", c_i64), ("eta", c_i32), ("R", c_i32),
+                ("v0", c_i64), ("v1", c_i64), ("us", c_dbl)]
+
+
+RSK_TUNE_DENSE, RSK_TUNE_MULTIRHS, RSK_TUNE_BATCHED = 0, 1, 2
+
+
 class RskLbParams(ctypes.Structure):
     _fields_ = [("lambda_", c_dbl), ("step", c_dbl), ("K", c_i64), ("warm_start", c_i32), ("x_ref", c_vp),
                 ("check_every", c_i64), ("err_hist", c_vp), ("res_hist", c_vp), ("status_dev", c_vp)]
@@ -49,6 +57,12 @@ class RskLbParams(ctypes.Structure):
 # name -> (restype, argtypes); every symbol include/rsk.h declares
 SIGNATURES = {
     "rsk_abi_version": (c_i32, []),
+    "rsk_tune_set": (c_i32, [ctypes.POINTER(RskTuneEntry)]),
+    "rsk_tune_get": (c_i32, [ctypes.POINTER(RskTuneEntry), ctypes.POINTER(RskTuneEntry), ctypes.POINTER(c_i32)]),
+    "rsk_tune_erase": (c_i32, [ctypes.POINTER(RskTuneEntry)]),
+    "rsk_tune_clear": (c_i32, [c_i32]),
+    "rsk_tune_load": (c_i32, [ctypes.c_char_p]),
+    "rsk_tune_save": (c_i32, [ctypes.c_char_p]),
     "rsk_status_string": (ctypes.c_char_p, [c_i32]),
     "rsk_rownorm2_dense": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_vp]),
     "rsk_workspace_size_dense": (c_i32, [ctypes.POINTER(RskDense), ctypes.POINTER(RskParams),

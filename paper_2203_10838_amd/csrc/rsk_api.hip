@@ -3,7 +3,12 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "rsk.h"
 #include "rsk_kernels.hpp"
@@ -11,6 +16,86 @@
 using rsk::u64;
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Tuning table: the choices kernel = 0 / grid = 0 (dense), the split of the multi-RHS products and
+// the batched workgroup targets read, written by a tuner (rsk_tune_set) or a cache file
+// (rsk_tune_load; RSK_TUNE_CACHE names one read at the first lookup). Process-global; a lookup
+// holds the lock only while it copies an entry.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::vector<rsk_tune_entry> g_tune;
+bool g_tune_env_done = false;
+
+bool tune_same_key(const rsk_tune_entry& a, const rsk_tune_entry& b) {
+  return a.path == b.path && a.dtype == b.dtype && a.m == b.m && a.n == b.n && a.eta == b.eta && a.R == b.R;
+}
+
+int32_t tune_load_locked(const char* path);
+
+void tune_env_locked() {
+  if (g_tune_env_done) return;
+  g_tune_env_done = true;
+  const char* f = getenv("RSK_TUNE_CACHE");
+  if (f && *f) tune_load_locked(f);
+}
+
+bool tune_find(int32_t path, int32_t dtype, int64_t m, int64_t n, int32_t eta, int32_t R, rsk_tune_entry* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_env_locked();
+  rsk_tune_entry key{};
+  key.path = path; key.dtype = dtype; key.m = m; key.n = n; key.eta = eta; key.R = R;
+  for (const rsk_tune_entry& e : g_tune)
+    if (tune_same_key(e, key)) { *out = e; return true; }
+  return false;
+}
+
+void tune_put_locked(const rsk_tune_entry& e) {
+  for (rsk_tune_entry& x : g_tune)
+    if (tune_same_key(x, e)) { x = e; return; }
+  g_tune.push_back(e);
+}
+
+// the batched classes of one dtype, ascending by their step-byte bound
+rsk::BatchWgTable tune_batch_table(int32_t dtype) {
+  rsk::BatchWgTable t{};
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_env_locked();
+  std::vector<rsk_tune_entry> cls;
+  for (const rsk_tune_entry& e : g_tune)
+    if (e.path == RSK_TUNE_BATCHED && e.dtype == dtype && e.v0 > 0) cls.push_back(e);
+  std::sort(cls.begin(), cls.end(), [](const rsk_tune_entry& a, const rsk_tune_entry& b) { return a.m < b.m; });
+  for (const rsk_tune_entry& e : cls) {
+    if (t.nc == rsk::kBatchClasses) break;
+    t.hi[t.nc] = e.m;
+    t.wg[t.nc] = e.v0;
+    ++t.nc;
+  }
+  return t;
+}
+
+// Cache file: one entry per line, whitespace-separated:
+//   path dtype m n eta R v0 v1 us
+// '#' starts a comment line. Unknown paths and malformed lines are skipped.
+int32_t tune_load_locked(const char* path) {
+  FILE* f = fopen(path, "r");
+  if (!f) return RSK_ERR_INVALID_ARG;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    rsk_tune_entry e{};
+    long long m, n, v0, v1;
+    int pth, dt, eta, R;
+    double us;
+    if (sscanf(line, "%d %d %lld %lld %d %d %lld %lld %lf", &pth, &dt, &m, &n, &eta, &R, &v0, &v1, &us) != 9)
+      continue;
+    if (pth < RSK_TUNE_DENSE || pth > RSK_TUNE_BATCHED) continue;
+    e.path = pth; e.dtype = dt; e.m = m; e.n = n; e.eta = eta; e.R = R; e.v0 = v0; e.v1 = v1; e.us = us;
+    tune_put_locked(e);
+  }
+  fclose(f);
+  return RSK_OK;
+}
 
 constexpr int kMaxEtaDense = 16384;
 constexpr size_t kTileCacheBytes = 96 * 1024;
@@ -134,7 +219,30 @@ bool plan_dense_rt(const rsk_dense* A, const rsk_params* p, int rg, DensePlan* p
 }
 
 template <typename T>
+int32_t plan_dense_fixed(const rsk_dense* A, const rsk_params* p, DensePlan* pl);
+
+// kernel = 0 and grid = 0: a tuned (kernel, grid) for this (dtype, m, n, eta), if the table has one
+// that applies to this matrix (alignment and leading dimension are not part of the key); else the
+// built-in choice.
+template <typename T>
 int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
+  rsk_tune_entry e;
+  if (p->kernel == 0 && p->grid == 0 &&
+      tune_find(RSK_TUNE_DENSE, A->dtype, A->m, A->n, p->eta, 0, &e) && e.v0 >= 1 && e.v0 <= 3 && e.v1 >= 1) {
+    rsk_params q = *p;
+    q.kernel = (int32_t)e.v0;
+    q.grid = (int32_t)e.v1;
+    DensePlan t;
+    if (plan_dense_fixed<T>(A, &q, &t) == RSK_OK) {
+      *pl = t;
+      return RSK_OK;
+    }
+  }
+  return plan_dense_fixed<T>(A, p, pl);
+}
+
+template <typename T>
+int32_t plan_dense_fixed(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   const size_t s = sizeof(T);
   pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0; pl->rg = 1;
   // float32: the register-tile kernel wherever its shape limits allow; its exchange is cheaper
@@ -317,8 +425,11 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   pl->eta_pad = (p->eta + 63) / 64 * 64;
   const int tiles = (pl->eta_pad / 64) * ((R + 63) / 64);
   const int cus = device_cus() > 0 ? device_cus() : 256;
+  rsk_tune_entry te;
+  const bool tuned = tune_find(RSK_TUNE_MULTIRHS, A->dtype, A->m, A->n, p->eta, R, &te);
   int S = (3 * cus + tiles - 1) / tiles;  // about three workgroups per CU for the n-long products
   if (S >= 8) S = (S + 7) / 8 * 8;        // whole XCD rounds: the tiles of a split share one L2
+  if (tuned && te.v0 >= 1) S = (int)(te.v0 < 4096 ? te.v0 : 4096);
   const int64_t max_s = (A->n + 255) / 256;  // at least 256 columns a split
   if (S > max_s) S = (int)max_s;
   if (S < 1) S = 1;
@@ -330,6 +441,8 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   const int att_tiles = (int)((A->n + 63) / 64) * ((R + 63) / 64);
   int S2 = cus / att_tiles;
   const int max_s2 = (p->eta + 63) / 64;
+  if (S2 > max_s2) S2 = max_s2;
+  if (tuned && te.v1 >= 1) S2 = (int)(te.v1 < 8 ? te.v1 : 8);
   if (S2 > max_s2) S2 = max_s2;
   S2 = S2 >= 8 ? 8 : S2 >= 4 ? 4 : S2 >= 2 ? 2 : 1;  // the reduction kernels take 2, 4 or 8
   pl->S2 = S2;
@@ -357,7 +470,8 @@ int32_t check_batch_item(const rsk_batch_item& it) {
 // [region offsets, nsys int64][one exchange region per system].
 struct BatchLayout {
   int vec, gmax;
-  int64_t wg_bytes, tickets, words;
+  rsk::BatchWgTable tab;
+  int64_t tickets, words;
   size_t lds, off_t0, off_woff, off_region, bytes;
 };
 
@@ -366,7 +480,14 @@ int32_t batch_layout(int32_t nsys, int32_t dtype, const rsk_batch_item* items, i
   if (dtype != RSK_F32 && dtype != RSK_F64) return RSK_ERR_UNSUPPORTED;
   const size_t es = elem_size(dtype);
   const int vmax = (int)(16 / es);
-  L->wg_bytes = wg_bytes ? wg_bytes : rsk::kBatchWgBytes;
+  if (wg_bytes > 0) {
+    L->tab = rsk::BatchWgTable{};
+    L->tab.nc = 1;
+    L->tab.hi[0] = INT64_MAX;
+    L->tab.wg[0] = wg_bytes;
+  } else {
+    L->tab = tune_batch_table(dtype);  // no classes: every system takes the default target
+  }
   L->vec = vmax;
   for (int32_t i = 0; i < nsys; ++i) {
     const int32_t st = check_batch_item(items[i]);
@@ -376,7 +497,7 @@ int32_t batch_layout(int32_t nsys, int32_t dtype, const rsk_batch_item* items, i
   L->gmax = 0; L->tickets = 0; L->words = 0; L->lds = 0;
   for (int32_t i = 0; i < nsys; ++i) {
     rsk::BatchPlan pl;
-    if (!rsk::batched_plan(items[i].n, items[i].eta, (int)es, L->vec, L->wg_bytes, &pl)) return RSK_ERR_UNSUPPORTED;
+    if (!rsk::batched_plan(items[i].n, items[i].eta, (int)es, L->vec, L->tab, &pl)) return RSK_ERR_UNSUPPORTED;
     if (pl.G > L->gmax) L->gmax = pl.G;
     if (pl.lds > L->lds) L->lds = pl.lds;
     L->tickets += pl.G;
@@ -609,10 +730,10 @@ int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item*
   if (rsk::launch_zero_words((u64*)w, L.bytes / sizeof(u64), s) != hipSuccess) return RSK_ERR_HIP;
   int64_t* t0 = (int64_t*)(w + L.off_t0);
   int64_t* wo = (int64_t*)(w + L.off_woff);
-  if (rsk::launch_batched_prep(items_dev, order, nsys, (int)elem_size(dtype), L.vec, L.wg_bytes, L.lds,
+  if (rsk::launch_batched_prep(items_dev, order, nsys, (int)elem_size(dtype), L.vec, L.tab, L.lds,
                                L.words, t0, wo, s) != hipSuccess)
     return RSK_ERR_HIP;
-  if (rsk::launch_batched(items_dev, order, nsys, t0, wo, (u64*)w, (u64*)(w + L.off_region), L.wg_bytes, dtype,
+  if (rsk::launch_batched(items_dev, order, nsys, t0, wo, (u64*)w, (u64*)(w + L.off_region), L.tab, dtype,
                           L.vec, L.lds, grid, s) != hipSuccess)
     return RSK_ERR_HIP;
   return RSK_OK;
@@ -890,6 +1011,63 @@ int32_t rsk_bsk_solve_dense(const rsk_dense* A, const void* b, const rsk_params*
   return A->dtype == RSK_F64
       ? bsk_solve_t<double>(A, b, p, x_star, x, block_norm2, workspace, ws_bytes, (hipStream_t)stream)
       : bsk_solve_t<float>(A, b, p, x_star, x, block_norm2, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t rsk_tune_set(const rsk_tune_entry* e) {
+  if (!e || e->path < RSK_TUNE_DENSE || e->path > RSK_TUNE_BATCHED) return RSK_ERR_INVALID_ARG;
+  if (e->dtype != RSK_F32 && e->dtype != RSK_F64) return RSK_ERR_INVALID_ARG;
+  if (e->path == RSK_TUNE_BATCHED && (e->m <= 0 || e->v0 <= 0)) return RSK_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_env_locked();
+  tune_put_locked(*e);
+  return RSK_OK;
+}
+
+int32_t rsk_tune_get(const rsk_tune_entry* key, rsk_tune_entry* out, int32_t* found) {
+  if (!key || !out || !found) return RSK_ERR_INVALID_ARG;
+  *found = tune_find(key->path, key->dtype, key->m, key->n, key->eta, key->R, out) ? 1 : 0;
+  return RSK_OK;
+}
+
+int32_t rsk_tune_erase(const rsk_tune_entry* key) {
+  if (!key) return RSK_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_env_locked();
+  g_tune.erase(std::remove_if(g_tune.begin(), g_tune.end(), [&](const rsk_tune_entry& e) { return tune_same_key(e, *key); }),
+               g_tune.end());
+  return RSK_OK;
+}
+
+int32_t rsk_tune_clear(int32_t path) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_env_done = true;  // a cleared table is not refilled from RSK_TUNE_CACHE
+  if (path < 0) {
+    g_tune.clear();
+  } else {
+    g_tune.erase(std::remove_if(g_tune.begin(), g_tune.end(), [&](const rsk_tune_entry& e) { return e.path == path; }),
+                 g_tune.end());
+  }
+  return RSK_OK;
+}
+
+int32_t rsk_tune_load(const char* path) {
+  if (!path) return RSK_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_env_done = true;
+  return tune_load_locked(path);
+}
+
+int32_t rsk_tune_save(const char* path) {
+  if (!path) return RSK_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = fopen(path, "w");
+  if (!f) return RSK_ERR_INVALID_ARG;
+  fprintf(f, "# librsk tuning cache: path dtype m n eta R v0 v1 us\n");
+  for (const rsk_tune_entry& e : g_tune)
+    fprintf(f, "%d %d %lld %lld %d %d %lld %lld %.3f\n", e.path, e.dtype, (long long)e.m, (long long)e.n, e.eta, e.R,
+            (long long)e.v0, (long long)e.v1, e.us);
+  const bool ok = fclose(f) == 0;
+  return ok ? RSK_OK : RSK_ERR_INVALID_ARG;
 }
 
 int32_t rsk_abi_version(void) { return RSK_ABI_VERSION; }

@@ -3,9 +3,10 @@
 // System s is solved by a group of G_s workgroups that split its columns the
 // way the single-system dense kernel does, with the same device code
 // (dense_run), exchanging partial dots through the system's own region of the
-// workspace. G_s follows the system's row bytes per step, so a large system
-// gets many CUs and a small one a single workgroup (whose exchange then stays
-// in LDS).
+// workspace. G_s follows the system's row bytes per step (a target of row
+// bytes per workgroup, per size class of the step: one explicit target, or the
+// tuned classes of the library's tuning table), so a large system gets many
+// CUs and a small one a single workgroup (whose exchange then stays in LDS).
 //
 // Scheduling. The systems, in the caller's order, own consecutive ranges of
 // G_s tickets. Persistent workgroups draw tickets from one atomic counter;
@@ -40,7 +41,7 @@ __device__ bool item_ok(const rsk_batch_item& it) {
 // and every system reports RSK_ERR_WORKSPACE.
 __global__ __launch_bounds__(kPrepThreads) void batched_prep(const rsk_batch_item* __restrict__ items,
                                                              const int32_t* __restrict__ order, int nsys, int esize,
-                                                             int vec, int64_t wg_bytes, size_t lds_launch,
+                                                             int vec, BatchWgTable tab, size_t lds_launch,
                                                              int64_t cap_words, int64_t* ticket0, int64_t* woff) {
   __shared__ int64_t sg[kPrepThreads], sw[kPrepThreads];
   const int tid = threadIdx.x;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(kPrepThreads) void batched_prep(const rsk_batch_ite
     if (s >= 0 && s < nsys) {
       const rsk_batch_item it = items[s];
       BatchPlan pl;
-      const bool ok = item_ok(it) && batched_plan(it.n, it.eta, esize, vec, wg_bytes, &pl) && pl.lds <= lds_launch;
+      const bool ok = item_ok(it) && batched_plan(it.n, it.eta, esize, vec, tab, &pl) && pl.lds <= lds_launch;
       if (ok) { G = pl.G; words = pl.words; }
       if (it.status_dev) {
         it.status_dev[0] = ok ? 0 : 1;
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kPrepThreads) void batched_prep(const rsk_batch_ite
     if (s >= 0 && s < nsys) {
       const rsk_batch_item it = items[s];
       BatchPlan pl;
-      if (item_ok(it) && batched_plan(it.n, it.eta, esize, vec, wg_bytes, &pl) && pl.lds <= lds_launch) {
+      if (item_ok(it) && batched_plan(it.n, it.eta, esize, vec, tab, &pl) && pl.lds <= lds_launch) {
         G = pl.G;
         words = pl.words;
       }
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(kDenseThreads) void rska_batched(const rsk_batch_it
                                                               const int32_t* __restrict__ order, int nsys,
                                                               const int64_t* __restrict__ ticket0,
                                                               const int64_t* __restrict__ woff, u64* queue,
-                                                              u64* regions, int64_t wg_bytes, uint64_t join_ticks) {
+                                                              u64* regions, BatchWgTable tab, uint64_t join_ticks) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int64_t sh[3];
   const int tid = threadIdx.x;
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kDenseThreads) void rska_batched(const rsk_batch_it
     const int s = order ? order[p] : p;
     const rsk_batch_item it = items[s];
     BatchPlan pl;
-    batched_plan(it.n, it.eta, sizeof(T), VEC, wg_bytes, &pl);  // succeeded in the prep kernel
+    batched_plan(it.n, it.eta, sizeof(T), VEC, tab, &pl);  // succeeded in the prep kernel
     const int rank = (int)(t - ticket0[p]);
     u64* region = regions + woff[p];
 
@@ -166,9 +167,9 @@ __global__ __launch_bounds__(kDenseThreads) void rska_batched(const rsk_batch_it
 }
 
 hipError_t launch_batched_prep(const rsk_batch_item* items, const int32_t* order, int nsys, int esize, int vec,
-                               int64_t wg_bytes, size_t lds_launch, int64_t cap_words, int64_t* ticket0,
+                               const BatchWgTable& tab, size_t lds_launch, int64_t cap_words, int64_t* ticket0,
                                int64_t* woff, hipStream_t stream) {
-  hipLaunchKernelGGL(batched_prep, dim3(1), dim3(kPrepThreads), 0, stream, items, order, nsys, esize, vec, wg_bytes,
+  hipLaunchKernelGGL(batched_prep, dim3(1), dim3(kPrepThreads), 0, stream, items, order, nsys, esize, vec, tab,
                      lds_launch, cap_words, ticket0, woff);
   return hipGetLastError();
 }
@@ -191,7 +192,7 @@ int batched_max_resident(int dtype, int vec, size_t lds) {
 }
 
 hipError_t launch_batched(const rsk_batch_item* items, const int32_t* order, int nsys, const int64_t* ticket0,
-                          const int64_t* woff, u64* queue, u64* regions, int64_t wg_bytes, int dtype, int vec,
+                          const int64_t* woff, u64* queue, u64* regions, const BatchWgTable& tab, int dtype, int vec,
                           size_t lds, int grid, hipStream_t stream) {
   void* fn = batched_fn(dtype, vec);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -200,7 +201,8 @@ hipError_t launch_batched(const rsk_batch_item* items, const int32_t* order, int
   if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
   uint64_t join_ticks = (uint64_t)khz * 1000ull * 60ull;  // a minute
-  void* args[] = {&items, &order, &nsys, &ticket0, &woff, &queue, &regions, &wg_bytes, &join_ticks};
+  BatchWgTable t = tab;
+  void* args[] = {&items, &order, &nsys, &ticket0, &woff, &queue, &regions, &t, &join_ticks};
   // co-residency of the whole grid: a group forms only from running workgroups
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kDenseThreads), args, (unsigned)lds, stream);
 }

@@ -195,9 +195,26 @@ struct BatchPlan {
   size_t lds;
 };
 
-__host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int vec, int64_t wg_bytes,
+// Row bytes per workgroup by size class of a system's step (eta * n * element bytes): system s
+// takes the first class with step bytes <= hi[c] (classes ascend), else the default. Either one
+// class of every size (an explicit target) or the tuned classes of the library's tuning table.
+constexpr int kBatchClasses = 8;
+struct BatchWgTable {
+  int nc;
+  int64_t hi[kBatchClasses];
+  int64_t wg[kBatchClasses];
+  __host__ __device__ int64_t lookup(int64_t step_bytes) const {
+    for (int c = 0; c < nc; ++c)
+      if (step_bytes <= hi[c]) return wg[c];
+    return kBatchWgBytes;
+  }
+};
+
+__host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int vec, const BatchWgTable& tab,
                                              BatchPlan* p) {
-  if (n <= 0 || eta <= 0 || vec <= 0 || wg_bytes <= 0) return false;
+  if (n <= 0 || eta <= 0 || vec <= 0) return false;
+  const int64_t wg_bytes = tab.lookup((int64_t)eta * n * esize);
+  if (wg_bytes <= 0) return false;
   const int64_t nchunks = (n + vec - 1) / vec;
   const int64_t gmax = nchunks < kBatchGcap ? nchunks : kBatchGcap;
   int64_t G = ((int64_t)eta * n * esize + wg_bytes - 1) / wg_bytes;
@@ -230,12 +247,12 @@ __host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int 
 }
 
 hipError_t launch_batched_prep(const rsk_batch_item* items, const int32_t* order, int nsys, int esize, int vec,
-                               int64_t wg_bytes, size_t lds_launch, int64_t cap_words, int64_t* ticket0,
+                               const BatchWgTable& tab, size_t lds_launch, int64_t cap_words, int64_t* ticket0,
                                int64_t* woff, hipStream_t stream);
 // Largest co-resident grid of the batched kernel with this LDS size (0 if none).
 int batched_max_resident(int dtype, int vec, size_t lds);
 hipError_t launch_batched(const rsk_batch_item* items, const int32_t* order, int nsys, const int64_t* ticket0,
-                          const int64_t* woff, u64* queue, u64* regions, int64_t wg_bytes, int dtype, int vec,
+                          const int64_t* woff, u64* queue, u64* regions, const BatchWgTable& tab, int dtype, int vec,
                           size_t lds, int grid, hipStream_t stream);
 
 struct DenseLaunch {
