@@ -246,7 +246,7 @@ def main():
             sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
             out = floor_run(sysd["A"], torch.from_numpy(sysd["b"]).to(dev), dev, stream)
         else:
-            out = (fn(dev, stream, tune=not args.no_tune) if args.only in ("batched", "multirhs", "config0")
+            out = (fn(dev, stream, tune=not args.no_tune) if args.only in ("batched", "multirhs", "config0", "adjoint")
                    else fn(dev, stream))
         print(json.dumps({args.only: out}), flush=True)
         teardown()
@@ -384,7 +384,7 @@ def main():
         out["batched"] = batched_run(dev, stream, tune=not args.no_tune)
         torch.cuda.empty_cache()
         out["multirhs"] = multirhs_run(dev, stream, tune=not args.no_tune)
-        out["adjoint"] = adjoint_run(dev, stream)
+        out["adjoint"] = adjoint_run(dev, stream, tune=not args.no_tune)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -720,7 +720,7 @@ def multirhs_time_to_tol(A, B, Xh, r2, alpha, eta, stream, tol=1e-5, C=20, kmax=
 ADJ_M, ADJ_N, ADJ_R, ADJ_ETA, ADJ_K, ADJ_C, ADJ_SEED = 8192, 4096, 64, 410, 200, 20, 20310838 + 400
 
 
-def adjoint_run(dev, stream):
+def adjoint_run(dev, stream, tune=False):
     """Differentiable unrolled RSKA: A 8192x4096 float32 N(0,1) (device), R = 64 right-hand sides from
     x_hat with 40 N(0,1) nonzeros, K = 200 steps, eta = 410, lambda = 1, alpha_k = alpha*, loss
     sum_r ||x_K - x_hat_r||^2, x* checkpoints every 20 steps. One training step = forward with
@@ -750,6 +750,17 @@ def adjoint_run(dev, stream):
                                   rownorm2_t=r2, ckpt=ckpt if with_ckpt else None, ckpt_every=C, workspace=ws,
                                   check=False)
 
+    tune_info = None
+    if tune:
+        # the forward and reverse products share the split of (m, n, eta, R): tuned on forward steps
+        from paper_2203_10838_amd import autotune
+        t = autotune.tune_multirhs(A, B, eta=eta, lam=1.0, alpha=alpha, index_stream=idx, steps=20, reps=3,
+                                   rownorm2_t=r2)
+        tune_info = {"default_plan": t["default"]["plan"], "default_us_per_step": round(t["default"]["us_per_step"], 2),
+                     "tuned": {"S": t["choice"][0], "S2": t["choice"][1]},
+                     "tuned_us_per_step": round(t["us_per_step"], 2), "candidates": len(t["table"])}
+        log(f"[bench] adjoint shape tuned: {tune_info}")
+
     def train_step():
         f = fwd()
         xbar = 2.0 * (f.x - Xht)
@@ -773,7 +784,10 @@ def adjoint_run(dev, stream):
            "train_TFLOPs_3x_forward_flops": round(3 * fl * K / (t_train * 1e-3) / 1e12, 2),
            "plain_single_rhs_steps_per_s": round(K / (t_plain * 1e-3), 1),
            "grad_norms": {"B": float(adj.Bbar.norm()), "lambda": float(adj.lambda_bar[0]),
-                          "alpha": float(adj.alpha_bar.norm())}}
+                          "alpha": float(adj.alpha_bar.norm())},
+           "plan": rsk.plan_multirhs(A, R, eta=eta)}
+    if tune_info is not None:
+        out["tuning"] = tune_info
     log(f"[bench] adjoint: {out}")
     return out
 

@@ -96,7 +96,8 @@ typedef struct {
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register
                                   tile, 3 = float32 register tile over two row groups (see
-                                  rsk_avg_solve_dense); CSR: 0, 1 or 2 */
+                                  rsk_avg_solve_dense); CSR: 0, 1 or 2; multi-RHS: 0, 1 or 2 (see
+                                  rsk_avg_solve_multirhs) */
   const void *row_w;           /* nullable device array (m, dtype of A): per-row weights w_i, the diagonal W of
                                   Definition 1 (variants v3/v4 of Sec. 5); row i is relaxed by alpha (or
                                   alpha_k[k]) times w_i. Dense, CSR and multi-RHS solves; not the adjoint or
@@ -234,14 +235,15 @@ int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
  * leading dimension) falls back to the built-in rule.
  *   path RSK_TUNE_DENSE:    key (dtype, m, n, eta);    v0 = kernel (1..3), v1 = grid.
  *   path RSK_TUNE_MULTIRHS: key (dtype, m, n, eta, R); v0 = S (splits of the n columns in
- *                           A_tau X), v1 = S2 (row splits of A_tau^T C: 1, 2, 4 or 8).
+ *                           A_tau X), v1 = S2 (row splits of A_tau^T C: 1, 2, 4 or 8), v2 = the
+ *                           forward's kernel (1 step kernels, 2 one persistent launch; 0 = built-in).
  *   path RSK_TUNE_BATCHED:  key (dtype, m = the class's upper bound on a system's step bytes
  *                           eta * n * element size; n = eta = R = 0); v0 = row bytes per
  *                           workgroup for systems of that class (a system takes the class
  *                           with the smallest bound >= its step bytes; at most 8 classes).
  * `us` is the measured time of the choice (informational). The cache file
  * (rsk_tune_save / rsk_tune_load) is text, one entry per line:
- * "path dtype m n eta R v0 v1 us". If the environment variable RSK_TUNE_CACHE
+ * "path dtype m n eta R v0 v1 v2 us". If the environment variable RSK_TUNE_CACHE
  * names a file, it is loaded at the first lookup. All calls are thread-safe;
  * a table changed between a workspace query and its solve can make the solve
  * return RSK_ERR_WORKSPACE.
@@ -251,7 +253,7 @@ typedef struct {
   int32_t path, dtype;
   int64_t m, n;
   int32_t eta, R;
-  int64_t v0, v1;
+  int64_t v0, v1, v2;
   double us;
 } rsk_tune_entry;
 int32_t rsk_tune_set(const rsk_tune_entry *e);                                   /* install or replace */
@@ -396,8 +398,12 @@ int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item 
  *   X       device, n x R row-major, out.
  * Requires R % 4 == 0, n % 4 == 0, ld % 4 == 0, eta <= 4096, A 16-byte aligned; the
  * monitor and y_out are not supported here (RSK_ERR_UNSUPPORTED).
- * Device faults and status_dev follow the single-RHS conventions; steps are
- * queued as kernels on `stream` (four per step).
+ * p->kernel: 1 = the step kernels (four launches per step), 2 = one persistent
+ * cooperative launch for all K steps (the same products and sums as the step
+ * kernels, tiles passed between workgroups through device-coherent stores and
+ * per-tile counters), 0 = a tuned choice (rsk_tune_*), else 1. Device faults
+ * and status_dev follow the single-RHS conventions (with kernel 2, X* and X
+ * are unspecified after a fault).
  */
 int32_t rsk_workspace_size_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, size_t *bytes);
 int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p, void *X_star,
@@ -405,10 +411,11 @@ int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, con
 
 /*
  * The split of rsk_avg_solve_multirhs's two products for A, R and p, without
- * running it. out: host int32[4] = { S: splits of the n columns in A_tau X
+ * running it. out: host int32[5] = { S: splits of the n columns in A_tau X
  * (fixed-order sum of S partials), columns per split, S2: splits of a step's
  * rows in A_tau^T C (1: one workgroup per 64 x 64 output tile over all rows),
- * eta rounded up to a multiple of 64 }.
+ * eta rounded up to a multiple of 64, the kernel (1 step kernels, 2 one
+ * persistent launch) }.
  */
 int32_t rsk_plan_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, int32_t *out);
 

@@ -43,7 +43,7 @@ class RskBatchItem(ctypes.Structure):
 
 class RskTuneEntry(ctypes.Structure):
     _fields_ = [("path", c_i32), ("dtype", c_i32), ("m", c_i64), ("n", c_i64), ("eta", c_i32), ("R", c_i32),
-                ("v0", c_i64), ("v1", c_i64), ("us", c_dbl)]
+                ("v0", c_i64), ("v1", c_i64), ("v2", c_i64), ("us", c_dbl)]
 
 
 RSK_TUNE_DENSE, RSK_TUNE_MULTIRHS, RSK_TUNE_BATCHED = 0, 1, 2

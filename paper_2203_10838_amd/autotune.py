@@ -27,12 +27,13 @@ import torch
 from . import _abi, rsk
 
 
-def _entry(path, dtype, m=0, n=0, eta=0, R=0, v0=0, v1=0, us=0.0) -> _abi.RskTuneEntry:
-    return _abi.RskTuneEntry(int(path), int(dtype), int(m), int(n), int(eta), int(R), int(v0), int(v1), float(us))
+def _entry(path, dtype, m=0, n=0, eta=0, R=0, v0=0, v1=0, v2=0, us=0.0) -> _abi.RskTuneEntry:
+    return _abi.RskTuneEntry(int(path), int(dtype), int(m), int(n), int(eta), int(R), int(v0), int(v1), int(v2),
+                             float(us))
 
 
-def set_entry(path, dtype, *, m=0, n=0, eta=0, R=0, v0, v1=0, us=0.0) -> None:
-    st = rsk._lib().rsk_tune_set(ctypes.byref(_entry(path, dtype, m, n, eta, R, v0, v1, us)))
+def set_entry(path, dtype, *, m=0, n=0, eta=0, R=0, v0, v1=0, v2=0, us=0.0) -> None:
+    st = rsk._lib().rsk_tune_set(ctypes.byref(_entry(path, dtype, m, n, eta, R, v0, v1, v2, us)))
     if st:
         raise rsk.RskError(st, "rsk_tune_set")
 
@@ -142,16 +143,17 @@ def tune_dense(A: torch.Tensor, b: torch.Tensor, *, eta: int, lam: float, alpha:
 def multirhs_candidates(A: torch.Tensor, R: int, eta: int) -> list:
     """(S, S2) pairs: column splits of A_tau X (at least 256 columns a split) and row splits of A_tau^T C."""
     n = A.shape[1]
-    max_s = max(1, (n + 255) // 256)
+    max_s = max(1, (n + 63) // 64)        # a tuned split keeps at least 64 columns (one stage)
     svals = sorted({s for s in (1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128) if s <= max_s})
-    s2vals = [s2 for s2 in (1, 2, 4, 8) if s2 <= max(1, (eta + 63) // 64)]
-    return [(s, s2) for s in svals for s2 in s2vals]
+    s2vals = [s2 for s2 in (1, 2, 4, 8) if s2 <= max(1, (eta + 15) // 16)]
+    return [(s, s2, kernel) for kernel in (1, 2) for s in svals for s2 in s2vals]
 
 
 def tune_multirhs(A: torch.Tensor, B: torch.Tensor, *, eta: int, lam: float, alpha: float,
                   index_stream: torch.Tensor, steps: int = 4, reps: int = 3, candidates: Optional[Iterable] = None,
                   install: bool = True, rownorm2_t: Optional[torch.Tensor] = None) -> dict:
-    """Time (S, S2) candidates of the multi-RHS products; install the fastest for (dtype, m, n, eta, R)."""
+    """Time (S, S2, kernel) candidates of the multi-RHS forward (kernel 1: step kernels, 2: one persistent
+    launch); install the fastest for (dtype, m, n, eta, R)."""
     m, n = A.shape
     R = B.shape[1]
     dtype = rsk._dtype_code(A)
@@ -168,24 +170,29 @@ def tune_multirhs(A: torch.Tensor, B: torch.Tensor, *, eta: int, lam: float, alp
     default_ms = _time_ms(run, reps)
     table = []
     seen = set()
-    for S, S2 in (list(candidates) if candidates is not None else multirhs_candidates(A, R, eta)):
-        set_entry(_abi.RSK_TUNE_MULTIRHS, dtype, m=m, n=n, eta=eta, R=R, v0=S, v1=S2)
+    for cand in (list(candidates) if candidates is not None else multirhs_candidates(A, R, eta)):
+        S, S2, kernel = (tuple(cand) + (1,))[:3]
+        set_entry(_abi.RSK_TUNE_MULTIRHS, dtype, m=m, n=n, eta=eta, R=R, v0=S, v1=S2, v2=kernel)
         plan = rsk.plan_multirhs(A, R, eta=eta, K=steps)
-        sig = (plan["S"], plan["S2"])
+        sig = (plan["S"], plan["S2"], plan["kernel"])
         if sig in seen:
             continue
         seen.add(sig)
-        ms = _time_ms(run, reps)
-        table.append({"S": plan["S"], "S2": plan["S2"], "us_per_step": ms * 1e3 / steps})
+        try:
+            ms = _time_ms(run, reps)
+        except rsk.RskError:
+            continue
+        table.append({"S": S, "S2": plan["S2"], "kernel": plan["kernel"], "us_per_step": ms * 1e3 / steps})
     best = min(table, key=lambda r: r["us_per_step"])
     if install:
         set_entry(_abi.RSK_TUNE_MULTIRHS, dtype, m=m, n=n, eta=eta, R=R, v0=best["S"], v1=best["S2"],
-                  us=best["us_per_step"])
+                  v2=best["kernel"], us=best["us_per_step"])
     elif prev is not None:
-        set_entry(_abi.RSK_TUNE_MULTIRHS, dtype, m=m, n=n, eta=eta, R=R, v0=prev["v0"], v1=prev["v1"], us=prev["us"])
+        set_entry(_abi.RSK_TUNE_MULTIRHS, dtype, m=m, n=n, eta=eta, R=R, v0=prev["v0"], v1=prev["v1"], v2=prev["v2"],
+                  us=prev["us"])
     else:
         erase(_abi.RSK_TUNE_MULTIRHS, dtype, m=m, n=n, eta=eta, R=R)
-    return {"choice": (best["S"], best["S2"]), "us_per_step": best["us_per_step"],
+    return {"choice": (best["S"], best["S2"], best["kernel"]), "us_per_step": best["us_per_step"],
             "default": {"plan": default_plan, "us_per_step": default_ms * 1e3 / steps}, "table": table}
 
 

@@ -75,7 +75,7 @@ rsk::BatchWgTable tune_batch_table(int32_t dtype) {
 }
 
 // Cache file: one entry per line, whitespace-separated:
-//   path dtype m n eta R v0 v1 us
+//   path dtype m n eta R v0 v1 v2 us
 // '#' starts a comment line. Unknown paths and malformed lines are skipped.
 int32_t tune_load_locked(const char* path) {
   FILE* f = fopen(path, "r");
@@ -84,13 +84,13 @@ int32_t tune_load_locked(const char* path) {
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
     rsk_tune_entry e{};
-    long long m, n, v0, v1;
+    long long m, n, v0, v1, v2;
     int pth, dt, eta, R;
     double us;
-    if (sscanf(line, "%d %d %lld %lld %d %d %lld %lld %lf", &pth, &dt, &m, &n, &eta, &R, &v0, &v1, &us) != 9)
+    if (sscanf(line, "%d %d %lld %lld %d %d %lld %lld %lld %lf", &pth, &dt, &m, &n, &eta, &R, &v0, &v1, &v2, &us) != 10)
       continue;
     if (pth < RSK_TUNE_DENSE || pth > RSK_TUNE_BATCHED) continue;
-    e.path = pth; e.dtype = dt; e.m = m; e.n = n; e.eta = eta; e.R = R; e.v0 = v0; e.v1 = v1; e.us = us;
+    e.path = pth; e.dtype = dt; e.m = m; e.n = n; e.eta = eta; e.R = R; e.v0 = v0; e.v1 = v1; e.v2 = v2; e.us = us;
     tune_put_locked(e);
   }
   fclose(f);
@@ -413,7 +413,10 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
 struct MultiPlan {
   int S, eta_pad, S2;
   int64_t kspan;
-  size_t offY, offC, offW, bytes;
+  int kernel;       // 1: step kernels (four per step), 2: one persistent launch for all K steps
+  int pS;           // persistent launch: its split of the n columns (kspan rounded up to 64)
+  int64_t pkspan;
+  size_t offY, offC, offW, offCnt, cnt_words, bytes;
 };
 
 int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiPlan* pl) {
@@ -430,7 +433,8 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   int S = (3 * cus + tiles - 1) / tiles;  // about three workgroups per CU for the n-long products
   if (S >= 8) S = (S + 7) / 8 * 8;        // whole XCD rounds: the tiles of a split share one L2
   if (tuned && te.v0 >= 1) S = (int)(te.v0 < 4096 ? te.v0 : 4096);
-  const int64_t max_s = (A->n + 255) / 256;  // at least 256 columns a split
+  // at least 256 columns a split by the built-in rule, at least 64 (one stage) for a tuned split
+  const int64_t max_s = tuned && te.v0 >= 1 ? (A->n + 63) / 64 : (A->n + 255) / 256;
   if (S > max_s) S = (int)max_s;
   if (S < 1) S = 1;
   pl->kspan = (A->n + S - 1) / S;
@@ -440,16 +444,25 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   // are split over S2 workgroups (at least 64 rows each) and summed in a second kernel
   const int att_tiles = (int)((A->n + 63) / 64) * ((R + 63) / 64);
   int S2 = cus / att_tiles;
-  const int max_s2 = (p->eta + 63) / 64;
+  // at least 64 rows a split by the built-in rule, at least 16 for a tuned split
+  const int max_s2 = tuned && te.v1 >= 1 ? (p->eta + 15) / 16 : (p->eta + 63) / 64;
   if (S2 > max_s2) S2 = max_s2;
   if (tuned && te.v1 >= 1) S2 = (int)(te.v1 < 8 ? te.v1 : 8);
   if (S2 > max_s2) S2 = max_s2;
   S2 = S2 >= 8 ? 8 : S2 >= 4 ? 4 : S2 >= 2 ? 2 : 1;  // the reduction kernels take 2, 4 or 8
   pl->S2 = S2;
+  // the kernel: p->kernel 1 or 2 as asked, else a tuned choice, else the step kernels
+  pl->kernel = p->kernel == 1 || p->kernel == 2 ? p->kernel : (tuned && (te.v2 == 1 || te.v2 == 2) ? (int)te.v2 : 1);
+  if (p->kernel == 3) return RSK_ERR_INVALID_ARG;
+  pl->pkspan = (pl->kspan + 63) / 64 * 64;
+  pl->pS = (int)((A->n + pl->pkspan - 1) / pl->pkspan);
+  const int64_t gt = pl->eta_pad / 64, gr = (R + 63) / 64, gn = (A->n + 63) / 64;
+  pl->cnt_words = (size_t)(gt * gr + gr + (int64_t)pl->S * gr + gn * gr);
   size_t o = 0;
   pl->offY = o; o = align256(o + (size_t)pl->S * pl->eta_pad * R * sizeof(float));
   pl->offC = o; o = align256(o + (size_t)pl->eta_pad * R * sizeof(float));
   pl->offW = o; o = align256(o + (S2 > 1 ? (size_t)S2 * A->n * R * sizeof(float) : 0));
+  pl->offCnt = o; o = align256(o + pl->cnt_words * sizeof(unsigned));
   pl->bytes = o;
   return RSK_OK;
 }
@@ -529,6 +542,40 @@ void fill_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_param
   const bool al = ((uintptr_t)X_star) % 16 == 0 && ((uintptr_t)X) % 16 == 0;
   a.S2 = (pl.S2 > 1 && al) ? pl.S2 : 1;
   a.Wp = a.S2 > 1 ? (float*)(w + pl.offW) : nullptr;
+  // tile counters of the split-K fix-ups: [gt * gr] for R_tau, then [gr], [S * gr], [gn * gr] for A_tau^T C
+  const int64_t gt = pl.eta_pad / 64, gr = (R + 63) / 64;
+  a.ycnt = (unsigned*)(w + pl.offCnt);
+  a.wcnt = a.ycnt + gt * gr + gr + (int64_t)pl.S * gr;
+}
+
+// One multi-RHS forward solve on the planned kernel (the persistent one zeroes its counters first).
+int32_t launch_multirhs_planned(const rsk_dense* A, int32_t R, const MultiPlan& pl, const rsk::MultiRhsArgs& a,
+                                void* workspace, hipStream_t s, float* ckpt, int64_t ckpt_every) {
+  if (pl.kernel != 2) {
+    if (rsk::launch_zero_words((u64*)((unsigned char*)workspace + pl.offCnt), (pl.cnt_words * sizeof(unsigned) + 7) / 8,
+                               s) != hipSuccess)
+      return RSK_ERR_HIP;
+  }
+  if (pl.kernel == 2) {
+    const int grid = rsk::multirhs_persistent_grid();
+    if (grid < 1) return RSK_ERR_UNSUPPORTED;
+    unsigned char* w = (unsigned char*)workspace;
+    unsigned* cnt = (unsigned*)(w + pl.offCnt);
+    rsk::MrpWork mw;
+    mw.gt = pl.eta_pad / 64;
+    mw.gr = (R + 63) / 64;
+    mw.gn = (int)((A->n + 63) / 64);
+    mw.S = pl.pS;
+    mw.kspan = pl.pkspan;
+    mw.ycnt = cnt;
+    mw.ccnt = mw.ycnt + mw.gt * mw.gr;
+    mw.xcnt = mw.ccnt + mw.gr;
+    mw.wcnt = mw.xcnt + (size_t)pl.S * mw.gr;
+    if (rsk::launch_zero_words((u64*)(w + pl.offCnt), (pl.cnt_words * sizeof(unsigned) + 7) / 8, s) != hipSuccess)
+      return RSK_ERR_HIP;
+    return rsk::launch_multirhs_persistent(a, mw, grid, s, ckpt, ckpt_every) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
+  }
+  return rsk::launch_multirhs(a, s, ckpt, ckpt_every) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
 }
 
 // Adjoint workspace: the forward's (Y, C) then Zh, Rh, x, zbar and the partial sums.
@@ -761,10 +808,11 @@ int32_t rsk_plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, in
   MultiPlan pl;
   st = plan_multirhs(A, R, p, &pl);
   if (st) return st;
-  out[0] = pl.S;
-  out[1] = (int32_t)pl.kspan;
+  out[0] = pl.kernel == 2 ? pl.pS : pl.S;
+  out[1] = (int32_t)(pl.kernel == 2 ? pl.pkspan : pl.kspan);
   out[2] = pl.S2;
   out[3] = pl.eta_pad;
+  out[4] = pl.kernel;
   return RSK_OK;
 }
 
@@ -782,8 +830,7 @@ int32_t rsk_avg_solve_multirhs(const rsk_dense* A, const void* B, int32_t R, con
   rsk::MultiRhsArgs a;
   fill_multirhs(A, B, R, p, X_star, X, &pl, workspace, &a);
   if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
-  if (rsk::launch_multirhs(a, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
-  return RSK_OK;
+  return launch_multirhs_planned(A, R, pl, a, workspace, (hipStream_t)stream, nullptr, 1);
 }
 
 
@@ -802,8 +849,7 @@ int32_t rsk_avg_solve_multirhs_ckpt(const rsk_dense* A, const void* B, int32_t R
   rsk::MultiRhsArgs a;
   fill_multirhs(A, B, R, p, X_star, X, &pl, workspace, &a);
   if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
-  if (rsk::launch_multirhs(a, (hipStream_t)stream, (float*)ckpt, ckpt_every) != hipSuccess) return RSK_ERR_HIP;
-  return RSK_OK;
+  return launch_multirhs_planned(A, R, pl, a, workspace, (hipStream_t)stream, (float*)ckpt, ckpt_every);
 }
 
 int32_t rsk_workspace_size_adjoint(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t ckpt_every,
@@ -855,6 +901,9 @@ int32_t rsk_avg_adjoint(const rsk_dense* A, const void* B, int32_t R, const rsk_
   d.zbar = (float*)(w + L.offZbar);
   d.abar_part = (double*)(w + L.offAbar);
   d.lam_part = (double*)(w + L.offLam);
+  if (rsk::launch_zero_words((u64*)(w + pl.offCnt), (pl.cnt_words * sizeof(unsigned) + 7) / 8, (hipStream_t)stream) !=
+      hipSuccess)
+    return RSK_ERR_HIP;
   if (rsk::launch_zero_status(p->status_dev, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
   if (rsk::launch_adjoint(d, (hipStream_t)stream) != hipSuccess) return RSK_ERR_HIP;
   return RSK_OK;
@@ -1062,10 +1111,10 @@ int32_t rsk_tune_save(const char* path) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   FILE* f = fopen(path, "w");
   if (!f) return RSK_ERR_INVALID_ARG;
-  fprintf(f, "# librsk tuning cache: path dtype m n eta R v0 v1 us\n");
+  fprintf(f, "# librsk tuning cache: path dtype m n eta R v0 v1 v2 us\n");
   for (const rsk_tune_entry& e : g_tune)
-    fprintf(f, "%d %d %lld %lld %d %d %lld %lld %.3f\n", e.path, e.dtype, (long long)e.m, (long long)e.n, e.eta, e.R,
-            (long long)e.v0, (long long)e.v1, e.us);
+    fprintf(f, "%d %d %lld %lld %d %d %lld %lld %lld %.3f\n", e.path, e.dtype, (long long)e.m, (long long)e.n, e.eta,
+            e.R, (long long)e.v0, (long long)e.v1, (long long)e.v2, e.us);
   const bool ok = fclose(f) == 0;
   return ok ? RSK_OK : RSK_ERR_INVALID_ARG;
 }

@@ -153,9 +153,23 @@ struct MultiRhsArgs {
   int64_t kspan;
   int S2 = 1;             // row splits of the A_tau^T products (small n x R outputs)
   float* Wp = nullptr;    // S2 x n x R partials of A_tau^T C when S2 > 1
+  unsigned* ycnt = nullptr;  // per 64 x 64 tile of R_tau: split partials counted (zero before a solve)
+  unsigned* wcnt = nullptr;  // per 64 x 64 tile of A_tau^T C: row-split partials counted (zero before a solve)
 };
 // ckpt (nullable): x*_k is copied to ckpt[k / ckpt_every] before every step k with k % ckpt_every == 0.
 hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckpt = nullptr, int64_t ckpt_every = 1);
+
+// Persistent multi-RHS forward (one cooperative launch for all K steps): its own split of the n
+// columns (kspan a multiple of 64, S = ceil(n / kspan)) and the tile counters, zeroed before the
+// launch: ycnt [gt * gr], ccnt [gr], xcnt [S * gr], wcnt [gn * gr].
+struct MrpWork {
+  int gt, gr, gn, S;
+  int64_t kspan;
+  unsigned *ycnt, *ccnt, *xcnt, *wcnt;
+};
+int multirhs_persistent_grid();
+hipError_t launch_multirhs_persistent(const MultiRhsArgs& a, const MrpWork& w, int grid, hipStream_t stream,
+                                      float* ckpt = nullptr, int64_t ckpt_every = 1);
 
 // Reverse mode of K multi-RHS steps. f holds the forward's arguments (alpha_k required);
 // workspace pieces: Zh (ckpt_every+1) n x R, Rh ckpt_every eta_pad x R, zbar n x R, partial sums.

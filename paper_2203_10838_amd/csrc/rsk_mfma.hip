@@ -108,6 +108,15 @@ __device__ __forceinline__ void att_mainloop(const float* __restrict__ A, int64_
   }
 }
 
+// Workgroup-uniform read of the fault word (thread 0 reads, everyone agrees).
+__device__ __forceinline__ bool any_fault(const int* status, int* flag) {
+  if (threadIdx.x == 0) *flag = __hip_atomic_load(const_cast<int*>(status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const bool f = *flag != 0;
+  __syncthreads();
+  return f;
+}
+
 __device__ __forceinline__ void stage_tau(const int32_t* __restrict__ tau, int eta, int* taus) {
   for (int t = threadIdx.x; t < eta; t += blockDim.x) taus[t] = tau[t];
 }
@@ -119,13 +128,19 @@ __device__ __forceinline__ void stage_tau(const int32_t* __restrict__ tau, int e
 // multiple of 8 the gt * gr tiles of one split run on one XCD (workgroup i goes to XCD i % 8), so
 // that XCD's L2 fetches A_tau[:, K_s] and X[K_s, :] once and serves their re-reads by the other
 // tiles (A_tau by the gr column tiles, X by the gt row tiles).
+//
+// With m > 0 each workgroup also range-checks the sampled rows it reads (a bad index is read as row
+// 0 and faults step k, so no later kernel of the step runs), and workgroup 0 records that the steps
+// before k completed (status[1] only grows: a fault at step k records k as well).
 __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, int64_t ld, int64_t n,
                                                   const int32_t* __restrict__ tau, int eta, const float* __restrict__ X,
                                                   int R, float* __restrict__ Y, int eta_pad, int64_t kspan,
-                                                  int gt, int gr, int S, const int* status) {
-  if (status[0]) return;
+                                                  int gt, int gr, int S, int* status, int64_t m, int64_t k) {
   __shared__ __align__(16) float Ar[BM][LDA];
   __shared__ __align__(16) float Bs[SK][LDP];
+  __shared__ int flag;
+  if (any_fault(status, &flag)) return;
+  if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicMax(status + 1, (int)k);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int id = blockIdx.x, T = gt * gr;
@@ -147,11 +162,18 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
   const int lr = tid >> 4, lc = (tid & 15) * 4;
   const float* arow[4];
   bool aok[4];
+  int bad = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int t = t0 + lr + 16 * i;
     aok[i] = t < eta;
-    arow[i] = A + (int64_t)(aok[i] ? tau[t] : 0) * ld;
+    int row = aok[i] ? tau[t] : 0;
+    if (m > 0 && (row < 0 || (int64_t)row >= m)) { bad = 1; row = 0; }
+    arow[i] = A + (int64_t)row * ld;
+  }
+  if (bad) {
+    set_status(status, ST_INDEX);
+    atomicMax(status + 1, (int)k);
   }
   const bool rok = r0 + lc < R;
   auto load = [&](int64_t jb, Stage& st) {
@@ -374,8 +396,76 @@ __global__ void init_multirhs(float* Xs, float* X, size_t total, float lambda, i
   }
 }
 
-// One forward step k: R_tau from x, C, Zout = Zin - A_tau^T C, x = S_lambda(Zout), then the
-// next step's index check (or the final step count).
+namespace {
+
+constexpr int kCq = 4;  // C items per 64 x 64 tile (16 rows each)
+
+__device__ __forceinline__ float4 ld_dev4(const float* p) {
+  const u64 lo = __hip_atomic_load(reinterpret_cast<const u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u64 hi = __hip_atomic_load(reinterpret_cast<const u64*>(p) + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_float4(__uint_as_float((unsigned)lo), __uint_as_float((unsigned)(lo >> 32)),
+                     __uint_as_float((unsigned)hi), __uint_as_float((unsigned)(hi >> 32)));
+}
+__device__ __forceinline__ void st_dev4(float* p, float4 v) {
+  __hip_atomic_store(reinterpret_cast<u64*>(p), (u64)__float_as_uint(v.x) | ((u64)__float_as_uint(v.y) << 32),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(reinterpret_cast<u64*>(p) + 1, (u64)__float_as_uint(v.z) | ((u64)__float_as_uint(v.w) << 32),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev1(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The workgroup's stores are complete, then one thread counts the item done.
+__device__ __forceinline__ void publish(unsigned* cnt) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until *cnt >= target (bounded), the workgroup learns the outcome: false when a
+// fault is recorded or the wait expired (then the fault is ST_ABORTED).
+__device__ __forceinline__ bool await(const unsigned* cnt, unsigned target, int* status, int* flag) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    unsigned spins = 0;
+    for (;;) {
+      if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      if (__hip_atomic_load(const_cast<unsigned*>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (++spins > kSpinLimit) { set_status(status, ST_ABORTED); ok = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *flag = ok;
+  }
+  __syncthreads();
+  const bool ok = *flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Whether a fault is recorded, decided once for the whole workgroup (thread 0 reads, all agree).
+__device__ __forceinline__ bool faulted(int* status, int* flag) {
+  if (threadIdx.x == 0) *flag = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const bool f = *flag != 0;
+  __syncthreads();
+  return f;
+}
+
+__device__ __forceinline__ void fault(int* status, int code, int64_t k) {
+  set_status(status, code);
+  atomicMin(status + 1, (int)k);
+}
+
+}  // namespace
+
+// status[1] = K after the last step if nothing faulted.
+__global__ void steps_done(int* status, int64_t K) {
+  if (threadIdx.x == 0 && status[0] == 0) status[1] = (int)K;
+}
+
+// One forward step k: R_tau from x (with the step's index check), C, Zout = Zin - A_tau^T C,
+// x = S_lambda(Zout).
 static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, float* zout, float* rh,
                           hipStream_t stream) {
   const int gt = (a.eta + BM - 1) / BM;
@@ -383,7 +473,7 @@ static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, fl
   const int gn = (int)((a.n + BM - 1) / BM);
   const int32_t* tk = a.idx + k * (int64_t)a.eta;
   hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R,
-                     a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status);
+                     a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status, a.m, k);
   hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
                      a.row_w, a.alpha, a.alpha_k, k, a.C, rh, a.status);
   if (a.S2 > 1) {
@@ -401,16 +491,11 @@ static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, fl
     hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
                        zin, zout, a.x, a.lambda, a.status);
   }
-  const int32_t* tn = (k + 1 < a.K) ? tk + a.eta : tk;
-  hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, tn, (k + 1 < a.K) ? a.eta : 0, a.m, a.status,
-                     k + 1);
 }
 
 hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckpt, int64_t ckpt_every) {
   const size_t total = (size_t)a.n * a.R;
   hipLaunchKernelGGL(init_multirhs, dim3(1024), dim3(256), 0, stream, a.x_star, a.x, total, a.lambda, a.warm);
-  if (a.K > 0)
-    hipLaunchKernelGGL(step_check, dim3(1), dim3(1024), 0, stream, a.idx, a.eta, a.m, a.status, (int64_t)0);
   for (int64_t k = 0; k < a.K; ++k) {
     if (ckpt && k % ckpt_every == 0) {
       hipError_t e = hipMemcpyAsync(ckpt + (size_t)(k / ckpt_every) * total, a.x_star, total * sizeof(float),
@@ -419,7 +504,305 @@ hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckp
     }
     multirhs_step(a, k, a.x_star, a.x_star, nullptr, stream);
   }
+  hipLaunchKernelGGL(steps_done, dim3(1), dim3(64), 0, stream, a.status, a.K);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent multi-RHS forward: all K steps in one cooperative launch.
+//
+// A step is four phases of work items, the same products as the step kernels above:
+//   Y items (row tile t, column tile r, split s):   Y_s[t, r] = A_tau[t, K_s] X[K_s, r]
+//   C items (row tile t, column tile r, 16 rows q): C[t, r] = (alpha_k/eta)(sum_s Y_s[t, r] - B_tau) / ||a||^2
+//   U items (n tile j, column tile r, row split s2): A_tau^T C over the split's rows; with one
+//           split it updates X*[j, r] and X[j, r] = S_lambda(X*) in its epilogue, else it writes
+//           its partial and a V item (j, r) adds the S2 partials in order and updates.
+// Items depend on earlier items only through cumulative per-tile counters (agent-scope atomics
+// that only grow): a Y item of step k waits until every X tile of its split has been updated k
+// times, a C item until its tile's S partials of step k are in, a U item until the C tiles of its
+// column are, a V item until its S2 partials are. Every workgroup walks its items (item i of a
+// phase belongs to workgroup i mod G) in one global order -- the phases of step 0 in turn, then
+// those of step 1, ... -- which is also the dependency order, so the earliest unfinished item
+// always has its inputs and the grid cannot deadlock (all workgroups are resident: cooperative
+// launch). Tiles that cross workgroups (Y partials, C, X, row-split partials) are written with
+// device-coherent stores (sc1: through the XCD's own L2) and read with device-coherent loads;
+// a producer waits for its stores to complete before it bumps the counter, so a consumer that sees
+// the count sees the data, without the L2 write-back a release fence would cost. X* stays with the
+// workgroup that owns its tile (the same one every step). Each wait is bounded and ends at once
+// when a fault has been recorded; a fault stops every workgroup within the step it occurs in.
+// ---------------------------------------------------------------------------
+
+
+// One item of each phase per call; see the block comment above. grid = G co-resident workgroups.
+__global__ __launch_bounds__(NTH) void multirhs_persistent(MultiRhsArgs a, MrpWork w, float* ckpt,
+                                                           int64_t ckpt_every) {
+  __shared__ __align__(16) float L0[BM * LDP];   // Y phase: A tile (pitch LDA); U phase: A^T tile (pitch LDP)
+  __shared__ __align__(16) float L1[SK][LDP];    // B operand tile of either phase
+  __shared__ int taus[kMaxTauLds];
+  __shared__ int flag;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int G = gridDim.x, me = blockIdx.x;
+  const int gt = w.gt, gr = w.gr, gn = w.gn, S = w.S, S2 = a.S2;
+  const int64_t kspan = w.kspan;
+  const int jpers = (int)(kspan / BM);           // n tiles per split (kspan is a multiple of 64)
+  const size_t total = (size_t)a.eta_pad * a.R;
+  const int lr = tid >> 4, lc = (tid & 15) * 4;
+  int* status = a.status;
+  const int nY = gt * gr * S, nC = gt * gr * kCq, nU = gn * gr * S2, nV = S2 > 1 ? gn * gr : 0;
+
+  for (int64_t k = 0; k < a.K; ++k) {
+    const int32_t* tk = a.idx + k * (int64_t)a.eta;
+    // ---- Y items: partial products of R_tau = A_tau X over the split's columns
+    for (int i = me; i < nY; i += G) {
+      const int tt = i % gt, rr = (i / gt) % gr, sp = i / (gt * gr);
+      const int64_t j_begin = (int64_t)sp * kspan;
+      int64_t j_end = j_begin + kspan;
+      if (j_end > a.n) j_end = a.n;
+      const int njs = (int)((j_end - j_begin + BM - 1) / BM);
+      if (!await(&w.xcnt[sp * gr + rr], (unsigned)(k * njs), status, &flag)) return;
+      const int t0 = tt * BM, r0 = rr * BN;
+      const float* arow[4];
+      bool aok[4];
+      int bad = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + lr + 16 * q;
+        aok[q] = t < a.eta;
+        int row = aok[q] ? tk[t] : 0;
+        if (row < 0 || (int64_t)row >= a.m) { bad = 1; row = 0; }
+        arow[q] = a.A + (int64_t)row * a.ld;
+      }
+      if (bad) fault(status, ST_INDEX, k);
+      const bool rok = r0 + lc < a.R;
+      auto load = [&](int64_t jb, Stage& st) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t c = jb + lc;
+          st.a[q] = (aok[q] && c < j_end) ? *reinterpret_cast<const float4*>(arow[q] + c)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+          const int64_t jj = jb + lr + 16 * q;
+          st.b[q] = (jj < j_end && rok) ? ld_dev4(a.x + jj * a.R + r0 + lc) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      };
+      f4 acc[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f4{0.f, 0.f, 0.f, 0.f};
+      Stage st;
+      load(j_begin, st);
+      for (int64_t jb = j_begin; jb < j_end; jb += SK) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int mm = lr + 16 * q;
+          *reinterpret_cast<float4*>(&L0[mm * LDA + lc]) = st.a[q];
+          *reinterpret_cast<float4*>(&L1[mm][lc]) = st.b[q];
+        }
+        __syncthreads();
+        if (jb + SK < j_end) load(jb + SK, st);
+        mma_stage_t<true>(L0, L1, wm, wn, lane, acc);
+      }
+      float* Ys = a.Y + (size_t)sp * total;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int t = t0 + wm * 32 + u * 16 + 4 * (lane >> 4) + e;
+            const int r = r0 + wn * 32 + v * 16 + (lane & 15);
+            if (r < a.R) st_dev1(Ys + (size_t)t * a.R + r, acc[u][v][e]);
+          }
+      publish(&w.ycnt[tt * gr + rr]);
+    }
+    // ---- C items: fixed-order sum of the S partials, coefficients
+    for (int i = me; i < nC; i += G) {
+      const int q = i % kCq, tt = (i / kCq) % gt, rr = i / (kCq * gt);
+      if (!await(&w.ycnt[tt * gr + rr], (unsigned)((k + 1) * S), status, &flag)) return;
+      const float ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
+      const float scale = ak / (float)a.eta;
+      const int t = tt * BM + q * 16 + (tid >> 4), r = rr * BN + lc;
+      if (r < a.R) {
+        const size_t e = (size_t)t * a.R + r;
+        // s ascending, eight partial loads issued before their adds (the step kernels' order)
+        float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+        int sp = 0;
+        for (; sp + 8 <= S; sp += 8) {
+          float4 v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = ld_dev4(a.Y + (size_t)(sp + u) * total + e);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            y.x += v[u].x;
+            y.y += v[u].y;
+            y.z += v[u].z;
+            y.w += v[u].w;
+          }
+        }
+        for (; sp < S; ++sp) {
+          const float4 v = ld_dev4(a.Y + (size_t)sp * total + e);
+          y.x += v.x;
+          y.y += v.y;
+          y.z += v.z;
+          y.w += v.w;
+        }
+        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t < a.eta) {
+          const int row = tk[t];
+          if (row >= 0 && (int64_t)row < a.m) {
+            const float rn = weighted_rn(a.r2, a.row_w, row);
+            if (rn == 0.f) fault(status, ST_ZERO_ROW, k);
+            const float4 bb = *reinterpret_cast<const float4*>(a.B + (int64_t)row * a.R + r);
+            c = make_float4(scale * (y.x - bb.x) / rn, scale * (y.y - bb.y) / rn, scale * (y.z - bb.z) / rn,
+                            scale * (y.w - bb.w) / rn);
+            if (!isfinite(c.x) || !isfinite(c.y) || !isfinite(c.z) || !isfinite(c.w)) fault(status, ST_NONFINITE, k);
+          }
+        }
+        st_dev4(a.C + e, c);
+      }
+      publish(&w.ccnt[rr]);
+    }
+    // ---- U items: A_tau^T C over a row split; with one split, the update of X*, X
+    for (int i = me; i < nU; i += G) {
+      const int jt = i % gn, rr = (i / gn) % gr, s2 = i / (gn * gr);
+      if (!await(&w.ccnt[rr], (unsigned)((k + 1) * gt * kCq), status, &flag)) return;
+      const int64_t j0 = (int64_t)jt * BM;
+      const int r0 = rr * BN;
+      const int tb0 = (int)((int64_t)s2 * a.eta / S2), tb1 = (int)((int64_t)(s2 + 1) * a.eta / S2);
+      stage_tau(tk + tb0, tb1 - tb0, taus);
+      __syncthreads();
+      const bool colok = j0 + lc < a.n, rok = r0 + lc < a.R;
+      const int etaS = tb1 - tb0;
+      auto load = [&](int tb, Stage& st) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int t = tb + lr + 16 * q;
+          const bool ok = t < etaS;
+          const int row = ok ? taus[t] : 0;
+          const bool rowok = row >= 0 && (int64_t)row < a.m;
+          st.a[q] = (ok && colok && rowok) ? *reinterpret_cast<const float4*>(a.A + (int64_t)row * a.ld + j0 + lc)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+          st.b[q] = (ok && rok) ? ld_dev4(a.C + (size_t)(tb0 + t) * a.R + r0 + lc) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      };
+      f4 acc[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f4{0.f, 0.f, 0.f, 0.f};
+      Stage st;
+      load(0, st);
+      float(*As)[LDP] = reinterpret_cast<float(*)[LDP]>(L0);
+      for (int tb = 0; tb < etaS; tb += SK) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          *reinterpret_cast<float4*>(&As[lr + 16 * q][lc]) = st.a[q];
+          *reinterpret_cast<float4*>(&L1[lr + 16 * q][lc]) = st.b[q];
+        }
+        __syncthreads();
+        if (tb + SK < etaS) load(tb + SK, st);
+        mma_stage(As, L1, wm, wn, lane, acc);
+      }
+      if (faulted(status, &flag)) return;  // no update from a bad step
+      const bool save = ckpt && k % ckpt_every == 0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t jj = j0 + wm * 32 + u * 16 + 4 * (lane >> 4) + e;
+            const int r = r0 + wn * 32 + v * 16 + (lane & 15);
+            if (jj < a.n && r < a.R) {
+              const size_t o = (size_t)jj * a.R + r;
+              if (S2 == 1) {
+                const float zo = a.x_star[o];
+                if (save) ckpt[(size_t)(k / ckpt_every) * a.n * a.R + o] = zo;
+                const float z = zo - acc[u][v][e];
+                a.x_star[o] = z;
+                st_dev1(a.x + o, shrink(z, a.lambda));
+              } else {
+                st_dev1(a.Wp + (size_t)s2 * a.n * a.R + o, acc[u][v][e]);
+              }
+            }
+          }
+      if (S2 == 1) {
+        publish(&w.xcnt[(int)(j0 / kspan) * gr + rr]);
+      } else {
+        publish(&w.wcnt[jt * gr + rr]);
+      }
+    }
+    // ---- V items: fixed-order sum of the row-split partials, update of X*, X
+    for (int i = me; i < nV; i += G) {
+      const int jt = i % gn, rr = i / gn;
+      if (!await(&w.wcnt[jt * gr + rr], (unsigned)((k + 1) * S2), status, &flag)) return;
+      if (faulted(status, &flag)) return;
+      const int64_t j0 = (int64_t)jt * BM;
+      const int r0 = rr * BN;
+      const bool save = ckpt && k % ckpt_every == 0;
+      for (int e4 = tid; e4 < BM * BN / 4; e4 += NTH) {
+        const int64_t jj = j0 + e4 / (BN / 4);
+        const int r = r0 + (e4 % (BN / 4)) * 4;
+        if (jj >= a.n || r >= a.R) continue;
+        const size_t o = (size_t)jj * a.R + r;
+        float4 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < S2) v[q] = ld_dev4(a.Wp + (size_t)q * a.n * a.R + o);
+        float4 tsum = v[0];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) {
+          if (q < S2) {
+            tsum.x += v[q].x;
+            tsum.y += v[q].y;
+            tsum.z += v[q].z;
+            tsum.w += v[q].w;
+          }
+        }
+        float4 z = *reinterpret_cast<const float4*>(a.x_star + o);
+        if (save) *reinterpret_cast<float4*>(ckpt + (size_t)(k / ckpt_every) * a.n * a.R + o) = z;
+        z.x -= tsum.x;
+        z.y -= tsum.y;
+        z.z -= tsum.z;
+        z.w -= tsum.w;
+        *reinterpret_cast<float4*>(a.x_star + o) = z;
+        st_dev4(a.x + o, make_float4(shrink(z.x, a.lambda), shrink(z.y, a.lambda), shrink(z.z, a.lambda),
+                                     shrink(z.w, a.lambda)));
+      }
+      publish(&w.xcnt[(int)(j0 / kspan) * gr + rr]);
+    }
+  }
+}
+
+// status[1] = K until a fault lowers it to the step it occurred in
+__global__ void mrp_status_init(int* status, int64_t K) {
+  if (threadIdx.x == 0) status[1] = (int)K;
+}
+
+int multirhs_persistent_grid() {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&multirhs_persistent, NTH, 0) != hipSuccess)
+    return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_multirhs_persistent(const MultiRhsArgs& a, const MrpWork& w, int grid, hipStream_t stream,
+                                      float* ckpt, int64_t ckpt_every) {
+  const size_t total = (size_t)a.n * a.R;
+  hipLaunchKernelGGL(init_multirhs, dim3(1024), dim3(256), 0, stream, a.x_star, a.x, total, a.lambda, a.warm);
+  hipLaunchKernelGGL(mrp_status_init, dim3(1), dim3(64), 0, stream, a.status, a.K);
+  if (a.K == 0) return hipGetLastError();
+  MultiRhsArgs aa = a;
+  MrpWork ww = w;
+  float* ck = ckpt;
+  int64_t ce = ckpt_every > 0 ? ckpt_every : 1;
+  void* args[] = {&aa, &ww, &ck, &ce};
+  return hipLaunchCooperativeKernel((const void*)&multirhs_persistent, dim3(grid), dim3(NTH), args, 0, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -758,7 +1141,7 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
       const int64_t j = k - k0;
       const int32_t* tk = a.idx + k * (int64_t)a.eta;
       hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, d.zbar,
-                         a.R, a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status);
+                         a.R, a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status, (int64_t)0, k);
       hipLaunchKernelGGL(adj_coef, dim3(kAdjCoefBlocks), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta,
                          d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
       hipLaunchKernelGGL(adj_bbar, dim3((unsigned)(((size_t)a.eta * a.R + 255) / 256)), dim3(256),

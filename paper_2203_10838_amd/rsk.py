@@ -125,18 +125,18 @@ def plan_dense(A: torch.Tensor, *, eta: int, K: int = 1, grid: int = 0, kernel: 
     return dict(zip(PLAN_FIELDS, [int(v) for v in out]))
 
 
-def plan_multirhs(A: torch.Tensor, R: int, *, eta: int, K: int = 1) -> dict:
+def plan_multirhs(A: torch.Tensor, R: int, *, eta: int, K: int = 1, kernel: int = 0) -> dict:
     """The split rsk_avg_solve_multirhs would use (nothing is queued): S column splits of A_tau X
     (and the columns per split), S2 row splits of A_tau^T C, eta padded to a multiple of 64."""
     d = dense_desc(A)
     dummy = torch.empty(2, dtype=torch.int32, device=A.device)
     params = _abi.RskParams(0.0, int(eta), 1.0, None, int(K), dummy.data_ptr(), 0, A.data_ptr(), 0, None, 0, 0.0,
-                            None, None, dummy.data_ptr(), 0, 0, None)
-    out = (ctypes.c_int32 * 4)()
+                            None, None, dummy.data_ptr(), 0, int(kernel), None)
+    out = (ctypes.c_int32 * 5)()
     st = _lib().rsk_plan_multirhs(ctypes.byref(d), int(R), ctypes.byref(params), out)
     if st:
         raise RskError(st, "rsk_plan_multirhs")
-    return dict(zip(("S", "kspan", "S2", "eta_pad"), [int(v) for v in out]))
+    return dict(zip(("S", "kspan", "S2", "eta_pad", "kernel"), [int(v) for v in out]))
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
@@ -292,8 +292,10 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
                    rownorm2_t: Optional[torch.Tensor] = None, X_star: Optional[torch.Tensor] = None,
                    warm_start: bool = False, workspace: Optional[torch.Tensor] = None,
                    ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
-                   row_w: Optional[torch.Tensor] = None, check: bool = True) -> SolveResult:
+                   row_w: Optional[torch.Tensor] = None, kernel: int = 0, check: bool = True) -> SolveResult:
     """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major).
+
+    ``kernel``: 1 the step kernels, 2 one persistent launch for all K steps, 0 the library's choice.
 
     With ``ckpt`` (ceil(K/ckpt_every) x n x R float32) the x* checkpoints the
     adjoint recomputes from are written as well.
@@ -315,7 +317,7 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
     status_dev = torch.empty(2, dtype=torch.int32, device=A.device)
     params = make_params(lam=lam, eta=eta, alpha=alpha, K=K, index_stream=index_stream, rownorm2_t=rownorm2_t,
                          status_dev=status_dev, stream_offset=stream_offset, alpha_k=alpha_k, warm_start=warm_start,
-                         dtype=dt, row_w=row_w)
+                         dtype=dt, row_w=row_w, kernel=kernel)
     if row_w is not None:
         _dev(row_w, "row_w", dt, m)
     d = dense_desc(A)

@@ -74,14 +74,15 @@ def test_tuned_multirhs_split_matches_oracle(cuda, tmp_path):
     A, B, ix = to_dev(s["A"], cuda), to_dev(s["B"], cuda), to_dev(idx, cuda)
     alpha = alpha_star(s["A"], eta)
     out = autotune.tune_multirhs(A, B, eta=eta, lam=lam, alpha=alpha, index_stream=ix, steps=3, reps=2,
-                                 candidates=[(1, 1), (2, 2), (4, 1), (4, 2)])
-    S, S2 = out["choice"]
-    assert rsk.plan_multirhs(A, R, eta=eta)["S"] == S and rsk.plan_multirhs(A, R, eta=eta)["S2"] == S2
+                                 candidates=[(1, 1, 1), (2, 2, 1), (4, 1, 1), (4, 2, 2), (2, 1, 2)])
+    S, S2, kernel = out["choice"]
+    plan = rsk.plan_multirhs(A, R, eta=eta)
+    assert plan["S2"] == S2 and plan["kernel"] == kernel
     tuned = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=ix)
-    # the same split set by hand: the explicit choice
+    # the same split and kernel set by hand: the explicit choice
     autotune.clear()
     autotune.set_entry(_abi.RSK_TUNE_MULTIRHS, _abi.RSK_F32, m=m, n=n, eta=eta, R=R, v0=S, v1=S2)
-    explicit = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=ix)
+    explicit = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=ix, kernel=kernel)
     assert torch.equal(tuned.x_star, explicit.x_star)
     ref = oracle.rska_multirhs(s["A"], s["B"], lam, eta, alpha, K, idx)
     check_columns(tuned.x_star, tuned.x, ref, lam, 1e-4, min_support=R)
@@ -90,7 +91,7 @@ def test_tuned_multirhs_split_matches_oracle(cuda, tmp_path):
     autotune.save(f)
     autotune.clear()
     autotune.load(f)
-    assert rsk.plan_multirhs(A, R, eta=eta)["S"] == S
+    assert rsk.plan_multirhs(A, R, eta=eta) == plan
 
 
 def test_tuned_batched_classes_match_oracle(cuda):

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2203_10838_amd import inputs, params
-from parity import check_columns
+from parity import alpha_star, check_columns
 
 pytestmark = pytest.mark.gpu
 
@@ -97,3 +97,65 @@ def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib):
             for q in range(len(cols))]
     ref = {"z": np.stack([r_["z"] for r_ in refs], 1), "x": np.stack([r_["x"] for r_ in refs], 1)}
     check_columns(res.x_star[:, cols], res.x[:, cols], ref, lam, 1e-4, min_support=40)
+
+
+@pytest.mark.parametrize("m,n,R,eta,K", [(3000, 1000, 64, 100, 40), (2000, 516, 12, 37, 60), (5000, 2048, 128, 300, 15),
+                                         (300, 64, 4, 5, 200), (1500, 704, 8, 1000, 10)])
+def test_multirhs_persistent_matches_oracle_and_step_kernels(cuda, rsk_lib, m, n, R, eta, K):
+    """One persistent launch for all K steps (kernel 2): every column against the single-RHS oracle,
+    and bitwise the step kernels' result wherever both split the n columns alike."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    sysd = inputs.multirhs_system(m, n, R, max(1, n // 20), seed=m + R + 1)
+    A, B = _t(sysd["A"], cuda), _t(sysd["B"], cuda)
+    idx = inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), K, eta, 9 + m)
+    alpha = alpha_star(sysd["A"], eta)
+    p1 = rsk.plan_multirhs(A, R, eta=eta, K=K, kernel=1)
+    p2 = rsk.plan_multirhs(A, R, eta=eta, K=K, kernel=2)
+    assert p2["kernel"] == 2 and p2["kspan"] % 64 == 0 and p2["S2"] == p1["S2"]
+    res2 = rsk.solve_multirhs(A, B, lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=2)
+    assert res2.status == 0 and res2.k_done == K
+    ref = oracle.rska_multirhs(sysd["A"], sysd["B"], 0.5, eta, alpha, K, idx)
+    check_columns(res2.x_star, res2.x, ref, 0.5, 1e-4, min_support=R)
+    again = rsk.solve_multirhs(A, B, lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=2)
+    assert torch.equal(again.x_star, res2.x_star)
+    if p1["kspan"] == p2["kspan"]:
+        res1 = rsk.solve_multirhs(A, B, lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=1)
+        assert torch.equal(res1.x_star, res2.x_star) and torch.equal(res1.x, res2.x)
+
+
+def test_multirhs_persistent_checkpoints_resume_and_faults(cuda, rsk_lib):
+    import torch
+    from paper_2203_10838_amd import rsk
+    sysd = inputs.multirhs_system(2400, 768, 16, 30, seed=71)
+    A, B = _t(sysd["A"], cuda), _t(sysd["B"], cuda)
+    K, eta = 24, 96
+    idx = inputs.index_stream(inputs.row_sampling_weights(sysd["A"]), K, eta, 72)
+    ak = np.linspace(20.0, 60.0, K).astype(np.float32)
+    kw = dict(lam=0.4, eta=eta, alpha=1.0, index_stream=_t(idx, cuda), alpha_k=_t(ak, cuda))
+    ck1 = torch.full((3, 768, 16), float("nan"), device=cuda)
+    ck2 = torch.full((3, 768, 16), float("nan"), device=cuda)
+    r1 = rsk.solve_multirhs(A, B, K=K, ckpt=ck1, ckpt_every=10, kernel=1, **kw)
+    r2 = rsk.solve_multirhs(A, B, K=K, ckpt=ck2, ckpt_every=10, kernel=2, **kw)
+    ref = oracle.rska_multirhs(sysd["A"], sysd["B"], 0.4, eta, 1.0, K, idx, alpha_k=ak.astype(np.float64))
+    check_columns(r2.x_star, r2.x, ref, 0.4, 1e-4, min_support=16)
+    same_split = rsk.plan_multirhs(A, 16, eta=eta, kernel=1)["kspan"] == rsk.plan_multirhs(A, 16, eta=eta,
+                                                                                          kernel=2)["kspan"]
+    if same_split:
+        assert torch.equal(ck1, ck2) and torch.equal(r1.x_star, r2.x_star)
+    assert torch.equal(ck2[0], torch.zeros_like(ck2[0]))
+    # resume: 10 + 14 steps from the checkpoint-free x* equal 24 steps
+    h = rsk.solve_multirhs(A, B, K=10, kernel=2, **kw)
+    kw2 = dict(kw, alpha_k=_t(ak[10:], cuda))
+    rest = rsk.solve_multirhs(A, B, K=K - 10, kernel=2, X_star=h.x_star.clone(), warm_start=True,
+                              stream_offset=10 * eta, **kw2)
+    assert torch.equal(rest.x_star, r2.x_star)
+    # an index out of range at step 5 stops the launch there; a blow-up is reported
+    bad = idx.copy()
+    bad[5 * eta + 3] = 2400
+    r = rsk.solve_multirhs(A, B, lam=0.4, eta=eta, alpha=8.0, K=K, index_stream=_t(bad, cuda), kernel=2, check=False)
+    torch.cuda.synchronize()
+    assert r.status_dev.cpu().tolist() == [6, 5]
+    with pytest.raises(rsk.RskError) as e:
+        rsk.solve_multirhs(A, B, lam=0.4, eta=eta, alpha=1e30, K=K, index_stream=_t(idx, cuda), kernel=2)
+    assert e.value.name == "RSK_ERR_NONFINITE"
