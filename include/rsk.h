@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RSK_ABI_VERSION 3
+#define RSK_ABI_VERSION 4
 
 typedef enum { RSK_F32 = 0, RSK_F64 = 1 } rsk_dtype;
 
@@ -91,7 +91,9 @@ typedef struct {
   int64_t check_every;         /* > 0 with x_ref: every check_every steps record ||x - x_ref||/||x_ref|| */
   double tol;                  /* with the monitor: stop early once the relative error is <= tol (0 = never) */
   double *err_hist;            /* nullable device array, K/check_every entries (double) */
-  void *y_out;                 /* nullable device array (m, dtype of A), in/out: y[tau_t] -= c_t, so x* = A^T y */
+  void *y_out;                 /* nullable device array (m, dtype of A), in/out: y[tau_t] -= c_t, so x* = A^T y.
+                                  Summed with floating-point atomics: where a row is drawn more than once in a
+                                  step, y is reproducible to rounding only (x* and x stay bitwise reproducible) */
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register
@@ -217,7 +219,8 @@ int32_t rsk_spectral_norm2_dense(const rsk_dense *A, int64_t iters, void *v, dou
  * mean what they mean there. block_norm2: nullable device double[K],
  * ||A_tau_k||_2^2 of every step. Device status: RSK_ERR_INDEX_RANGE (stream
  * index outside [0, m)), RSK_ERR_ZERO_ROW (a block of zero rows: that step
- * leaves x* unchanged), RSK_ERR_NONFINITE. Bitwise reproducible.
+ * leaves x* unchanged), RSK_ERR_NONFINITE. x* and x are bitwise reproducible
+ * (y_out: see rsk_params).
  */
 int32_t rsk_workspace_size_bsk_dense(const rsk_dense *A, const rsk_params *p, size_t *bytes);
 int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
@@ -297,7 +300,8 @@ int32_t rsk_workspace_size_csr(const rsk_csr *A, const rsk_params *p, size_t *by
  * even number of workgroups). 0 = the
  * library's choice: for float32, 3 for 88 <= eta <= 800, else 2, where the
  * register tile applies; else 1. Kernels 2 and 3 sum in
- * different orders (results agree to rounding); each is bitwise reproducible.
+ * different orders (results agree to rounding); each gives bitwise
+ * reproducible x* and x (y_out: see rsk_params).
  * A kernel that does not apply to the shape returns RSK_ERR_UNSUPPORTED.
  */
 int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,
@@ -327,11 +331,14 @@ int32_t rsk_avg_solve_dense_noalloc(const rsk_dense *A, const void *b, const rsk
 /*
  * The launch rsk_avg_solve_dense would make for A and p, without making it
  * (nothing is queued; A->val is only inspected for its alignment). out:
- * host int32[8] = { kernel (1 general, 2 register tile, 3 register tile over
+ * host int32[9] = { kernel (1 general, 2 register tile, 3 register tile over
  * two row groups), workgroups G, threads per workgroup, row passes and float4
  * chunks per lane of the register tile (0 for the general kernel), row groups,
- * exchange hops per step (1 or 2), elements per vector load }. Returns what
- * rsk_avg_solve_dense would return for an unsupported shape or bad argument.
+ * exchange hops per step (1 or 2), elements per vector load, row tile of the
+ * general kernel (0 rows read from HBM twice a step, 1 one LDS tile, 2 two LDS
+ * tiles with the next step's rows loaded during the step; 0 for the register
+ * tile) }. Returns what rsk_avg_solve_dense would return for an unsupported
+ * shape or bad argument.
  */
 int32_t rsk_plan_dense(const rsk_dense *A, const rsk_params *p, int32_t *out);
 
@@ -343,8 +350,8 @@ int32_t rsk_plan_dense(const rsk_dense *A, const rsk_params *p, int32_t *out);
  * eta/8 up to the CU count, three grid barriers per step), 0 = 2 when
  * eta >= 4, else 1. Columns hit by several sampled rows of a step are summed
  * in int64 fixed point with a per-step power-of-two quantum (2^-41 of the
- * step's largest contribution), so results are bitwise reproducible for a
- * given kernel. eta <= 4096.
+ * step's largest contribution), so x* and x are bitwise reproducible for a
+ * given kernel (y_out: see rsk_params). eta <= 4096.
  * Workspace: n + 1 int64 accumulators plus the grid kernel's barrier and
  * monitor words (rsk_workspace_size_csr), zeroed by the call.
  * A column index outside [0, n) in a sampled row is RSK_ERR_INDEX_RANGE.

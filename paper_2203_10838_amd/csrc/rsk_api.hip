@@ -99,6 +99,8 @@ int32_t tune_load_locked(const char* path) {
 
 constexpr int kMaxEtaDense = 16384;
 constexpr size_t kTileCacheBytes = 96 * 1024;
+// both tiles of the pipelined row tile (the next step's rows loaded during the step)
+constexpr size_t kPipeTileBytes = 128 * 1024;
 // General-kernel grid for grid = 0. A step is a chain of dependent round trips, so below a few MB
 // it is bound by latency, not bytes: one workgroup (no exchange) while the step and its rows are
 // small, else about 4 KB of rows per workgroup on 16..128 workgroups, the whole chip for big steps.
@@ -281,10 +283,19 @@ int32_t plan_dense_fixed(const rsk_dense* A, const rsk_params* p, DensePlan* pl)
     pl->G = G;
     pl->wq_max = (int)((pl->nchunks + G - 1) / G);
     pl->lpr = next_pow2(pl->wq_max) < 64 ? next_pow2(pl->wq_max) : 64;
-    pl->tile_cache = ((size_t)p->eta * pl->wq_max * pl->vec * s) <= kTileCacheBytes;
+    const size_t tile_bytes = (size_t)p->eta * pl->wq_max * pl->vec * s;
+    pl->tile_cache = tile_bytes <= kTileCacheBytes;
     pl->two_hop = ((int64_t)G * p->eta * pl->W) > kOneHopWords;
     size_t lds = 0;
     const int64_t xr = pl->two_hop ? 0 : rsk::onehop_lds_elems(G, p->eta);
+    // the pipelined tile (next step's rows loaded during the step) for one workgroup, where two
+    // tiles fit: with an exchange its step is no faster (measured on 1000x500 float64, eta = 10,
+    // 16 workgroups: 8.4 against 6.9 us), as the exchange, not the row loads, sets the pace
+    if (G == 1 && rsk::dense_pipe_ok(s, pl->vec, p->eta, pl->wq_max) && 2 * tile_bytes <= kPipeTileBytes &&
+        rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, 2, xr, &lds) >= G) {
+      pl->tile_cache = 2;
+      break;
+    }
     int maxg = rsk::dense_max_grid<T>(pl->vec, p->eta, pl->wq_max, pl->tile_cache, xr, &lds);
     if (maxg == 0 && pl->tile_cache) {
       pl->tile_cache = 0;
@@ -1199,6 +1210,7 @@ int32_t rsk_plan_dense(const rsk_dense* A, const rsk_params* p, int32_t* out) {
   out[5] = pl.rg;
   out[6] = pl.two_hop ? 2 : 1;
   out[7] = pl.vec;
+  out[8] = rt ? 0 : pl.tile_cache;
   return RSK_OK;
 }
 

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kPrepThreads) void batched_prep(const rsk_batch_ite
 }
 
 template <typename T, int VEC>
-__global__ __launch_bounds__(kDenseThreads) void rska_batched(const rsk_batch_item* __restrict__ items,
+__global__ __launch_bounds__(kDenseThreads, 2) void rska_batched(const rsk_batch_item* __restrict__ items,
                                                               const int32_t* __restrict__ order, int nsys,
                                                               const int64_t* __restrict__ ticket0,
                                                               const int64_t* __restrict__ woff, u64* queue,
@@ -162,7 +162,10 @@ __global__ __launch_bounds__(kDenseThreads) void rska_batched(const rsk_batch_it
     a.xM = a.xC + (size_t)it.eta * Words<T>::N;
     a.G = pl.G; a.two_hop = pl.two_hop; a.tile_cache = pl.tile_cache;
     a.nchunks = pl.nchunks; a.wq_max = pl.wq_max; a.lpr = pl.lpr;
-    dense_run<T, VEC, kDenseThreads>(a, rank, rank, smem);
+    if (a.tile_cache == 2 && dense_pipe_ok(sizeof(T), VEC, a.eta, a.wq_max))
+      dense_run<T, VEC, kDenseThreads, true>(a, rank, rank, smem);
+    else
+      dense_run<T, VEC, kDenseThreads, false>(a, rank, rank, smem);
   }
 }
 

@@ -256,7 +256,8 @@ template hipError_t launch_csr<double>(CsrArgs<double>&, hipStream_t);
 //      (integer adds commute: the totals do not depend on atomic order);  barrier
 //   C. every touched column applied once, by the lane that swaps its nonzero
 //      total out of the accumulator: x*_j -= total q, x_j = S_lambda(x*_j); barrier
-// The result is bitwise reproducible (the dots use a fixed lane order).
+// x* and x are bitwise reproducible (the dots use a fixed lane order); the optional dual y
+// is summed with float atomics, reproducible to rounding where a row repeats within a step.
 // ---------------------------------------------------------------------------
 
 namespace {

@@ -19,9 +19,12 @@
 namespace rsk {
 
 template <typename T, int VEC, int NT>
-__global__ __launch_bounds__(NT) void rska_dense_persistent(DenseArgs<T> a) {
+__global__ __launch_bounds__(NT, 2) void rska_dense_persistent(DenseArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  dense_run<T, VEC, NT>(a, blockIdx.x, xcd_slice(blockIdx.x, a.G), smem);
+  if (a.tile_cache == 2 && dense_pipe_ok(sizeof(T), VEC, a.eta, a.wq_max))
+    dense_run<T, VEC, NT, true>(a, blockIdx.x, xcd_slice(blockIdx.x, a.G), smem);
+  else
+    dense_run<T, VEC, NT, false>(a, blockIdx.x, xcd_slice(blockIdx.x, a.G), smem);
 }
 
 template <typename T>
@@ -66,12 +69,13 @@ static void* dense_kernel_ptr() {
 
 template <typename T>
 static void* dense_kernel_for(int vec) {
-  if (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4) {
     if (vec == 4) return dense_kernel_ptr<T, 4>();
     return dense_kernel_ptr<T, 1>();
+  } else {
+    if (vec == 2) return dense_kernel_ptr<T, 2>();
+    return dense_kernel_ptr<T, 1>();
   }
-  if (vec == 2) return dense_kernel_ptr<T, 2>();
-  return dense_kernel_ptr<T, 1>();
 }
 
 template <typename T>

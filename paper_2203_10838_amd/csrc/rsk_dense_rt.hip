@@ -30,7 +30,8 @@
 //  * Each pass publishes its partial dots as soon as its own loads have
 //    landed; the next step's indices, and b and ||a||^2 of the rows this
 //    workgroup reduces, are fetched a step ahead.
-//  * Summation orders are fixed, so results are bitwise reproducible.
+//  * Summation orders are fixed, so x* and x are bitwise reproducible (the
+//    optional dual y is summed with atomics: reproducible to rounding).
 #include "rsk_device.hpp"
 #include "rsk_kernels.hpp"
 

@@ -12,12 +12,21 @@ namespace rsk {
 // that holds element col; the elements past n are discarded by a select.
 template <typename T, int VEC>
 __device__ __forceinline__ Vec<T, VEC> load_vec(const T* __restrict__ rowp, int64_t col, int64_t n) {
-  Vec<T, VEC> v = *reinterpret_cast<const Vec<T, VEC>*>(rowp + col);
+  Vec<T, VEC> v;
+  load_global_vec<T, VEC>(rowp + col, v.v);
   if constexpr (VEC > 1) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) v.v[e] = col + e < n ? v.v[e] : T(0);
   }
   return v;
+}
+
+// Chunk v of a row read from LDS, columns [col, col+VEC) relative to the
+// slice: the elements at or past nrel (past n) set to zero, as load_vec does.
+template <typename T, int VEC>
+__device__ __forceinline__ void mask_tail(Vec<T, VEC>& v, int64_t col, int64_t nrel) {
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) v.v[e] = col + e < nrel ? v.v[e] : T(0);
 }
 
 // One-hop gather: the n_slots tagged partials of a step (slot s = q*eta + t)
@@ -174,8 +183,17 @@ __device__ __forceinline__ void wait_rows(const u64* xP, int eta, int q, bool qo
 // keeps many of them in flight: a lane loads the chunks of U rows before it
 // uses any, a wave polls the partials of UR rows at once, and the next step's
 // indices, b and ||a||^2 are fetched while the current step runs (into the
-// second of two LDS buffers). None of this changes any summation order.
-template <typename T, int VEC, int NT>
+// second of two LDS buffers). The row sample of every step is known in
+// advance (it does not depend on x), so with the pipelined tile (PIPE, for
+// a.tile_cache == 2) the next step's rows are loaded into registers while the
+// step runs on the LDS tile of its own rows, and written to the other tile at
+// its end: no HBM round trip is left on a step's critical path but the
+// exchange's. The indices are then fetched two steps ahead. None of this
+// changes any summation order: the pipelined tile gives the same bits as the
+// single one. PIPE is a template argument so that the other variant's
+// register loads never share a code path with it (the compiler would wait for
+// them, and with them for the prefetch, where the paths join).
+template <typename T, int VEC, int NT, bool PIPE>
 __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, const int slice, unsigned char* smem) {
   using V = Vec<T, VEC>;
   constexpr int NW = NT / 64;
@@ -201,11 +219,38 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
   int* orB = orA + 2;                                        // end of step: 4 bad index in the next step
   V* tile = reinterpret_cast<V*>(smem + L.tile);
   T* xr = reinterpret_cast<T*>(smem + L.xr);
+  constexpr bool pipe = PIPE && VEC * sizeof(T) == 16;
+  constexpr int PR = pipe_reg_chunks(sizeof(T));
+  const size_t tslots = (size_t)eta * a.wq_max;  // chunks of one pipelined tile
 
   const int64_t q0 = (int64_t)slice * a.nchunks / G, q1 = (int64_t)(slice + 1) * a.nchunks / G;
   const int wq = (int)(q1 - q0);
   const int64_t c0 = q0 * VEC;
   const int wcols = wq * VEC;
+  const bool ragged = c0 + wcols > a.n;  // the last chunk holds columns past n
+
+  // pipelined tile: chunk e = t*wq + q of row tsrc[t] of this slice, thread tid taking
+  // e = tid + p*NT (coalesced: consecutive threads read consecutive chunks of a row); whole
+  // 16-byte chunks, the columns past n masked where the tile is read. Every thread issues all
+  // PR loads, unconditionally, so that they leave back to back
+  auto load_tile = [&](const int* tsrc, V (&nv)[PR]) {
+    const int total = eta * wq;
+#pragma unroll
+    for (int p = 0; p < PR; ++p) {
+      // past the tile: its last chunk again (unused)
+      const int e = tid + p * NT < total ? tid + p * NT : total - 1;
+      const int t = e / wq, q = e - t * wq;
+      load_global_vec<T, VEC>(a.A + (int64_t)tsrc[t] * a.ld + c0 + (int64_t)q * VEC, nv[p].v);
+    }
+  };
+  auto store_tile = [&](V* dst, const V (&nv)[PR]) {
+    const int total = eta * wq;
+#pragma unroll
+    for (int p = 0; p < PR; ++p) {
+      const int e = tid + p * NT;
+      if (e < total) dst[e] = nv[p];
+    }
+  };
 
   // x*_0, x_0 = S_lambda(x*_0)
   for (int j = tid; j < wcols; j += NT) {
@@ -218,13 +263,23 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
   int row_err = 0;
   if (a.K > 0) {
     for (int t = tid; t < eta; t += NT) {
-      const int i = a.idx[t];
+      const int i = load_global(a.idx + t);
       const bool ok = i >= 0 && (int64_t)i < a.m;
       if (!ok) row_err = ST_INDEX;
       const int ic = ok ? i : 0;
       taub[t] = ic;
-      bqb[t] = a.b[ic];
+      bqb[t] = load_global(a.b + ic);
       rqb[t] = weighted_rn(a.r2, a.row_w, ic);
+    }
+  }
+  // pipelined: the indices of step 1 as well (its rows, b and ||a||^2 follow during step 0)
+  int row_err1 = 0;
+  if (pipe && a.K > 1) {
+    for (int t = tid; t < eta; t += NT) {
+      const int i = load_global(a.idx + eta + t);
+      const bool ok = i >= 0 && (int64_t)i < a.m;
+      if (!ok) row_err1 = ST_INDEX;
+      taub[eta + t] = ok ? i : 0;
     }
   }
 
@@ -237,12 +292,30 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
   // step 0's rows were fetched above; every workgroup checks all of them (this barrier also
   // orders the clearing of the flag words)
   int row_bad = __syncthreads_or(row_err);
+  int row_bad1 = pipe ? __syncthreads_or(row_err1) : 0;  // pipelined: the next step's verdict
+  if (pipe && a.K > 0 && !row_bad) {
+    V nv[PR];
+    load_tile(taub, nv);
+    store_tile(tile, nv);
+    __syncthreads();
+  }
 
   for (int64_t k = 0; k < a.K; ++k) {
     const unsigned tag = (unsigned)(k + 1);
     const T ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
     const int buf = (int)(k & 1);
-    const int* tau = taub + buf * eta;
+    const int* tau = taub + (pipe ? (int)(k % 3) : buf) * eta;
+    const V* tcur = tile + (size_t)buf * tslots;  // pipelined: this step's tile
+    // chunk q of the step's row t: from the tile (masked past n when pipelined) or from HBM
+    auto tile_at = [&](int t, int q) -> V {
+      if (pipe) {
+        V v = tcur[(size_t)t * wq + q];
+        if (ragged && q == wq - 1) mask_tail<T, VEC>(v, (int64_t)q * VEC, a.n - c0);
+        return v;
+      }
+      return a.tile_cache ? tile[(size_t)t * wq + q]
+                          : load_vec<T, VEC>(a.A + (int64_t)tau[t] * a.ld + c0, (int64_t)q * VEC, a.n - c0);
+    };
     const T* bq = bqb + buf * eta;
     const T* rq = rqb + buf * eta;
     // partials are double-buffered by step parity: with every workgroup
@@ -256,20 +329,74 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
     if (row_bad) { stop_code = ST_INDEX; break; }
     const bool has_next = k + 1 < a.K;
     const int32_t* tk1 = a.idx + (k + 1) * (int64_t)eta;
+    const bool has_next2 = k + 2 < a.K;
     int ni[PF];
     T nb[PF], nr[PF];
-    if (pf_regs && has_next) {
+    V nv[PR];  // pipelined: the next step's chunks of this slice
+    if (pipe) {
+      // the next step's rows, b and ||a||^2 (its indices were checked a step ago) and the raw
+      // indices of the step after it, all into registers: nothing waits for them before the
+      // step's end
+      // (every lane loads, the rows past eta as row eta-1: straight-line loads, which the
+      // compiler does not guard with waits for earlier ones)
+      if (has_next) {
+        const int* t1 = taub + (int)((k + 1) % 3) * eta;
+        load_tile(t1, nv);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          const int t = tid + p * NT < eta ? tid + p * NT : eta - 1;
+          nb[p] = load_global(a.b + t1[t]);
+          nr[p] = weighted_rn(a.r2, a.row_w, t1[t]);
+        }
+      }
+      if (has_next2) {
+        const int32_t* tk2 = a.idx + (k + 2) * (int64_t)eta;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) ni[p] = load_global(tk2 + (tid + p * NT < eta ? tid + p * NT : eta - 1));
+      }
+    } else if (pf_regs && has_next) {
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
         const int t = tid + p * NT;
-        ni[p] = t < eta ? tk1[t] : 0;
+        ni[p] = t < eta ? load_global(tk1 + t) : 0;
       }
     }
 
     // 2. partial dots over the own columns: every lane issues the loads of
     //    U rows x QU chunks before it uses any (rows past eta load a valid
     //    row and are discarded), so a batch costs one memory round trip
-    if (eta <= rstride) {
+    if (pipe) {
+      // the tile is in LDS: lane group rs of a wave takes U rows at once, its lpr lanes the
+      // chunks of each in ascending order (the order of the loads from HBM below)
+      for (int tb = wave * rpw; tb < eta; tb += rstride * U) {
+        T acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = T(0);
+        for (int q = cl; q < wq; q += lpr) {
+          V v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int t = tb + u * rstride + rs;
+            v[u] = tile_at(t < eta ? t : eta - 1, q);
+          }
+          const V xx = reinterpret_cast<const V*>(xv)[q];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (tb + u * rstride + rs < eta) {
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) acc[u] += v[u].v[e] * xx.v[e];
+            }
+        }
+        T sum[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) sum[u] = lane_sum(acc[u], lpr);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = tb + u * rstride + rs;
+          if (t < eta && cl == 0) cs[t] = sum[u];
+        }
+      }
+    } else if (eta <= rstride) {
       // at most one row per lane group: keep 8 chunks of that row in flight instead
       constexpr int QC = 8;
       const int t = wave * rpw + rs;
@@ -352,7 +479,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
 
     // 2b. b and ||a||^2 of the next step's rows (indices checked first)
     int next_err = 0;
-    if (pf_regs && has_next) {
+    if (!pipe && pf_regs && has_next) {
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
         const int t = tid + p * NT;
@@ -360,7 +487,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
           const bool ok = ni[p] >= 0 && (int64_t)ni[p] < a.m;
           if (!ok) next_err = ST_INDEX;
           ni[p] = ok ? ni[p] : 0;
-          nb[p] = a.b[ni[p]];
+          nb[p] = load_global(a.b + ni[p]);
           nr[p] = weighted_rn(a.r2, a.row_w, ni[p]);
         }
       }
@@ -437,6 +564,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
     const int fl = block_or(orA, (lerr ? 1 : 0) | (bad ? 2 : 0), k);
     if (fl) { stop_code = (fl & 1) ? ST_ABORTED : ST_NONFINITE; break; }
 
+    // the dual (x* = A^T y): float atomics, so a row drawn twice in a step adds in either order
     if (a.y && g == 0)
       for (int t = tid; t < eta; t += NT) atomicAdd(&a.y[tau[t]], -cs[t]);
 
@@ -454,8 +582,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
 #pragma unroll
           for (int u = 0; u < UB; ++u) {
             const int t = tb + u * nrg < eta ? tb + u * nrg : eta - 1;
-            v[u] = a.tile_cache ? tile[(size_t)t * wq + q]
-                                : load_vec<T, VEC>(a.A + (int64_t)tau[t] * a.ld + c0, (int64_t)q * VEC, a.n - c0);
+            v[u] = tile_at(t, q);
           }
 #pragma unroll
           for (int u = 0; u < UB; ++u) {
@@ -495,8 +622,7 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
 #pragma unroll
           for (int u = 0; u < UB; ++u) {
             const int t = tb + u < eta ? tb + u : eta - 1;
-            v[u] = a.tile_cache ? tile[(size_t)t * wq + q]
-                                : load_vec<T, VEC>(a.A + (int64_t)tau[t] * a.ld + c0, (int64_t)q * VEC, a.n - c0);
+            v[u] = tile_at(t, q);
           }
 #pragma unroll
           for (int u = 0; u < UB; ++u) {
@@ -518,7 +644,35 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
     }
     // next step's rows into the other buffer (last read by the previous
     // step, which ended at a barrier)
-    if (has_next) {
+    if (pipe) {
+      if (has_next) {
+        store_tile(tile + (size_t)(buf ^ 1) * tslots, nv);
+        T* bn = bqb + (buf ^ 1) * eta;
+        T* rn = rqb + (buf ^ 1) * eta;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          const int t = tid + p * NT;
+          if (t < eta) { bn[t] = nb[p]; rn[t] = nr[p]; }
+        }
+      }
+      if (has_next2) {
+        // the indices of step k+2, checked (their verdict is agreed below), into the buffer
+        // that held those of step k-1
+        int* tn = taub + (int)((k + 2) % 3) * eta;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          const int t = tid + p * NT;
+          if (t < eta) {
+            const bool ok = ni[p] >= 0 && (int64_t)ni[p] < a.m;
+            if (!ok) next_err = ST_INDEX;
+            tn[t] = ok ? ni[p] : 0;
+          }
+        }
+      }
+      // every prefetch has landed (the stores above used them); said explicitly, so that the
+      // next step's prefetch, whose loads are conditional, is not made to wait for this one's
+      __builtin_amdgcn_s_waitcnt(0);
+    } else if (has_next) {
       int* tn = taub + (buf ^ 1) * eta;
       T* bn = bqb + (buf ^ 1) * eta;
       T* rn = rqb + (buf ^ 1) * eta;
@@ -530,19 +684,25 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
         }
       } else {
         for (int t = tid; t < eta; t += NT) {
-          const int i = tk1[t];
+          const int i = load_global(tk1 + t);
           const bool ok = i >= 0 && (int64_t)i < a.m;
           if (!ok) next_err = ST_INDEX;
           const int ic = ok ? i : 0;
           tn[t] = ic;
-          bn[t] = a.b[ic];
+          bn[t] = load_global(a.b + ic);
           rn[t] = weighted_rn(a.r2, a.row_w, ic);
         }
       }
     }
     // columns past n inside the last chunk stay zero: their tile entries are zero; the
     // barrier agrees on a bad index among the next step's rows
-    row_bad = block_or(orB, next_err ? 4 : 0, k) & 4;
+    const int nbad = block_or(orB, next_err ? 4 : 0, k) & 4;
+    if (pipe) {
+      row_bad = row_bad1;  // checked a step ago
+      row_bad1 = nbad;
+    } else {
+      row_bad = nbad;
+    }
     k_done = k + 1;
     // 6. monitor
     if (a.xref && a.check_every > 0 && (k + 1) % a.check_every == 0) {
@@ -606,7 +766,10 @@ __device__ __forceinline__ void dense_run(const DenseArgs<T>& a, const int g, co
     if (c < a.n) { a.x_star[c] = xs[j]; a.x[c] = xv[j]; }
   }
   if (g == 0 && tid == 0) a.status[1] = (int)k_done;
-  __syncthreads();  // the caller may reuse the LDS for its next task
+  // nothing of this task stays in flight: the caller may reuse the LDS and the registers for
+  // its next task (the compiler then need not guard the next task's writes with waits)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 }
 
 }  // namespace rsk

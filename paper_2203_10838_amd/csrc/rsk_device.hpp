@@ -32,6 +32,23 @@ __device__ __forceinline__ u64 xload(const u64* p) {
   return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Loads from device (global) memory through a generic pointer. A pointer read
+// from memory (a batch descriptor) is otherwise accessed with FLAT
+// instructions, which count against the LDS counter as well, so that every LDS
+// wait and barrier would also wait for them. Scalars and vectors only: an
+// aggregate copy binds a generic reference and loses the address space.
+template <typename T>
+__device__ __forceinline__ T load_global(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T, int N>
+__device__ __forceinline__ void load_global_vec(const T* p, T (&out)[N]) {
+  typedef T vt __attribute__((ext_vector_type(N)));
+  const vt v = *(const __attribute__((address_space(1))) vt*)p;
+#pragma unroll
+  for (int e = 0; e < N; ++e) out[e] = v[e];
+}
+
 template <typename T> struct Words;
 template <> struct Words<float> { static constexpr int N = 1; };
 template <> struct Words<double> { static constexpr int N = 2; };
@@ -120,8 +137,8 @@ __device__ __forceinline__ void set_status(int* status, int code) {
 // row stays 0 (reported as such); w = 0 gives an infinite norm, i.e. no update from the row.
 template <typename T>
 __device__ __forceinline__ T weighted_rn(const T* r2, const T* row_w, int64_t i) {
-  const T rn = r2[i];
-  return (row_w && rn != T(0)) ? rn / row_w[i] : rn;
+  const T rn = load_global(r2 + i);
+  return (row_w && rn != T(0)) ? rn / load_global(row_w + i) : rn;
 }
 
 template <typename T>

@@ -37,7 +37,9 @@ struct DenseArgs {
   u64* xU = nullptr;      // register-tile kernel with RG > 1 row groups: update parts [2][G][slice floats]
   int G;
   int two_hop;            // 1: owners reduce rows, then everyone gathers; 0: everyone reduces everything
-  int tile_cache;         // 1: keep the step's row tile in LDS between dot and scatter
+  int tile_cache;         // 1: keep the step's row tile in LDS between dot and scatter;
+                          // 2: two LDS tiles, the next step's rows loaded (into registers)
+                          // while the step runs on the other (see dense_pipe_ok)
                           // (two_hop == 0 requires G*eta*words <= kOneHopWords)
   int64_t nchunks;        // ceil(n / VEC)
   int wq_max;             // max chunks per workgroup slice
@@ -46,26 +48,43 @@ struct DenseArgs {
 
 constexpr int kDenseThreads = 256;
 
+// The pipelined tile (tile_cache == 2) loads the next step's rows into
+// registers during the step (at most pipe_reg_chunks 16-byte chunks a thread:
+// 8 for float, 4 for double, whose other values take twice the registers) and
+// keeps the next step's b and ||a||^2 in registers (at most 4 rows a thread):
+// it needs whole 16-byte vectors, eta <= 4 * kDenseThreads and a tile of at
+// most pipe_reg_chunks * kDenseThreads chunks.
+__host__ __device__ constexpr int pipe_reg_chunks(size_t esize) { return esize == 8 ? 4 : 8; }
+__host__ __device__ inline bool dense_pipe_ok(size_t esize, int vec, int eta, int wq) {
+  return esize * (size_t)vec == 16 && eta >= 1 && eta <= 4 * kDenseThreads && wq >= 1 &&
+         (int64_t)eta * wq <= (int64_t)pipe_reg_chunks(esize) * kDenseThreads;
+}
+
 // LDS layout of one workgroup of the general dense kernel (byte offsets):
-// own slices of x* and x, the step's coefficients, the rows' indices, b and
-// ||a||^2 (two buffers: the next step's are prefetched during the current
-// one), the update's row-group partials, monitor scratch and, optionally, the
-// step's row tile; with the one-hop exchange also the G*eta partials of the step.
+// own slices of x* and x, the step's coefficients, the rows' indices (three
+// buffers: the pipelined tile fetches them two steps ahead), b and ||a||^2 (two
+// buffers: the next step's are prefetched during the current one), the
+// update's row-group partials, monitor scratch and, optionally, the step's row
+// tile (two tiles when pipelined); with the one-hop exchange also the G*eta
+// partials of the step.
 struct DenseSmem {
   size_t xs, xv, cs, tau, bq, rq, red, xr, flags, tile, total;
   __host__ __device__ static size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
+
   __host__ __device__ DenseSmem(size_t esize, int vec, int wq_max, int eta, int nt, int tile_cache, int64_t xr_elems) {
     size_t o = 0;
     xs = o; o += al16(esize * (size_t)wq_max * vec);
     xv = o; o += al16(esize * (size_t)wq_max * vec);
     cs = o; o += al16(esize * (size_t)eta);
-    tau = o; o += al16(sizeof(int) * 2 * (size_t)eta);
+    tau = o; o += al16(sizeof(int) * 3 * (size_t)eta);
     bq = o; o += al16(esize * 2 * (size_t)eta);
     rq = o; o += al16(esize * 2 * (size_t)eta);
     red = o; o += al16(esize * (size_t)nt * vec);
     xr = o; o += al16(esize * (size_t)xr_elems);
     flags = o; o += 128;
-    tile = o; o += tile_cache ? al16(esize * (size_t)eta * wq_max * vec) : 0;
+    tile = o;
+    if (tile_cache == 2) o += 2 * al16(esize * (size_t)eta * wq_max * vec);
+    else if (tile_cache) o += al16(esize * (size_t)eta * wq_max * vec);
     total = o;
   }
 };
@@ -237,8 +256,15 @@ __host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int 
   for (;;) {
     const int wq = (int)((nchunks + G - 1) / G);
     const int64_t xr = G * eta * (esize / 4) > kOneHopWords ? 0 : onehop_lds_elems(G, eta);
+    const DenseSmem piped(esize, vec, wq, eta, kDenseThreads, 2, xr);
     const DenseSmem with_tile(esize, vec, wq, eta, kDenseThreads, 1, xr);
     const DenseSmem no_tile(esize, vec, wq, eta, kDenseThreads, 0, xr);
+    if (dense_pipe_ok(esize, vec, eta, wq) && piped.total <= kBatchLdsCap) {
+      p->tile_cache = 2;
+      p->lds = piped.total;
+      p->wq_max = wq;
+      break;
+    }
     if (with_tile.total <= kBatchLdsCap || no_tile.total <= kBatchLdsCap) {
       p->tile_cache = with_tile.total <= kBatchLdsCap;
       p->lds = p->tile_cache ? with_tile.total : no_tile.total;

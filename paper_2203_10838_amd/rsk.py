@@ -106,19 +106,20 @@ def workspace_size_dense(A: torch.Tensor, params: _abi.RskParams) -> int:
     return int(nbytes.value)
 
 
-PLAN_FIELDS = ("kernel", "G", "threads", "row_passes", "chunks_per_lane", "row_groups", "hops", "vec")
+PLAN_FIELDS = ("kernel", "G", "threads", "row_passes", "chunks_per_lane", "row_groups", "hops", "vec", "row_tile")
 
 
 def plan_dense(A: torch.Tensor, *, eta: int, K: int = 1, grid: int = 0, kernel: int = 0, lam: float = 0.0,
                alpha: float = 1.0) -> dict:
     """The launch rsk_avg_solve_dense would make for A, eta, grid and kernel (nothing is queued):
     the kernel (1 general, 2 register tile, 3 register tile over two row groups), its workgroups,
-    threads, row passes and chunks per lane, row groups, exchange hops and vector width."""
+    threads, row passes and chunks per lane, row groups, exchange hops, vector width and the
+    general kernel's row tile (0 none, 1 in LDS, 2 two LDS tiles loaded a step ahead)."""
     d = dense_desc(A)
     dummy = torch.empty(2, dtype=torch.int32, device=A.device)
     params = _abi.RskParams(float(lam), int(eta), float(alpha), None, int(K), dummy.data_ptr(), 0,
                             A.data_ptr(), 0, None, 0, 0.0, None, None, dummy.data_ptr(), int(grid), int(kernel), None)
-    out = (ctypes.c_int32 * 8)()
+    out = (ctypes.c_int32 * 9)()
     st = _lib().rsk_plan_dense(ctypes.byref(d), ctypes.byref(params), out)
     if st:
         raise RskError(st, "rsk_plan_dense")

@@ -139,3 +139,31 @@ def test_batched_host_checks(cuda, rsk_lib):
     systems[1].alpha = -1.0
     with pytest.raises(rsk.RskError, match="INVALID_ARG"):
         rsk.solve_batched(systems)
+
+
+@pytest.mark.parametrize("dtype,wg_bytes,tol", [("f32", 0, 1e-4), ("f32", 4096, 1e-4), ("f64", 0, 1e-10),
+                                                ("f64", 2048, 1e-10)])
+def test_batched_pipelined_tiles_with_nan_padding(cuda, rsk_lib, dtype, wg_bytes, tol):
+    """Rows padded past n with NaN to a whole number of 16-byte chunks (the pipelined tile loads
+    whole chunks, so the padding reaches LDS and must never be used); ragged n. Every system
+    matches its oracle run."""
+    import torch
+    from paper_2203_10838_amd import rsk
+    K = 120
+    batch = _batch(24, 31, dtype, False, K, m_hi=600)
+    vec = 4 if dtype == "f32" else 2
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    systems = []
+    for s, eta, idx, al, lam in batch:
+        m, n = s["A"].shape
+        full = torch.full((m, -(-n // vec) * vec + vec), float("nan"), dtype=tdt, device=cuda)
+        full[:, :n] = _t(s["A"], cuda)
+        systems.append(rsk.BatchSystem(A=full[:, :n], b=_t(s["b"], cuda), index_stream=_t(idx, cuda), eta=eta,
+                                       K=K, alpha=al, lam=lam))
+    res = rsk.solve_batched(systems, wg_bytes=wg_bytes)
+    assert all(k == K for k in res.k_done)
+    support = 0
+    for i, (s, eta, idx, al, lam) in enumerate(batch):
+        ref = oracle.rska_dense(s["A"], s["b"], lam, eta, al, K, idx)
+        support += check_iterate(res.x_star[i], res.x[i], ref, lam, tol, min_support=0, what=f"system {i}")[1]
+    assert support >= 3 * len(batch)

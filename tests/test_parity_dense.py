@@ -269,3 +269,52 @@ def test_rownorm2_matches_oracle(cuda, rsk_lib):
         ref = oracle.rownorm2_dense(sysd["A"])
         g = got.double().cpu().numpy()
         assert np.all(np.abs(g - ref) <= tol * ref), dtype
+
+
+@pytest.mark.parametrize("dtype,m,n,eta,K", [
+    ("f32", 700, 301, 17, 80),     # 301 = 75 chunks of 4 + 1
+    ("f32", 2000, 122, 66, 40),    # more rows than one pass of the waves' row groups (64)
+    ("f64", 600, 101, 16, 80),     # 2-element chunks, ragged (101 = 50*2 + 1)
+    ("f64", 900, 61, 33, 60),
+])
+def test_pipelined_row_tile_matches_oracle(cuda, rsk_lib, dtype, m, n, eta, K):
+    """The general kernel on one workgroup with two LDS tiles, the next step's rows loaded (whole
+    16-byte chunks, into registers) while the step runs. The rows are padded with NaN past
+    column n, which the loads bring into the tile and the kernel must never use. The result
+    matches the oracle; a bad index at step 0, 1 or 5 stops the solve at that step (the indices
+    are checked two steps ahead), with x* that of the steps before it; the monitor stops at the
+    oracle's step. The batched kernel runs the same code for its small systems
+    (test_parity_batched.py)."""
+    grid = 1
+    import torch
+    from paper_2203_10838_amd import rsk
+    lam = 0.5
+    sysd, idx = _case(m, n, max(1, n // 20), dtype, 8800 + n, eta, K, lam)
+    vec = 4 if dtype == "f32" else 2
+    ld = -(-n // vec) * vec + vec
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    full = torch.full((m, ld), float("nan"), dtype=tdt, device=cuda)
+    full[:, :n] = _to(sysd["A"], cuda)
+    A = full[:, :n]
+    plan = rsk.plan_dense(A, eta=eta, grid=grid, kernel=1)
+    assert (plan["kernel"], plan["G"], plan["row_tile"], plan["vec"]) == (1, grid, 2, vec), plan
+    b = _to(sysd["b"], cuda)
+    alpha = _alpha_star(sysd["A"], eta)
+    kw = dict(lam=lam, eta=eta, alpha=alpha, grid=grid, kernel=1)
+    res = rsk.solve_dense(A, b, K=K, index_stream=_to(idx, cuda), **kw)
+    assert res.status == 0 and res.k_done == K
+    ref = oracle.rska_dense(sysd["A"], sysd["b"], lam, eta, alpha, K, idx)
+    check_iterate(res.x_star, res.x, ref, lam, TOL[dtype], min_support=3)
+    for step in (0, 1, 5):
+        bad = idx.copy()
+        bad[step * eta + eta // 2] = m
+        r = rsk.solve_dense(A, b, K=K, index_stream=_to(bad, cuda), check=False, **kw)
+        st = r.status_dev.cpu().tolist()
+        assert st == [6, step], (step, st)
+        if step:
+            part = oracle.rska_dense(sysd["A"], sysd["b"], lam, eta, alpha, step, idx)
+            check_vec(r.x_star, part["z"], TOL[dtype], what=f"x* before the bad step {step}")
+    # early stop on the monitor
+    xr = _to(sysd["xhat"], cuda)
+    mon = rsk.solve_dense(A, b, K=K, index_stream=_to(idx, cuda), x_ref=xr, check_every=10, tol=1e30, **kw)
+    assert mon.k_done == 10

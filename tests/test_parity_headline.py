@@ -28,7 +28,7 @@ M, N, S, NOISE = 100_000, 20_000, 200, 0.01
 DATA_SEED = 20310838 + 100          # the benchmark's matrix
 TOL = 1e-4
 BENCH_PLAN = {"kernel": 2, "G": 256, "threads": 512, "row_passes": 8, "chunks_per_lane": 5, "row_groups": 1,
-              "hops": 2, "vec": 4}
+              "hops": 2, "vec": 4, "row_tile": 0}
 
 
 def _threads():
