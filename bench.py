@@ -73,10 +73,12 @@ def step_bytes(eta, n):
 
 def source_hash():
     """Hash of the code that decides the headline launch's traffic (the register-tile kernel, the
-    shared device header, the kernel constants and the planner; comments and blank space removed),
-    so that the recorded HBM counters stay valid across comment edits but not across code changes."""
+    shared device header and the kernel constants; comments and blank space removed), so that the
+    recorded HBM counters stay valid across comment edits but not across code changes. The planner's
+    decision is checked separately: the recorded launch plan (kernel, grid, threads, row passes,
+    chunks, row groups, exchange hops, vector width, row tile) must equal the running one."""
     h = hashlib.sha256()
-    for f in ("rsk_dense_rt.hip", "rsk_device.hpp", "rsk_kernels.hpp", "rsk_api.hip"):
+    for f in ("rsk_dense_rt.hip", "rsk_dense_rt.hpp", "rsk_device.hpp", "rsk_kernels.hpp"):
         src = open(os.path.join(ROOT, "paper_2203_10838_amd", "csrc", f)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)
@@ -209,11 +211,21 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library built-in choices)")
-    ap.add_argument("--record-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"), default=None,
-                    help="write the traffic summary (profiles/dense_rt_traffic.json's format) from two rocprofv3 "
-                         "--pmc counter_collection.csv files of `bench.py --no-sweep --no-cpu --copy-probe` "
-                         "(FETCH_SIZE, then WRITE_SIZE)")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG", "OUT_JSON"),
+                    default=None,
+                    help="host only, no GPU: write the traffic summary (profiles/dense_rt_traffic.json's format) "
+                         "from two rocprofv3 --pmc counter_collection.csv files of `bench.py --no-sweep --no-cpu "
+                         "--copy-probe` (FETCH_SIZE, then WRITE_SIZE) and the JSON line that the first of those "
+                         "runs printed (its launch plan and iterations per launch)")
     args = ap.parse_args()
+    if args.record_traffic:
+        fetch_csv, write_csv, log_path, out_json = args.record_traffic
+        line = [ln for ln in open(log_path) if ln.startswith("{")][-1]
+        head = json.loads(line)
+        d = record_traffic(fetch_csv, write_csv, out_json, head["roofline"]["plan"],
+                           head["config"]["iters_per_step"])
+        print(json.dumps(d))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
               "(multi-GPU column sharding is a design note, not an implementation); use --gpus 1.",
@@ -389,8 +401,6 @@ def main():
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, sysd["b"], weights, LAM, eta, params.optimal_alpha(eta, fro2, smax2))
-    if args.record_traffic:
-        out["traffic_recorded"] = record_traffic(*args.record_traffic, plan, iters)
     print(json.dumps(out), flush=True)
     del A, b, xhat, idx, r2, sysd
     teardown()
@@ -567,6 +577,12 @@ def batched_run(dev, stream, plain=True, wg_bytes=0, tune=False):
     t_b = _median_ms(lambda: rsk.solve_batched(fixed, check=False, wg_bytes=wg_bytes), stream)
     byts = float(sum(int(ki) * step_bytes(s.eta, s.A.shape[1]) for ki, s in zip(k, systems)))
     gbs = byts / (t_b * 1e-3) / 1e9
+    plan = rsk.plan_batched(fixed, wg_bytes=wg_bytes)
+    # the other launch on the same systems and steps (the general kernel when the library took the
+    # register tile), for comparison
+    other = 1 if plan["kernel"] == 2 else None
+    t_other = (_median_ms(lambda: rsk.solve_batched(fixed, check=False, wg_bytes=wg_bytes, kernel=other), stream)
+               if other else None)
     out = {"workload": "512 float32 systems, m~U{500..8000}, n~U{200..m/2}, eta=1+n/10, alpha*, lambda=1, "
                        "x_hat 5% nonzeros, K_i = first check (every 10 steps) with rel.err <= 1e-5, at most 20000",
            "systems": len(systems), "tol": BATCH_TOL, "converged": conv, "k_min": int(k.min()),
@@ -574,7 +590,12 @@ def batched_run(dev, stream, plain=True, wg_bytes=0, tune=False):
            "max_rel_err_converged": float(errs[k < BATCH_KMAX].max()) if conv else None,
            "batched_ms": round(t_b, 3), "batched_GBps": round(gbs, 2),
            "batched_frac_hbm": round(gbs / PEAK_HBM_GBS, 4), "bytes": byts,
-           "batched_early_stop_ms": round(t_early, 3)}
+           "batched_early_stop_ms": round(t_early, 3),
+           "kernel": {1: "general", 2: "register tile"}[plan["kernel"]], "workgroups_total": sum(plan["groups"]),
+           "workgroups_max": max(plan["groups"])}
+    if t_other is not None:
+        out["general_kernel_ms"] = round(t_other, 3)
+        out["general_kernel_GBps"] = round(byts / (t_other * 1e-3) / 1e9, 2)
     log(f"[bench] batched: K_i=k*_i {t_b:.1f} ms ({gbs:.0f} GB/s), early-stop {t_early:.1f} ms, "
         f"converged {conv}/{len(systems)}, k median {out['k_median']} max {out['k_max']}")
     if tune and wg_bytes == 0:
@@ -583,7 +604,7 @@ def batched_run(dev, stream, plain=True, wg_bytes=0, tune=False):
         # whole batch again with the tuned classes
         from paper_2203_10838_amd import autotune
         short = [dataclasses.replace(s_, K=int(min(s_.K, 2000))) for s_ in fixed]
-        tt = autotune.tune_batched(short, candidates_kib=(16, 32, 56, 96), reps=1)
+        tt = autotune.tune_batched(short, reps=1)
         res_t = rsk.solve_batched(fixed)
         errs_t = [int(st) for st in res_t.status]
         if any(errs_t):
@@ -594,7 +615,7 @@ def batched_run(dev, stream, plain=True, wg_bytes=0, tune=False):
                         "batched_ms": round(t_bt, 3), "batched_GBps": round(byts / (t_bt * 1e-3) / 1e9, 2),
                         "batched_frac_hbm": round(byts / (t_bt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                         "same_bits_as_default": same}
-        out["default_wg_kib"] = 56
+        out["default_wg_kib"] = 256 if plan["kernel"] == 2 else 56
         log(f"[bench] batched tuned: {out['tuned']}")
     if plain:
         ws = torch.empty(64 << 20, dtype=torch.uint8, device=dev)

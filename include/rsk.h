@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RSK_ABI_VERSION 4
+#define RSK_ABI_VERSION 5
 
 typedef enum { RSK_F32 = 0, RSK_F64 = 1 } rsk_dtype;
 
@@ -241,8 +241,9 @@ int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
  *                           A_tau X), v1 = S2 (row splits of A_tau^T C: 1, 2, 4 or 8), v2 = the
  *                           forward's kernel (1 step kernels, 2 one persistent launch; 0 = built-in).
  *   path RSK_TUNE_BATCHED:  key (dtype, m = the class's upper bound on a system's step bytes
- *                           eta * n * element size; n = eta = R = 0); v0 = row bytes per
- *                           workgroup for systems of that class (a system takes the class
+ *                           eta * n * element size; n = eta = 0; R = the batched launch: 0
+ *                           general kernel, 2 register tile); v0 = row bytes per workgroup for
+ *                           systems of that class in that launch (a system takes the class
  *                           with the smallest bound >= its step bytes; at most 8 classes).
  * `us` is the measured time of the choice (informational). The cache file
  * (rsk_tune_save / rsk_tune_load) is text, one entry per line:
@@ -366,7 +367,13 @@ int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, 
  * holds about wg_bytes of the step's rows (at most 256); they split its
  * columns and exchange partial dots through the system's own workspace
  * region, exactly as rsk_avg_solve_dense does for one system. Persistent
- * workgroups take (system, rank) tickets in the order `order`.
+ * workgroups take (system, rank) tickets in the order `order`. Two launches
+ * exist: the general kernel (any dtype and alignment; 256-thread
+ * workgroups, two a CU, the step's rows in LDS) and the float32 register
+ * tile (512-thread workgroups, one a CU, the step's rows in VGPRs, column
+ * slices of at most 160 floats, eta <= 512, every system's A 16-byte aligned
+ * with ld % 4 == 0; a last float4 of a row that reaches past n reads the
+ * row padding, which is masked to zero).
  *   nsys       number of systems (0 returns RSK_OK at once).
  *   dtype      RSK_F32 or RSK_F64, the dtype of every system.
  *   items      host array of nsys descriptors, checked before any launch
@@ -377,8 +384,14 @@ int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, 
  *   order      device int32[nsys], a permutation of 0..nsys-1 (nullable: identity).
  *              Largest work first balances the CUs best. A repeated entry makes
  *              two groups write the same x (undefined result).
- *   wg_bytes   target row bytes per workgroup per step (0: 56 KiB). Must be the
- *              value given to rsk_workspace_size_batched.
+ *   wg_bytes   target row bytes per workgroup per step (0: the tuned class of
+ *              the system's step bytes, else 56 KiB for the general kernel and
+ *              256 KiB for the register tile). Must be the value given to
+ *              rsk_workspace_size_batched.
+ *   kernel     0: the register tile if every system takes it, else the general
+ *              kernel; 1: general kernel; 2: register tile (RSK_ERR_UNSUPPORTED
+ *              if a system does not fit it). Must be the value given to
+ *              rsk_workspace_size_batched.
  * Per-system status_dev[0] is reset by the call; it ends 0 or an RSK_ERR_*
  * code, status_dev[1] the steps completed. The kernels plan from the device
  * copy: a device descriptor that is invalid or needs more LDS than the host
@@ -389,10 +402,17 @@ int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, 
  * exchange region per system), zeroed by the call.
  */
 int32_t rsk_workspace_size_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *items, int64_t wg_bytes,
-                                   size_t *bytes);
+                                   int32_t kernel, size_t *bytes);
 int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *items,
                               const rsk_batch_item *items_dev, const int32_t *order, int64_t wg_bytes,
-                              void *workspace, size_t ws_bytes, void *stream);
+                              int32_t kernel, void *workspace, size_t ws_bytes, void *stream);
+/*
+ * The launch rsk_avg_solve_batched would make (nothing is queued, no device
+ * memory is touched): *kernel_out = 1 (general) or 2 (register tile), and
+ * groups_out[i] = G_i, the workgroups of system i (host array of nsys).
+ */
+int32_t rsk_plan_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *items, int64_t wg_bytes,
+                         int32_t kernel, int32_t *kernel_out, int32_t *groups_out);
 
 /*
  * Many right-hand sides sharing A and the index stream (float32 only), on the

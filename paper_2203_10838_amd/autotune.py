@@ -9,8 +9,8 @@ What is tuned, per key:
   its workgroup count, among the launches rsk_plan_dense accepts;
 * multi-RHS (dtype, m, n, eta, R): S, the column splits of A_tau X, and S2, the row splits of
   A_tau^T C;
-* batched (dtype, size class of a system's step bytes eta*n*s): the row bytes per workgroup that
-  set a system's workgroup count.
+* batched (dtype, size class of a system's step bytes eta*n*s, launch: general kernel or register
+  tile): the row bytes per workgroup that set a system's workgroup count.
 
 A candidate's time is the median of ``reps`` timed calls (HIP events on the current stream)
 after one untimed call. Every candidate computes the same iteration: a tuned choice changes
@@ -198,18 +198,24 @@ def tune_multirhs(A: torch.Tensor, B: torch.Tensor, *, eta: int, lam: float, alp
 
 BATCH_CLASS_BOUNDS = (32 << 10, 128 << 10, 512 << 10, 2 << 20, 8 << 20, 1 << 62)
 BATCH_CANDIDATES_KIB = (8, 16, 24, 32, 48, 64, 96, 128)
+BATCH_RT_CANDIDATES_KIB = (16, 32, 64, 128, 256)
 
 
-def tune_batched(systems, *, bounds=BATCH_CLASS_BOUNDS, candidates_kib=BATCH_CANDIDATES_KIB, reps: int = 2,
+def tune_batched(systems, *, bounds=BATCH_CLASS_BOUNDS, candidates_kib=None, reps: int = 2, kernel: int = 0,
                  install: bool = True) -> dict:
     """Per size class of a system's step bytes (eta * n * element bytes, classes ending at ``bounds``):
     the systems of that class run as one batch for each candidate target of row bytes per
-    workgroup; the fastest target is installed for the class. Systems of other classes are not
-    in the timed batch (a class is tuned on its own). Returns the per-class table."""
+    workgroup; the fastest target is installed for the class and the launch (``kernel`` 1 general,
+    2 register tile, 0 the launch the library picks for the whole batch). Systems of other classes
+    are not in the timed batch (a class is tuned on its own). Returns the per-class table."""
     if not systems:
         raise ValueError("empty batch")
     dtype = rsk._dtype_code(systems[0].A)
     es = systems[0].A.element_size()
+    if kernel == 0:
+        kernel = rsk.plan_batched(systems)["kernel"]
+    if candidates_kib is None:
+        candidates_kib = BATCH_RT_CANDIDATES_KIB if kernel == 2 else BATCH_CANDIDATES_KIB
     step = [s.eta * s.A.shape[1] * es for s in systems]
     out, lo = [], 0
     for hi in bounds:
@@ -220,10 +226,10 @@ def tune_batched(systems, *, bounds=BATCH_CLASS_BOUNDS, candidates_kib=BATCH_CAN
         rows = []
         for kib in candidates_kib:
             try:
-                rsk.solve_batched(members, wg_bytes=kib << 10, check=False)
+                rsk.solve_batched(members, wg_bytes=kib << 10, kernel=kernel, check=False)
             except rsk.RskError:
                 continue
-            ms = _time_ms(lambda: rsk.solve_batched(members, wg_bytes=kib << 10, check=False), reps)
+            ms = _time_ms(lambda: rsk.solve_batched(members, wg_bytes=kib << 10, kernel=kernel, check=False), reps)
             rows.append({"wg_kib": kib, "ms": ms})
         if not rows:
             continue
@@ -231,5 +237,6 @@ def tune_batched(systems, *, bounds=BATCH_CLASS_BOUNDS, candidates_kib=BATCH_CAN
         out.append({"step_bytes_hi": hi, "systems": len(members), "wg_kib": best["wg_kib"], "ms": best["ms"],
                     "table": rows})
         if install:
-            set_entry(_abi.RSK_TUNE_BATCHED, dtype, m=hi, v0=best["wg_kib"] << 10, us=best["ms"] * 1e3)
-    return {"classes": out}
+            set_entry(_abi.RSK_TUNE_BATCHED, dtype, m=hi, R=2 if kernel == 2 else 0, v0=best["wg_kib"] << 10,
+                      us=best["ms"] * 1e3)
+    return {"kernel": kernel, "classes": out}

@@ -56,14 +56,16 @@ void tune_put_locked(const rsk_tune_entry& e) {
   g_tune.push_back(e);
 }
 
-// the batched classes of one dtype, ascending by their step-byte bound
-rsk::BatchWgTable tune_batch_table(int32_t dtype) {
+// the batched classes of one dtype and launch kind (key R: 0 general kernel, 2 register tile),
+// ascending by their step-byte bound
+rsk::BatchWgTable tune_batch_table(int32_t dtype, int kind) {
   rsk::BatchWgTable t{};
   std::lock_guard<std::mutex> lock(g_tune_mu);
   tune_env_locked();
   std::vector<rsk_tune_entry> cls;
+  const int32_t key_r = kind == 2 ? 2 : 0;
   for (const rsk_tune_entry& e : g_tune)
-    if (e.path == RSK_TUNE_BATCHED && e.dtype == dtype && e.v0 > 0) cls.push_back(e);
+    if (e.path == RSK_TUNE_BATCHED && e.dtype == dtype && e.R == key_r && e.v0 > 0) cls.push_back(e);
   std::sort(cls.begin(), cls.end(), [](const rsk_tune_entry& a, const rsk_tune_entry& b) { return a.m < b.m; });
   for (const rsk_tune_entry& e : cls) {
     if (t.nc == rsk::kBatchClasses) break;
@@ -493,35 +495,58 @@ int32_t check_batch_item(const rsk_batch_item& it) {
 // Workspace of a batch: [256 B: ticket counter][ticket starts, nsys+1 int64]
 // [region offsets, nsys int64][one exchange region per system].
 struct BatchLayout {
+  int kind;  // 1 general kernel, 2 register tile
   int vec, gmax;
   rsk::BatchWgTable tab;
   int64_t tickets, words;
   size_t lds, off_t0, off_woff, off_region, bytes;
 };
 
-int32_t batch_layout(int32_t nsys, int32_t dtype, const rsk_batch_item* items, int64_t wg_bytes, BatchLayout* L) {
-  if (nsys < 0 || (nsys > 0 && !items) || wg_bytes < 0) return RSK_ERR_INVALID_ARG;
+rsk::BatchWgTable batch_table(int32_t dtype, int kind, int64_t wg_bytes) {
+  if (wg_bytes > 0) {
+    rsk::BatchWgTable t{};
+    t.nc = 1;
+    t.hi[0] = INT64_MAX;
+    t.wg[0] = wg_bytes;
+    return t;
+  }
+  return tune_batch_table(dtype, kind);  // no classes: every system takes the kind's default target
+}
+
+// The launch of a batch: kernel 1 (general), 2 (register tile: float32, every system's rows 16-byte
+// aligned and its plan within the tile's limits, else RSK_ERR_UNSUPPORTED) or 0 (the register tile
+// where every system takes it, else the general kernel); each system's plan and the workspace.
+int32_t batch_layout(int32_t nsys, int32_t dtype, const rsk_batch_item* items, int64_t wg_bytes, int32_t kernel,
+                     BatchLayout* L, int32_t* g_out = nullptr) {
+  if (nsys < 0 || (nsys > 0 && !items) || wg_bytes < 0 || kernel < 0 || kernel > 2) return RSK_ERR_INVALID_ARG;
   if (dtype != RSK_F32 && dtype != RSK_F64) return RSK_ERR_UNSUPPORTED;
   const size_t es = elem_size(dtype);
   const int vmax = (int)(16 / es);
-  if (wg_bytes > 0) {
-    L->tab = rsk::BatchWgTable{};
-    L->tab.nc = 1;
-    L->tab.hi[0] = INT64_MAX;
-    L->tab.wg[0] = wg_bytes;
-  } else {
-    L->tab = tune_batch_table(dtype);  // no classes: every system takes the default target
-  }
   L->vec = vmax;
   for (int32_t i = 0; i < nsys; ++i) {
     const int32_t st = check_batch_item(items[i]);
     if (st) return st;
     if ((items[i].ld % vmax) != 0 || ((uintptr_t)items[i].A) % 16 != 0) L->vec = 1;
   }
+  L->kind = 1;
+  if (kernel != 1 && dtype == RSK_F32 && L->vec == 4 && nsys > 0) {
+    const rsk::BatchWgTable tab = batch_table(dtype, 2, wg_bytes);
+    bool all = true;
+    for (int32_t i = 0; i < nsys && all; ++i) {
+      rsk::BatchPlan pl;
+      all = rsk::batched_rt_plan(items[i].n, items[i].eta, tab, &pl);
+    }
+    if (all) L->kind = 2;
+  }
+  if (kernel == 2 && L->kind != 2) return RSK_ERR_UNSUPPORTED;
+  L->tab = batch_table(dtype, L->kind, wg_bytes);
   L->gmax = 0; L->tickets = 0; L->words = 0; L->lds = 0;
   for (int32_t i = 0; i < nsys; ++i) {
     rsk::BatchPlan pl;
-    if (!rsk::batched_plan(items[i].n, items[i].eta, (int)es, L->vec, L->tab, &pl)) return RSK_ERR_UNSUPPORTED;
+    const bool ok = L->kind == 2 ? rsk::batched_rt_plan(items[i].n, items[i].eta, L->tab, &pl)
+                                 : rsk::batched_plan(items[i].n, items[i].eta, (int)es, L->vec, L->tab, &pl);
+    if (!ok) return RSK_ERR_UNSUPPORTED;
+    if (g_out) g_out[i] = pl.G;
     if (pl.G > L->gmax) L->gmax = pl.G;
     if (pl.lds > L->lds) L->lds = pl.lds;
     L->tickets += pl.G;
@@ -762,25 +787,35 @@ int32_t noalloc_scratch(void** out) {
 extern "C" {
 
 int32_t rsk_workspace_size_batched(int32_t nsys, int32_t dtype, const rsk_batch_item* items, int64_t wg_bytes,
-                                   size_t* bytes) {
+                                   int32_t kernel, size_t* bytes) {
   if (!bytes) return RSK_ERR_INVALID_ARG;
   BatchLayout L;
-  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, &L);
+  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, kernel, &L);
   if (st) return st;
   *bytes = L.bytes;
   return RSK_OK;
 }
 
+int32_t rsk_plan_batched(int32_t nsys, int32_t dtype, const rsk_batch_item* items, int64_t wg_bytes, int32_t kernel,
+                         int32_t* kernel_out, int32_t* groups_out) {
+  if (!kernel_out || (nsys > 0 && !groups_out)) return RSK_ERR_INVALID_ARG;
+  BatchLayout L;
+  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, kernel, &L, groups_out);
+  if (st) return st;
+  *kernel_out = L.kind;
+  return RSK_OK;
+}
+
 int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item* items,
                               const rsk_batch_item* items_dev, const int32_t* order, int64_t wg_bytes,
-                              void* workspace, size_t ws_bytes, void* stream) {
+                              int32_t kernel, void* workspace, size_t ws_bytes, void* stream) {
   BatchLayout L;
-  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, &L);
+  const int32_t st = batch_layout(nsys, dtype, items, wg_bytes, kernel, &L);
   if (st) return st;
   if (nsys == 0) return RSK_OK;
   if (!items_dev) return RSK_ERR_INVALID_ARG;
   if (!workspace || ws_bytes < L.bytes || ((uintptr_t)workspace) % 256) return RSK_ERR_WORKSPACE;
-  const int maxg = rsk::batched_max_resident(dtype, L.vec, L.lds);
+  const int maxg = L.kind == 2 ? rsk::batched_rt_max_resident() : rsk::batched_max_resident(dtype, L.vec, L.lds);
   if (maxg < L.gmax) return RSK_ERR_UNSUPPORTED;
   const int grid = L.tickets < maxg ? (int)L.tickets : maxg;
   unsigned char* w = (unsigned char*)workspace;
@@ -788,13 +823,14 @@ int32_t rsk_avg_solve_batched(int32_t nsys, int32_t dtype, const rsk_batch_item*
   if (rsk::launch_zero_words((u64*)w, L.bytes / sizeof(u64), s) != hipSuccess) return RSK_ERR_HIP;
   int64_t* t0 = (int64_t*)(w + L.off_t0);
   int64_t* wo = (int64_t*)(w + L.off_woff);
-  if (rsk::launch_batched_prep(items_dev, order, nsys, (int)elem_size(dtype), L.vec, L.tab, L.lds,
+  if (rsk::launch_batched_prep(L.kind, items_dev, order, nsys, (int)elem_size(dtype), L.vec, L.tab, L.lds,
                                L.words, t0, wo, s) != hipSuccess)
     return RSK_ERR_HIP;
-  if (rsk::launch_batched(items_dev, order, nsys, t0, wo, (u64*)w, (u64*)(w + L.off_region), L.tab, dtype,
-                          L.vec, L.lds, grid, s) != hipSuccess)
-    return RSK_ERR_HIP;
-  return RSK_OK;
+  const hipError_t e = L.kind == 2
+      ? rsk::launch_batched_rt(items_dev, order, nsys, t0, wo, (u64*)w, (u64*)(w + L.off_region), L.tab, grid, s)
+      : rsk::launch_batched(items_dev, order, nsys, t0, wo, (u64*)w, (u64*)(w + L.off_region), L.tab, dtype,
+                            L.vec, L.lds, grid, s);
+  return e == hipSuccess ? RSK_OK : RSK_ERR_HIP;
 }
 
 int32_t rsk_workspace_size_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, size_t* bytes) {

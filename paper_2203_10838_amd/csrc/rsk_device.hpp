@@ -49,6 +49,16 @@ __device__ __forceinline__ void load_global_vec(const T* p, T (&out)[N]) {
   for (int e = 0; e < N; ++e) out[e] = v[e];
 }
 
+__device__ __forceinline__ float4 load_global_f4(const float* p) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = *(const __attribute__((address_space(1))) v4*)p;
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+template <typename T>
+__device__ __forceinline__ void store_global(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 template <typename T> struct Words;
 template <> struct Words<float> { static constexpr int N = 1; };
 template <> struct Words<double> { static constexpr int N = 2; };

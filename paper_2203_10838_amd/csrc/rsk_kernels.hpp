@@ -224,6 +224,7 @@ constexpr int64_t kBatchRegionHead = 32;        // words: join counter + padding
 
 struct BatchPlan {
   int G, two_hop, tile_cache, lpr, wq_max;
+  int cpl;  // register-tile launch: float4 chunks a lane (units of 16 floats of the widest slice)
   int64_t nchunks, words;
   size_t lds;
 };
@@ -236,10 +237,10 @@ struct BatchWgTable {
   int nc;
   int64_t hi[kBatchClasses];
   int64_t wg[kBatchClasses];
-  __host__ __device__ int64_t lookup(int64_t step_bytes) const {
+  __host__ __device__ int64_t lookup(int64_t step_bytes, int64_t dflt = kBatchWgBytes) const {
     for (int c = 0; c < nc; ++c)
       if (step_bytes <= hi[c]) return wg[c];
-    return kBatchWgBytes;
+    return dflt;
   }
 };
 
@@ -279,6 +280,7 @@ __host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int 
   const int W = esize / 4;
   p->G = (int)G;
   p->lpr = lpr;
+  p->cpl = 0;
   p->nchunks = nchunks;
   p->two_hop = G * eta * W > kOneHopWords;
   const int64_t body = 2 * G * eta * W + (int64_t)eta * W + 4 * G;
@@ -286,7 +288,8 @@ __host__ __device__ inline bool batched_plan(int64_t n, int eta, int esize, int 
   return true;
 }
 
-hipError_t launch_batched_prep(const rsk_batch_item* items, const int32_t* order, int nsys, int esize, int vec,
+// kind 1: general kernel plans (batched_plan); kind 2: register-tile plans (batched_rt_plan)
+hipError_t launch_batched_prep(int kind, const rsk_batch_item* items, const int32_t* order, int nsys, int esize, int vec,
                                const BatchWgTable& tab, size_t lds_launch, int64_t cap_words, int64_t* ticket0,
                                int64_t* woff, hipStream_t stream);
 // Largest co-resident grid of the batched kernel with this LDS size (0 if none).
@@ -319,6 +322,57 @@ int dense_rt_max_grid(int nt, int rp, int cpl, int rg);
 hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, int rg, hipStream_t stream);
 // kRtOwnMax: rows of a step one wave of the register-tile kernel reduces
 constexpr int kRtMaxEta = 1024, kRtMaxCPL = 5, kRtOwnMax = 4;
+
+// Batched launch on the register tile (float32): kBrtThreads threads a workgroup, one per CU,
+// kBrtPasses row passes of kBrtThreads / 4 rows (eta <= 512) and at most kBrtCpl float4 chunks a
+// lane, i.e. column slices of up to 16 * kBrtCpl floats (640-byte pieces of each sampled row).
+constexpr int kBrtThreads = 512, kBrtPasses = 4, kBrtCpl = 10;
+// LDS of the next-step prefetch (one workgroup a CU)
+constexpr int kBrtPfBytes = 147456;
+constexpr int kBrtMaxEta = kBrtPasses * (kBrtThreads / 4);
+// default row bytes per workgroup per step of the register-tile launch (a tuned class overrides it)
+constexpr int64_t kBrtWgBytes = 256 * 1024;
+
+// Plan of one system on the batched register tile (the same function on host and device):
+// G_s from the row bytes per workgroup of the system's size class, at least enough slices for
+// kBrtCpl chunks a lane and, with two exchange hops, for kRtOwnMax rows per wave; the
+// exchange region has the layout of the general batched kernel (4-byte words); at most one
+// workgroup per 16-float unit of a row. False if the system does not fit (eta > kBrtMaxEta, or
+// more workgroups needed than it has units or than kBatchGcap).
+__host__ __device__ inline bool batched_rt_plan(int64_t n, int eta, const BatchWgTable& tab, BatchPlan* p) {
+  if (n <= 0 || eta <= 0 || eta > kBrtMaxEta) return false;
+  const int64_t wg_bytes = tab.lookup((int64_t)eta * n * 4, kBrtWgBytes);
+  if (wg_bytes <= 0) return false;
+  const int64_t nchunks = (n + 3) / 4, nunits = (nchunks + 3) / 4;
+  const int64_t gmax = nunits < kBatchGcap ? nunits : kBatchGcap;
+  int64_t G = ((int64_t)eta * n * 4 + wg_bytes - 1) / wg_bytes;
+  if (G > gmax) G = gmax;  // a small target: one 16-float unit a slice
+  const int64_t gcpl = (nunits + kBrtCpl - 1) / kBrtCpl;
+  if (G < gcpl) G = gcpl;
+  if (G < 1) G = 1;
+  const int own = kRtOwnMax * (kBrtThreads / 64);
+  if (G * eta > kRtOneHopWords || eta > own) {
+    const int64_t gown = (eta + own - 1) / own;
+    if (G < gown) G = gown;
+  }
+  if (G > gmax) return false;
+  p->G = (int)G;
+  p->two_hop = (G * eta > kRtOneHopWords || eta > own) ? 1 : 0;
+  p->tile_cache = 0;
+  p->lds = 0;
+  p->nchunks = nchunks;
+  p->cpl = (int)((nunits + G - 1) / G);
+  p->wq_max = 4 * p->cpl;
+  p->lpr = 4;
+  const int64_t body = 2 * G * eta + (int64_t)eta + 4 * G;
+  p->words = kBatchRegionHead + (body + 31) / 32 * 32;
+  return true;
+}
+// Largest co-resident grid of the batched register-tile kernel (0 if none).
+int batched_rt_max_resident();
+hipError_t launch_batched_rt(const rsk_batch_item* items, const int32_t* order, int nsys, const int64_t* ticket0,
+                             const int64_t* woff, u64* queue, u64* regions, const BatchWgTable& tab, int grid,
+                             hipStream_t stream);
 hipError_t launch_zero_status(int* status, hipStream_t stream);
 
 // Linearized Bregman (full batch) and power iteration on A^T A. One pass reads A once with

@@ -622,11 +622,8 @@ class BatchResult:
     keep: list
 
 
-def solve_batched(systems, *, order=None, wg_bytes: int = 0, workspace: Optional[torch.Tensor] = None,
-                  check: bool = True) -> BatchResult:
-    """All systems in one launch; system i on G_i workgroups (largest work first by default)."""
-    if not systems:
-        raise ValueError("empty batch")
+def _batch_items(systems):
+    """Host descriptors of a batch and the tensors they point to (outputs, row norms kept alive)."""
     dev = systems[0].A.device
     dt = systems[0].A.dtype
     nsys = len(systems)
@@ -655,20 +652,51 @@ def solve_batched(systems, *, order=None, wg_bytes: int = 0, workspace: Optional
         xs_out.append(xs)
         x_out.append(x)
         hist_out.append(eh)
+    return items, status_dev, xs_out, x_out, hist_out, keep
+
+
+def plan_batched(systems, *, wg_bytes: int = 0, kernel: int = 0) -> dict:
+    """The launch rsk_avg_solve_batched would make (nothing is queued): the kernel (1 general,
+    2 register tile) and each system's workgroups."""
+    if not systems:
+        raise ValueError("empty batch")
+    items, _, _, _, _, _ = _batch_items(systems)
+    kout = ctypes.c_int32(0)
+    groups = (ctypes.c_int32 * len(systems))()
+    st = _lib().rsk_plan_batched(len(systems), _dtype_code(systems[0].A), ctypes.addressof(items), int(wg_bytes),
+                                 int(kernel), ctypes.byref(kout), groups)
+    if st:
+        raise RskError(st, "rsk_plan_batched")
+    return {"kernel": int(kout.value), "groups": [int(g) for g in groups]}
+
+
+def solve_batched(systems, *, order=None, wg_bytes: int = 0, kernel: int = 0,
+                  workspace: Optional[torch.Tensor] = None, check: bool = True) -> BatchResult:
+    """All systems in one launch; system i on G_i workgroups (most steps first by default).
+    ``kernel``: 0 library's choice, 1 general kernel, 2 float32 register tile."""
+    if not systems:
+        raise ValueError("empty batch")
+    dev = systems[0].A.device
+    nsys = len(systems)
+    items, status_dev, xs_out, x_out, hist_out, keep = _batch_items(systems)
     items_dev = torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(dev)
     if order is None:
+        # longest first: a system's steps take about the same time whatever its size (each step is
+        # bound by the exchange latency), so the systems with the most steps go first, larger work
+        # first among equal step counts, and the launch does not end on a long system started late
         work = [sy.K * sy.eta * sy.A.shape[1] for sy in systems]
-        order = sorted(range(nsys), key=lambda i: -work[i])
+        order = sorted(range(nsys), key=lambda i: (-systems[i].K, -work[i]))
     order_dev = torch.tensor(list(order), dtype=torch.int32, device=dev)
     code = _dtype_code(systems[0].A)
     nbytes = ctypes.c_size_t(0)
-    st = _lib().rsk_workspace_size_batched(nsys, code, ctypes.addressof(items), int(wg_bytes), ctypes.byref(nbytes))
+    st = _lib().rsk_workspace_size_batched(nsys, code, ctypes.addressof(items), int(wg_bytes), int(kernel),
+                                           ctypes.byref(nbytes))
     if st:
         raise RskError(st, "rsk_workspace_size_batched")
     if workspace is None or workspace.numel() < nbytes.value:
         workspace = _workspace(nbytes.value, dev)
     st = _lib().rsk_avg_solve_batched(nsys, code, ctypes.addressof(items), items_dev.data_ptr(), order_dev.data_ptr(),
-                                      int(wg_bytes), workspace.data_ptr(), workspace.numel(), _stream())
+                                      int(wg_bytes), int(kernel), workspace.data_ptr(), workspace.numel(), _stream())
     if st:
         raise RskError(st, "rsk_avg_solve_batched")
     status = k_done = None

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_host_only_calls():
     lib = _abi.load()
-    assert lib.rsk_abi_version() == 4
+    assert lib.rsk_abi_version() == 5
     assert lib.rsk_status_string(7) == b"RSK_ERR_NONFINITE"
     assert lib.rsk_status_string(99) == b"RSK_ERR_UNKNOWN"
 
@@ -66,3 +66,41 @@ def test_host_validation_rejects_bad_arguments():
     assert lib.rsk_avg_solve_dense(None, 0x5000, ctypes.byref(p), 0x6000, 0x7000, 0x8000, 1 << 20, None) == 1
     assert lib.rsk_avg_solve_dense(ctypes.byref(d), None, ctypes.byref(p), 0x6000, 0x7000, 0x8000, 1 << 20,
                                    None) == 1
+
+
+def test_batched_launch_choice_host_only():
+    """rsk_plan_batched (host only): the register tile for a float32 batch whose systems all fit it
+    (rows 16-byte aligned, ld % 4 == 0, eta <= 512), else the general kernel; kernel = 2 on a batch
+    that does not fit is refused."""
+    lib = _abi.load()
+
+    def items(specs):
+        arr = (_abi.RskBatchItem * len(specs))()
+        for i, (m, n, ld, eta, base) in enumerate(specs):
+            arr[i] = _abi.RskBatchItem(base, m, n, ld, 0x2000, 0x3000, 0x4000, 10, eta, 0, 1.0, 0.5, 0x5000, 0x6000,
+                                       None, 0, 0.0, None, 0x7000)
+        return arr
+
+    def plan(specs, dtype=0, wg=0, kernel=0):
+        arr = items(specs)
+        k = ctypes.c_int32(-1)
+        g = (ctypes.c_int32 * len(specs))()
+        st = lib.rsk_plan_batched(len(specs), dtype, ctypes.addressof(arr), wg, kernel, ctypes.byref(k), g)
+        return st, k.value, list(g)
+
+    fits = [(4000, 2000, 2000, 201, 0x10000), (1000, 301, 304, 31, 0x20000), (600, 200, 200, 21, 0x30000)]
+    st, k, g = plan(fits)
+    assert st == 0 and k == 2, (st, k)
+    # 2000 columns: 125 units of 16 floats, at most 10 a lane -> at least 13 slices; 201 rows of
+    # 8000 bytes at 128 KiB a workgroup -> 13 workgroups
+    assert g[0] == 13 and g[1] >= 2 and g[2] >= 2, g
+    st, k, g = plan(fits, wg=16 << 10)
+    assert st == 0 and k == 2 and g[0] == 99, g
+    assert plan(fits, kernel=1)[:2] == (0, 1)
+    for bad in [(4000, 2000, 2000, 600, 0x10000),  # eta > 512
+                (1000, 301, 301, 31, 0x20000),      # ld % 4 != 0
+                (1000, 300, 300, 31, 0x20004)]:     # rows not 16-byte aligned
+        assert plan(fits + [bad])[:2] == (0, 1), bad
+        assert plan(fits + [bad], kernel=2)[0] == 2, bad  # RSK_ERR_UNSUPPORTED
+    assert plan(fits, dtype=1)[:2] == (0, 1)  # float64: general kernel
+    assert plan(fits, dtype=1, kernel=2)[0] == 2
