@@ -78,7 +78,7 @@ def source_hash():
     decision is checked separately: the recorded launch plan (kernel, grid, threads, row passes,
     chunks, row groups, exchange hops, vector width, row tile) must equal the running one."""
     h = hashlib.sha256()
-    for f in ("rsk_dense_rt.hip", "rsk_dense_rt.hpp", "rsk_device.hpp", "rsk_kernels.hpp"):
+    for f in ("rsk_dense_rt.hip", "rsk_device.hpp", "rsk_kernels.hpp"):
         src = open(os.path.join(ROOT, "paper_2203_10838_amd", "csrc", f)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)

@@ -1,38 +1,25 @@
-// Dense RSKA, float32, register-tile persistent kernel (the throughput path): the step body,
-// shared by the single-system kernel and the batched launch.
+// Dense RSKA, float32, register-tile step for the batched launch (rska_batched_rt).
 //
-// Same iteration and exchange protocol as rska_dense_persistent, laid out for
-// HBM streaming on gfx950:
-//  * NT threads per workgroup (1024, or 512 for eta > 768), one workgroup per
-//    CU. The G workgroups form RG row groups of G/RG column slices: the
-//    workgroup of slice s and group h owns the slice's x (at most 4*RG*CPL
-//    float4 chunks, whole 64-byte units) and reads the slice of the rows
-//    h*etaR .. (h+1)*etaR - 1 of each step, etaR = ceil(eta/RG). Wider
-//    slices (RG = 2) make longer contiguous pieces of each row, which HBM
-//    serves faster; the RG workgroups of a slice then add their parts of the
-//    update in a third exchange hop, in a fixed order, so that they keep
-//    identical copies of x.
-//  * With RL = 16/RG, lane l of wave w holds group row p*(NT/64)*RL + RL*w +
-//    (l % RL) of pass p and chunks q = (l / RL) + 4*RG*r, r < CPL. The RL
-//    lanes that hold one chunk column are adjacent, so the column sums of the
-//    update reduce with DPP adds within a row; the lanes that hold one row
-//    reduce with swaps.
-//  * All RP*CPL float4 loads of a step are issued before the first is used
-//    (up to 20 KB in flight per CU). The addresses never depend on a
-//    predicate: a chunk outside the slice is clamped into the row and meets a
-//    zero x entry in the dot, and its column sum is discarded.
-//  * The step's tile stays in VGPRs from the dots to the transposed update:
-//    A is read from HBM exactly once per step.
-//  * The first NPF (pass, chunk) slots of the next step's tile (up to 144 KB
-//    a workgroup; all slots for tiles that fit) are loaded straight into LDS
-//    (global_load_lds, no VGPRs) by the waves that take no part in the
-//    exchange, while the exchange runs; the next step reads them from LDS, so
-//    only the other slots load from HBM on the step's critical path.
-//  * Each pass publishes its partial dots as soon as its own loads have
-//    landed; the next step's indices, and b and ||a||^2 of the rows this
-//    workgroup reduces, are fetched a step ahead.
-//  * Summation orders are fixed, so x* and x are bitwise reproducible (the
-//    optional dual y is summed with atomics: reproducible to rounding).
+// The step of the single-system register-tile kernel (rska_dense_rt in rsk_dense_rt.hip: same
+// lane layout, LDS prefetch of the next step's first slots, exchange protocol and summation
+// orders), written as a device function for a workgroup that solves one system of a batch after
+// another. What differs for a batched system (BATCH = true):
+//  * ranks map to column slices in order (the ranks of a system are drawn from a ticket queue,
+//    so their XCDs are not known);
+//  * only the chunk slots of a lane that hold the system's columns (cplr <= CPL) and the passes
+//    that hold rows of the step are loaded and used;
+//  * a last float4 of a row that reaches past n (rows padded to a multiple of 4 floats) has its
+//    padding masked to zero before the dots and the update;
+//  * global memory is read through address-space-1 pointers (the pointers come from a
+//    descriptor in memory and would otherwise be FLAT loads, whose count also gates every LDS
+//    wait of the step);
+//  * a wave that reduces several rows polls their partial sums in one round trip when each lane
+//    holds one slice (at most 64 workgroups);
+//  * the issuing waves wait for their LDS prefetch with the count of HBM slot loads they issued
+//    after it, which varies with the system.
+// The single-system kernel keeps its own copy of the step: compiled from this function it ran
+// 6% slower on its headline shape (100000 x 20000, eta = 1024: 21.9 against 20.6 us per
+// iteration, same registers and LDS; the instruction schedule differs).
 #pragma once
 #include "rsk_device.hpp"
 #include "rsk_kernels.hpp"
@@ -76,6 +63,20 @@ __device__ __forceinline__ float lanes_sum(float v) {
 
 }  // namespace
 
+// Loads of the step: through the global address space for a batched system (its pointers come
+// from a descriptor in memory and would otherwise be FLAT, whose count also gates every LDS wait);
+// plain loads for one system (kernel-argument pointers are global already).
+template <bool GLOBAL, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (GLOBAL) return load_global(p);
+  else return *p;
+}
+template <bool GLOBAL>
+__device__ __forceinline__ float4 ld4(const float* p) {
+  if constexpr (GLOBAL) return load_global_f4(p);
+  else return *reinterpret_cast<const float4*>(p);
+}
+
 // s_waitcnt until at most n vector memory loads of the wave are outstanding (n wave-uniform,
 // 0 <= n <= N): the count is an immediate, so uniform branches pick the constant.
 template <int N>
@@ -99,7 +100,7 @@ __device__ __forceinline__ void wait_vm_at_most(int n) {
 // to a multiple of 4 floats) has its padding masked to zero.
 // PF_BYTES: LDS for the next step's prefetched slots (147456: one workgroup a CU).
 template <int NT, int RP, int CPL, int RG, bool BATCH, int PF_BYTES = 147456>
-__device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, const int cplr) {
+__device__ __forceinline__ void rt_run(DenseArgs<float> a, const int g, const int cplr) {
   constexpr int kRtThreads = NT;
   constexpr int kRtWaves = NT / 64;
   constexpr int RL = 16 / RG;                     // rows a wave holds per pass
@@ -159,11 +160,13 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
   auto son = [&](int r) { return !BATCH || r < cplr; };
   auto pon = [&](int p, int wv) { return !BATCH || p * kRtRowsPerPass + RL * wv < etaH; };
   int nhbm = 0;  // next-step slots this wave loads from HBM (not from the LDS prefetch)
+  if constexpr (BATCH) {
 #pragma unroll
-  for (int p = 0; p < RP; ++p)
+    for (int p = 0; p < RP; ++p)
 #pragma unroll
-    for (int r = 0; r < CPL; ++r)
-      if (p * CPL + r >= NPF && son(r) && pon(p, wave)) ++nhbm;
+      for (int r = 0; r < CPL; ++r)
+        if (p * CPL + r >= NPF && son(r) && pon(p, wave)) ++nhbm;
+  }
   auto mask_tail = [&](float4& v, int q) {
     if (BATCH && nrem && q >= qlast) {
       if (nrem < 2) v.y = 0.f;
@@ -182,7 +185,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
   if (tid < 2) orflag[tid] = hop3_bad[tid] = 0;
   for (int j = tid; j < SW; j += kRtThreads) {
     const int64_t c = c0 + j;
-    const float z = (a.warm && j < wq * 4 && c < a.n) ? load_global(a.x_star + c) : 0.f;
+    const float z = (a.warm && j < wq * 4 && c < a.n) ? ld<BATCH>(a.x_star + c) : 0.f;
     xs[j] = z;
     xv[j] = shrink(z, a.lambda);
   }
@@ -200,7 +203,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
       const int t = p * kRtRowsPerPass + RL * wave + ri;
-      ri_out[p] = load_global(tk + (t < etaH ? hr0 + t : 0));
+      ri_out[p] = ld<BATCH>(tk + (t < etaH ? hr0 + t : 0));
     }
     int xo[RG > 1 ? RP : 1];
     if constexpr (RG > 1) {
@@ -208,7 +211,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
       for (int p = 0; p < RP; ++p) {
         const int t = p * kRtRowsPerPass + RL * wave + ri;
         const int tt = (1 - h) * etaR + t;
-        xo[p] = load_global(tk + ((t < etaR && tt < eta) ? tt : 0));
+        xo[p] = ld<BATCH>(tk + ((t < etaR && tt < eta) ? tt : 0));
       }
     }
 #pragma unroll
@@ -232,8 +235,8 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
       ob[j] = 0.f;
       orn[j] = 1.f;
       if (lane == 0 && t < ot1) {
-        const int i = load_global(tk + t);
-        if (i >= 0 && (int64_t)i < a.m) { ob[j] = load_global(a.b + i); orn[j] = weighted_rn(a.r2, a.row_w, i); }
+        const int i = ld<BATCH>(tk + t);
+        if (i >= 0 && (int64_t)i < a.m) { ob[j] = ld<BATCH>(a.b + i); orn[j] = weighted_rn(a.r2, a.row_w, i); }
       }
     }
   };
@@ -294,7 +297,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
       for (int r = 0; r < CPL; ++r) {
         if (p * CPL + r < NPF || !son(r)) continue;
         const int q = sl + CL * r;  // clamped into the row: past the slice it meets x = 0
-        tile[p][r] = load_global_f4(rowp + 4 * (q < qlast ? q : qlast));
+        tile[p][r] = ld4<BATCH>(rowp + 4 * (q < qlast ? q : qlast));
       }
     }
   }
@@ -307,7 +310,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
     asm volatile("" : "+v"(tidl));
     const int tid = tidl, lane = tidl & 63, wave = tidl >> 6, sl = lane / RL, ri = lane % RL;
     const unsigned tag = (unsigned)(k + 1);
-    const float ak = a.alpha_k ? load_global(a.alpha_k + k) : a.alpha;
+    const float ak = a.alpha_k ? ld<BATCH>(a.alpha_k + k) : a.alpha;
     u64* xP = a.xP + (size_t)(k & 1) * G * eta;
     const bool has_next = k + 1 < a.K;
 
@@ -364,9 +367,9 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
         }
       }
     };
-    if (C <= 64) {
-      // one slice a lane: the wave's rows (kRtWaves apart) are polled together, one round trip
-      // for all of them (the same sums as row by row)
+    if (BATCH && C <= 64) {
+      // one slice a lane (a batched system): the wave's rows (kRtWaves apart) are polled
+      // together, one round trip for all of them (the same sums as row by row)
       const int tw = ot0 + wave;
       int nown = tw < ot1 ? (ot1 - tw + kRtWaves - 1) / kRtWaves : 0;
       if (nown > kOwnMax) nown = kOwnMax;
@@ -470,7 +473,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
         for (int r = 0; r < CPL; ++r) {
           if (p * CPL + r < NPF || !son(r)) continue;
           const int q = sl + CL * r;
-          tile[p][r] = load_global_f4(rowp + 4 * (q < qlast ? q : qlast));
+          tile[p][r] = ld4<BATCH>(rowp + 4 * (q < qlast ? q : qlast));
         }
       }
     };
@@ -524,7 +527,7 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
       for (int j = tid; j < wq * 4; j += kRtThreads) {
         const int64_t c = c0 + j;
         if (c < a.n && h == 0) {  // one copy of each slice counts
-          const double rf = (double)load_global(a.xref + c);
+          const double rf = (double)ld<BATCH>(a.xref + c);
           const double d = (double)xv[j] - rf;
           e2 += d * d;
           r2s += rf * rf;
@@ -570,8 +573,13 @@ __device__ __forceinline__ void rt_run(const DenseArgs<float>& a, const int g, c
     for (int j = tid; j < wq * 4; j += kRtThreads) {
       const int64_t c = c0 + j;
       if (c < a.n) {
-        store_global(a.x_star + c, xs[j]);
-        store_global(a.x + c, xv[j]);
+        if constexpr (BATCH) {
+          store_global(a.x_star + c, xs[j]);
+          store_global(a.x + c, xv[j]);
+        } else {
+          a.x_star[c] = xs[j];
+          a.x[c] = xv[j];
+        }
       }
     }
   if (g == 0 && tid == 0) a.status[1] = (int)k_done;
