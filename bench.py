@@ -205,7 +205,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep and time-to-plateau runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["batched", "multirhs", "adjoint", "csr", "lb", "bsk", "variants", "config0",
-                                       "floor"],
+                                       "floor", "gather"],
                     default=None,
                     help="run one secondary workload alone and print its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
@@ -257,6 +257,9 @@ def main():
         if args.only == "floor":
             sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
             out = floor_run(sysd["A"], torch.from_numpy(sysd["b"]).to(dev), dev, stream)
+        elif args.only == "gather":
+            sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
+            out = gather_run(sysd["A"], sysd["weights"], dev, stream)
         else:
             out = (fn(dev, stream, tune=not args.no_tune) if args.only in ("batched", "multirhs", "config0", "adjoint")
                    else fn(dev, stream))
@@ -390,6 +393,12 @@ def main():
 
     if not args.no_sweep:
         out["floor"] = floor_run(A, b, dev, stream, r2=r2)
+        out["gather"] = gather_run(A, weights, dev, stream)
+        g1 = [r for r in out["gather"]["runs"] if r["eta"] == eta and r["row_groups"] == 1
+              and r["layout"] == "register tile"]
+        if g1:
+            out["roofline"]["gather_ceiling_GBps"] = g1[0]["GB/s"]
+            out["roofline"]["frac_of_gather_ceiling"] = round(achieved / g1[0]["GB/s"], 4)
         out["sampler"] = sampler_run(A, dev, stream)
         out["config0"] = config0_run(dev, stream, tune=not args.no_tune)
         out["csr"] = csr_run(dev, stream)
@@ -416,6 +425,29 @@ def teardown():
     torch.cuda.synchronize()
     sys.stdout.flush()
     sys.stderr.flush()
+
+
+def gather_run(A, weights, dev, stream, etas=(1024, 256), groups=(1, 2, 4, 8)):
+    """The HBM reads of the register-tile solve alone (rsk_gather_rate_dense): for each eta the
+    column slices of the sampled rows that 256 workgroups in 1, 2, 4 or 8 row groups would read,
+    no exchange and no update; GB/s of eta * n * 4 bytes a step (median of 3 calls)."""
+    import torch
+    from paper_2203_10838_amd import inputs, rsk
+    out = []
+    for eta in etas:
+        K = max(20, int(4e9 / (eta * N * 4)))
+        idx = torch.from_numpy(inputs.index_stream(weights, K, eta, SEED + 5)).to(dev)
+        for rg in groups:
+            for lay in ((0, 1) if rg == 1 else (0,)):
+                rsk.gather_rate(A, idx, eta=eta, K=K, row_groups=rg, layout=lay)
+                ms = _median_ms(lambda: rsk.gather_rate(A, idx, eta=eta, K=K, row_groups=rg, layout=lay), stream)
+                out.append({"eta": eta, "row_groups": rg, "layout": ["whole pieces", "register tile"][lay],
+                            "piece_bytes": round(N * 4 * rg / 256), "us_per_step": round(ms * 1e3 / K, 3),
+                            "GB/s": round(K * eta * N * 4 / (ms * 1e-3) / 1e9, 1)})
+                log(f"[bench] gather {out[-1]}")
+        del idx
+    return {"workload": f"dense {M}x{N} float32, the register-tile solve's row pieces on 256 workgroups, "
+                        "no exchange, no update", "runs": out}
 
 
 def floor_run(A, b, dev, stream, K=400, r2=None):

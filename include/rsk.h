@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RSK_ABI_VERSION 5
+#define RSK_ABI_VERSION 6
 
 typedef enum { RSK_F32 = 0, RSK_F64 = 1 } rsk_dtype;
 
@@ -266,6 +266,28 @@ int32_t rsk_tune_erase(const rsk_tune_entry *key);                              
 int32_t rsk_tune_clear(int32_t path);                                            /* path < 0: every entry */
 int32_t rsk_tune_load(const char *path);                                         /* merge a cache file */
 int32_t rsk_tune_save(const char *path);
+
+/*
+ * Measurement, not a solve: the HBM reads of a float32 register-tile solve on
+ * `grid` workgroups in `row_groups` row groups (1, 2, 4 or 8), alone. For K
+ * steps, workgroup g reads the part of step k's sampled rows (index_stream,
+ * step-major, K * eta entries) that it would hold in such a solve: its row
+ * group's rows of the step and its column slice (whole 16-float units, the
+ * solve's XCD-aware slice order), with no exchange and no update. The time of
+ * the call against K * eta * n * 4 bytes is the rate HBM serves that pattern
+ * of row pieces at, the ceiling of the solve's own rate (eq. (rska) reads
+ * each sampled row once a step). sink: device float[grid * 512], each
+ * thread's sum of what it read (so the reads are used). layout 0: consecutive
+ * lanes read consecutive 16-byte chunks of one row's piece (one instruction
+ * covers whole pieces of a few rows); layout 1: the register tile's own lanes
+ * (one instruction reads 64 bytes of each of 16 rows; a row's piece takes
+ * several instructions; one row group, slices of at most 80 floats, eta <=
+ * 1024, else RSK_ERR_UNSUPPORTED). An index outside [0, m) reads row 0.
+ * Requires A float32, 16-byte aligned, n and ld multiples of 4, 1 <= eta <=
+ * 4096, grid <= 1024 a multiple of row_groups.
+ */
+int32_t rsk_gather_rate_dense(const rsk_dense *A, const int32_t *index_stream, int32_t eta, int64_t K, int32_t grid,
+                              int32_t row_groups, int32_t layout, float *sink, void *stream);
 
 /* Version of this ABI (RSK_ABI_VERSION). */
 int32_t rsk_abi_version(void);

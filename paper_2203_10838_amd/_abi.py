@@ -95,6 +95,7 @@ SIGNATURES = {
     "rsk_workspace_size_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, c_i32, ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_batched": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_i32, c_vp, c_sz, c_vp]),
     "rsk_plan_batched": (c_i32, [c_i32, c_i32, c_vp, c_i64, c_i32, c_vp, c_vp]),
+    "rsk_gather_rate_dense": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i32, c_i32, c_vp, c_vp]),
     "rsk_workspace_size_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_i32, ctypes.POINTER(RskParams),
                                             ctypes.POINTER(c_sz)]),
     "rsk_avg_solve_multirhs": (c_i32, [ctypes.POINTER(RskDense), c_vp, c_i32, ctypes.POINTER(RskParams), c_vp, c_vp,

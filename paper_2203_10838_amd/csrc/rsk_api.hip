@@ -1166,6 +1166,26 @@ int32_t rsk_tune_save(const char* path) {
   return ok ? RSK_OK : RSK_ERR_INVALID_ARG;
 }
 
+int32_t rsk_gather_rate_dense(const rsk_dense* A, const int32_t* index_stream, int32_t eta, int64_t K, int32_t grid,
+                              int32_t row_groups, int32_t layout, float* sink, void* stream) {
+  int32_t st = check_dense(A);
+  if (st) return st;
+  if (A->dtype != RSK_F32 || (A->n % 4) || (A->ld % 4) || (((uintptr_t)A->val) % 16)) return RSK_ERR_UNSUPPORTED;
+  if (!sink || (K > 0 && !index_stream) || eta < 1 || eta > 4096 || K < 0) return RSK_ERR_INVALID_ARG;
+  if (row_groups != 1 && row_groups != 2 && row_groups != 4 && row_groups != 8) return RSK_ERR_INVALID_ARG;
+  if (grid < row_groups || grid > 1024 || grid % row_groups || (layout != 0 && layout != 1)) return RSK_ERR_INVALID_ARG;
+  if (layout == 1) {
+    // the register tile's lanes: one row group, slices of at most 5 units of 16 floats, eta <= 1024
+    const int64_t nunits = (A->n / 4 + 3) / 4;
+    if (row_groups != 1 || eta > 1024 || (nunits + grid - 1) / grid > 5) return RSK_ERR_UNSUPPORTED;
+  }
+  if (K == 0) return RSK_OK;
+  return rsk::launch_gather_rate((const float*)A->val, A->m, A->ld, A->n, index_stream, eta, K, grid, row_groups,
+                                 layout, sink, (hipStream_t)stream) == hipSuccess
+             ? RSK_OK
+             : RSK_ERR_HIP;
+}
+
 int32_t rsk_abi_version(void) { return RSK_ABI_VERSION; }
 
 const char* rsk_status_string(int32_t s) {

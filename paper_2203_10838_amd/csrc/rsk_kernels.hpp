@@ -374,6 +374,9 @@ hipError_t launch_batched_rt(const rsk_batch_item* items, const int32_t* order, 
                              const int64_t* woff, u64* queue, u64* regions, const BatchWgTable& tab, int grid,
                              hipStream_t stream);
 hipError_t launch_zero_status(int* status, hipStream_t stream);
+// the gather of the register-tile solve alone (rsk_gather_rate_dense); sink: G * 512 floats
+hipError_t launch_gather_rate(const float* A, int64_t m, int64_t ld, int64_t n, const int32_t* idx, int eta, int64_t K,
+                              int G, int rg, int layout, float* sink, hipStream_t stream);
 
 // Linearized Bregman (full batch) and power iteration on A^T A. One pass reads A once with
 // kLbThreads threads a workgroup, chunks of vec elements (16 bytes, or 1 element when A is not

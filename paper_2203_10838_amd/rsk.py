@@ -126,6 +126,22 @@ def plan_dense(A: torch.Tensor, *, eta: int, K: int = 1, grid: int = 0, kernel: 
     return dict(zip(PLAN_FIELDS, [int(v) for v in out]))
 
 
+def gather_rate(A: torch.Tensor, index_stream: torch.Tensor, *, eta: int, K: int, grid: int = 256,
+                row_groups: int = 1, layout: int = 0, stream_offset: int = 0) -> torch.Tensor:
+    """Queue the gather of a float32 register-tile solve alone (rsk_gather_rate_dense): K steps of
+    the sampled rows' column slices that ``grid`` workgroups in ``row_groups`` row groups would
+    read, no exchange, no update; ``layout`` 0 reads whole pieces per instruction, 1 the register
+    tile's lanes. Returns the sink (grid * 512 floats); time the call with events."""
+    d = dense_desc(A)
+    _dev(index_stream, "index_stream", torch.int32, stream_offset + K * eta)
+    sink = torch.empty(grid * 512, dtype=torch.float32, device=A.device)
+    st = _lib().rsk_gather_rate_dense(ctypes.byref(d), index_stream.data_ptr() + 4 * stream_offset, int(eta), int(K),
+                                      int(grid), int(row_groups), int(layout), sink.data_ptr(), _stream())
+    if st:
+        raise RskError(st, "rsk_gather_rate_dense")
+    return sink
+
+
 def plan_multirhs(A: torch.Tensor, R: int, *, eta: int, K: int = 1, kernel: int = 0) -> dict:
     """The split rsk_avg_solve_multirhs would use (nothing is queued): S column splits of A_tau X
     (and the columns per split), S2 row splits of A_tau^T C, eta padded to a multiple of 64."""

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_host_only_calls():
     lib = _abi.load()
-    assert lib.rsk_abi_version() == 5
+    assert lib.rsk_abi_version() == 6
     assert lib.rsk_status_string(7) == b"RSK_ERR_NONFINITE"
     assert lib.rsk_status_string(99) == b"RSK_ERR_UNKNOWN"
 
