@@ -211,6 +211,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (reference point for HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library built-in choices)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched leg: skip the 512 sequential plain solves it is compared with")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG", "OUT_JSON"),
                     default=None,
                     help="host only, no GPU: write the traffic summary (profiles/dense_rt_traffic.json's format) "
@@ -261,8 +263,11 @@ def main():
             sysd = inputs.dense_system_device(M, N, S_NNZ, seed=SEED, noise_rel=NOISE, device=dev)
             out = gather_run(sysd["A"], sysd["weights"], dev, stream)
         else:
-            out = (fn(dev, stream, tune=not args.no_tune) if args.only in ("batched", "multirhs", "config0", "adjoint")
-                   else fn(dev, stream))
+            if args.only == "batched":
+                out = batched_run(dev, stream, plain=not args.no_plain, tune=not args.no_tune)
+            else:
+                out = (fn(dev, stream, tune=not args.no_tune) if args.only in ("multirhs", "config0", "adjoint")
+                       else fn(dev, stream))
         print(json.dumps({args.only: out}), flush=True)
         teardown()
         return
