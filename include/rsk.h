@@ -92,8 +92,10 @@ typedef struct {
   double tol;                  /* with the monitor: stop early once the relative error is <= tol (0 = never) */
   double *err_hist;            /* nullable device array, K/check_every entries (double) */
   void *y_out;                 /* nullable device array (m, dtype of A), in/out: y[tau_t] -= c_t, so x* = A^T y.
-                                  Summed with floating-point atomics: where a row is drawn more than once in a
-                                  step, y is reproducible to rounding only (x* and x stay bitwise reproducible) */
+                                  CSR: each row's slots of a step are applied once, in a fixed order, so y is
+                                  bitwise reproducible. Dense: summed with floating-point atomics, so where a
+                                  row is drawn more than once in a step y is reproducible to rounding only
+                                  (x* and x stay bitwise reproducible) */
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register
@@ -375,8 +377,10 @@ int32_t rsk_plan_dense(const rsk_dense *A, const rsk_params *p, int32_t *out);
  * in int64 fixed point with a per-step power-of-two quantum (2^-41 of the
  * step's largest contribution), so x* and x are bitwise reproducible for a
  * given kernel (y_out: see rsk_params). eta <= 4096.
- * Workspace: n + 1 int64 accumulators plus the grid kernel's barrier and
- * monitor words (rsk_workspace_size_csr), zeroed by the call.
+ * Workspace: n + 1 int64 accumulators, with y_out m int32 row counters (and
+ * for the grid kernel eta coefficients), plus the grid kernel's barrier and
+ * monitor words (rsk_workspace_size_csr, which depends on whether y_out is
+ * set), zeroed by the call.
  * A column index outside [0, n) in a sampled row is RSK_ERR_INDEX_RANGE.
  */
 int32_t rsk_avg_solve_csr(const rsk_csr *A, const void *b, const rsk_params *p, void *x_star, void *x,

@@ -361,12 +361,13 @@ int32_t check_csr(const rsk_csr* A) {
 }
 
 // CSR plan: one workgroup (small steps) or the multi-workgroup kernel.
-// Workspace: n + 1 int64 column accumulators (the last a spare slot), then for
-// the grid kernel the barrier counter, the step-parity exponent words and the
-// monitor words.
+// Workspace: n + 1 int64 column accumulators (the last a spare slot); with a
+// dual output, m per-row slot counters and (grid kernel) the step's eta
+// coefficients; then for the grid kernel the barrier counter, the step-parity
+// exponent words and the monitor words.
 struct CsrPlan {
   int kernel, G;
-  size_t offBar, offEmax, offM, bytes;
+  size_t offYcnt, offCy, offBar, offEmax, offM, bytes;
 };
 
 template <typename T>
@@ -378,6 +379,11 @@ int32_t plan_csr(const rsk_csr* A, const rsk_params* p, CsrPlan* pl) {
   pl->kernel = grid ? 2 : 1;
   pl->G = 1;
   size_t o = align256((size_t)(A->n + 1) * sizeof(long long));
+  pl->offYcnt = pl->offCy = 0;
+  if (p->y_out) {
+    pl->offYcnt = o; o = align256(o + (size_t)A->m * sizeof(int));
+    if (grid) { pl->offCy = o; o = align256(o + (size_t)p->eta * sizeof(T)); }
+  }
   pl->offBar = pl->offEmax = pl->offM = o;
   if (grid) {
     int G = p->grid > 0 ? p->grid : (p->eta + rpp - 1) / rpp;
@@ -413,6 +419,8 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
   a.xref = (const T*)p->x_ref; a.check_every = p->x_ref ? p->check_every : 0; a.tol = p->tol;
   a.err_hist = p->err_hist; a.status = p->status_dev;
   a.acc = (long long*)ws;
+  a.ycnt = p->y_out ? (int*)(w + pl.offYcnt) : nullptr;
+  a.cy = p->y_out && pl.offCy ? (T*)(w + pl.offCy) : nullptr;
   a.G = pl.G;
   a.bar = (u64*)(w + pl.offBar);
   a.emax = (int*)(w + pl.offEmax);

@@ -16,6 +16,11 @@
 //      that swaps it out of the accumulator: x*_j -= total*q, x_j = S_lambda(x*_j).
 //      The quantisation error is below 2^-41 of the step's largest
 //      contribution, far under float32 resolution of the update.
+//   3. the optional dual output y (y_i -= c_t for every slot t of row i, the
+//      dual update at the start of Sec. 4) is applied once per row and step:
+//      each slot counts itself on an integer per-row counter, and the slot
+//      whose increment found zero applies all of the row's coefficients in
+//      slot order, so y is bitwise reproducible however the slots race.
 // x*, x and the accumulators live in global memory and are shared only within
 // the workgroup, so workgroup-scope atomics order them (device-scope atomics
 // would cost a serialized memory round trip each).
@@ -30,6 +35,7 @@ constexpr int kCsrThreads = 512;
 constexpr int kCsrWaves = kCsrThreads / 64;
 constexpr int kRowChunk = 32;   // nonzeros of a row a thread holds in registers
 constexpr int kSub = 8;         // swaps in flight per thread when applying totals
+static_assert(kCsrMaxEta <= 32 * kCsrThreads, "a thread's y-owner bits fit one word");
 
 template <typename T>
 __device__ __forceinline__ T ld_wg(const T* p) {
@@ -126,13 +132,14 @@ __global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
     const T ak = a.alpha_k ? a.alpha_k[k] : a.alpha;
     const int32_t* tk = a.idx + k * (int64_t)eta;
     int lerr = 0;
+    unsigned yown = 0;  // bit s: this thread's slot tid + s * kCsrThreads applies its row's y update
 
     // 1. residual and coefficient of each sampled row: r_t = sum_p val_p x[col_p] - b, c_t
     int jc[kRowChunk];
     T vv[kRowChunk];
     int64_t p0 = 0, p1 = 0;
     double vmax = 0.0;
-    for (int t = tid; t < eta; t += kCsrThreads) {
+    for (int t = tid, s = 0; t < eta; t += kCsrThreads, ++s) {
       const int i = tk[t];
       if (i < 0 || (int64_t)i >= a.m) { lerr = ST_INDEX; continue; }
       p0 = a.row_ptr[i];
@@ -156,7 +163,8 @@ __global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
       if (rn == T(0)) { c = T(NAN); lerr = ST_ZERO_ROW; }
       else c = (ak / T(eta)) * (dot - a.b[i]) / rn;
       cs[t] = c;
-      if (a.y) atomicAdd(&a.y[i], -c);
+      if (a.y && __hip_atomic_fetch_add(a.ycnt + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+        yown |= 1u << s;
       // the step's largest contribution fixes the quantum
       for (int64_t q = 0; q < p1 - p0; q += kRowChunk) {
         if (!(resident && q == 0)) load_chunk(a, p0, p1, q, jc, vv);
@@ -176,6 +184,23 @@ __global__ __launch_bounds__(kCsrThreads) void rska_csr_single(CsrArgs<T> a) {
     const int fl = block_or(orw, (lerr ? 1 : 0) | (bad ? 2 : 0), k);
     if (fl & 1) { stop_code = ST_INDEX; break; }
     if (fl & 2) { stop_code = ST_NONFINITE; break; }
+    // dual output: the counters are final after the barrier; the owner takes the row's count
+    // (resetting it for the next step) and subtracts its coefficients in slot order
+    if (a.y) {
+      for (int t = tid, s = 0; t < eta; t += kCsrThreads, ++s) {
+        if (!((yown >> s) & 1u)) continue;
+        const int i = tk[t];
+        const int cnt = __hip_atomic_exchange(a.ycnt + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        T yi = ld_wg(a.y + i);
+        if (cnt == 1) {
+          yi -= cs[t];
+        } else {
+          for (int u = 0; u < eta; ++u)
+            if (tk[u] == i) yi -= cs[u];
+        }
+        st_wg(a.y + i, yi);
+      }
+    }
     double gmax = 0.0;
     for (int w = 0; w < kCsrWaves; ++w) gmax = fmax(gmax, wmax[w]);
     // power-of-two quantum q = 2^(e-40): |v/q| < 2^41
@@ -256,8 +281,10 @@ template hipError_t launch_csr<double>(CsrArgs<double>&, hipStream_t);
 //      (integer adds commute: the totals do not depend on atomic order);  barrier
 //   C. every touched column applied once, by the lane that swaps its nonzero
 //      total out of the accumulator: x*_j -= total q, x_j = S_lambda(x*_j); barrier
-// x* and x are bitwise reproducible (the dots use a fixed lane order); the optional dual y
-// is summed with float atomics, reproducible to rounding where a row repeats within a step.
+// x* and x are bitwise reproducible (the dots use a fixed lane order). The optional dual y
+// is too: after barrier A, one slot per sampled row (the one whose increment of the row's
+// integer counter found zero) subtracts the coefficients of all the row's slots, gathered by
+// its 32 lanes in a fixed order from the step's coefficient array.
 // ---------------------------------------------------------------------------
 
 namespace {
@@ -346,6 +373,7 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
   constexpr int RPP = kCsrGridRowsPerPass;
   __shared__ T cl[kCsrGridMaxPasses * RPP];
   __shared__ int il[kCsrGridMaxPasses * RPP];
+  __shared__ int yo[kCsrGridMaxPasses * RPP];  // the slot applies its row's y update
   __shared__ double wmax[kGridThreads / 64];
   __shared__ double mon[2 * (kGridThreads / 64) + 2];
   const int g = blockIdx.x, G = a.G, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -395,7 +423,18 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
           if (!isfinite(c) && !lerr) lerr = ST_NONFINITE;
         }
         for (int64_t q = r0 + p; q < r1; q += 32) vmax = fmax(vmax, fabs((double)(c * a.val[q])));
-        if (p == 0) { cl[ps * RPP + hw] = c; il[ps * RPP + hw] = i; }
+        if (p == 0) {
+          cl[ps * RPP + hw] = c;
+          il[ps * RPP + hw] = i;
+          if (a.y) {
+            int own = 0;
+            if (i >= 0) {
+              st_ag(a.cy + t, c);
+              own = __hip_atomic_fetch_add(a.ycnt + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+            }
+            yo[ps * RPP + hw] = own;
+          }
+        }
       }
     }
     if (lerr) set_status(a.status, lerr);
@@ -412,6 +451,30 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
     if (ld_ag(a.status)) { stop_code = -1; break; }  // the fault was recorded by the workgroup that saw it
     const int eb = ld_ag(a.emax + (k & 1));
     if (g == 0 && tid == 0) st_ag(a.emax + ((k + 1) & 1), 0);  // read by everyone two barriers ago
+
+    // dual output (the counters and coefficients are complete after barrier A): the owning
+    // slot takes its row's count, resetting it for the next step; a repeated row's 32 lanes
+    // collect the coefficients of its slots, each lane in slot order, then a fixed-order sum
+    if (a.y) {
+      for (int ps = 0; ps < passes; ++ps) {
+        const int t = ps * RPP * G + g * RPP + hw;
+        if (t < eta && yo[ps * RPP + hw]) {  // uniform over the row's 32 lanes
+          const int i = il[ps * RPP + hw];
+          int cnt = 0;
+          if (p == 0) cnt = __hip_atomic_exchange(a.ycnt + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          cnt = __shfl(cnt, lane & 32);
+          T sc = T(0);
+          if (cnt == 1) {
+            if (p == 0) sc = cl[ps * RPP + hw];
+          } else {
+            for (int u = p; u < eta; u += 32)
+              if (tk[u] == i) sc += ld_ag(a.cy + u);
+          }
+          sc = sum32(sc);
+          if (p == 0) st_ag(a.y + i, ld_ag(a.y + i) - sc);
+        }
+      }
+    }
 
     if (eb > 0) {
       const int e = eb - kEBias;
@@ -444,7 +507,6 @@ __global__ __launch_bounds__(kGridThreads) void rska_csr_grid(CsrArgs<T> a) {
               st_ag(a.x + j, shrink(z, a.lambda));
             }
           }
-          if (a.y && p == 0) atomicAdd(&a.y[i], -cl[ps * RPP + hw]);
         }
       }
     } else {

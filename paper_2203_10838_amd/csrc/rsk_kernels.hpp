@@ -132,6 +132,8 @@ struct CsrArgs {
   double* err_hist;
   int* status;
   long long* acc;         // n + 1 int64 accumulators (the last a spare), zero on entry and on exit
+  int* ycnt;              // [m] slots of the current step per row (y only; zero on entry and between steps)
+  T* cy;                  // [eta] the step's coefficients by slot (grid kernel, y only)
   // grid kernel only
   int G;                  // workgroups
   u64* bar;               // grid barrier counter (zero on entry)

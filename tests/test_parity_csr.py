@@ -67,6 +67,33 @@ def test_csr_ragged_rows_and_determinism(cuda, rsk_lib, kernel):
 
 
 @KERNELS
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f64", 1e-10)])
+def test_csr_dual_output_repeated_rows_bitwise(cuda, rsk_lib, kernel, dtype, tol):
+    """y_i -= c_t for every slot of row i (the dual update at the start of Sec. 4) on a stream
+    where most steps sample some row several times (300 rows, eta = 200): two runs give the same
+    bits, and y matches the oracle's from a non-zero y_0, element by element."""
+    import torch
+    m = 300
+    c = inputs.csr_system(m, 700, 9, 10, seed=31, dtype=dtype)
+    K, eta = 120, 200
+    idx = _stream(c, K, eta, 32)
+    steps = idx.reshape(K, eta)
+    assert sum(len(np.unique(r)) < eta for r in steps) == K  # every step repeats a row
+    y0 = np.random.default_rng(33).standard_normal(m).astype(c["val"].dtype)
+    ys = []
+    for _ in range(2):
+        y = _t(y0, cuda)
+        r = _solve(c, idx, cuda, lam=0.4, eta=eta, alpha=60.0, K=K, y_out=y, kernel=kernel)
+        assert r.status == 0 and r.k_done == K
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    ref = oracle.rska_csr(c["row_ptr"], c["col"], c["val"], c["n"], c["b"], 0.4, eta, 60.0, K, idx, want_y=True,
+                          y0=y0)
+    check_iterate(r.x_star, r.x, ref, 0.4, tol, min_support=3)
+    check_vec(ys[0], ref["y"], tol, what="y")
+
+
+@KERNELS
 def test_csr_resume_is_exact(cuda, rsk_lib, kernel):
     import torch
     c = inputs.csr_system(4000, 3000, 12, 20, seed=8)
