@@ -656,7 +656,9 @@ template <typename T>
 int32_t lb_layout(const rsk_dense* A, LbLayout* L) {
   constexpr int V = rsk::kLbVec<T>;
   L->vec = (((uintptr_t)A->val) % 16 == 0 && A->ld % V == 0) ? V : 1;
-  if (!rsk::lb_plan<T>(A->n, L->vec, &L->cpt, &L->lds, &L->G, &L->nstride)) return RSK_ERR_UNSUPPORTED;
+  const int planned = rsk::lb_plan<T>(A->n, L->vec, &L->cpt, &L->lds, &L->G, &L->nstride);
+  if (planned < 0) return RSK_ERR_HIP;
+  if (planned == 0) return RSK_ERR_UNSUPPORTED;
   L->offPart = 0;
   L->offR = align256((size_t)L->G * L->nstride * sizeof(T));
   L->bytes = L->offR + align256((size_t)L->G * sizeof(double));

@@ -508,6 +508,7 @@ static void* lb_pass_fn(int vec, int cpt) {
 }
 
 // vec: kLbVec<T> (A 16-byte aligned, ld a multiple of kLbVec) or 1.
+// Returns 1 when planned, 0 when the shape is not supported, -1 when a HIP query failed.
 template <typename T>
 int lb_plan(int64_t n, int vec, int* cpt, size_t* lds, int* grid, int64_t* nstride) {
   const int64_t nch = (n + vec - 1) / vec;
@@ -519,13 +520,13 @@ int lb_plan(int64_t n, int vec, int* cpt, size_t* lds, int* grid, int64_t* nstri
   *nstride = nch * vec;
   *lds = (size_t)nch * vec * sizeof(T);
   void* fn = lb_pass_fn<T>(vec, *cpt);
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)*lds) != hipSuccess) return 0;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)*lds) != hipSuccess) return -1;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLbThreads, *lds) != hipSuccess || per_cu < 1)
-    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLbThreads, *lds) != hipSuccess) return -1;
+  if (per_cu < 1) return 0;
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
   *grid = per_cu * cus;
   return 1;
 }
