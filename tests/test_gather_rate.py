@@ -9,14 +9,16 @@ from paper_2203_10838_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-@pytest.mark.parametrize("m,n,eta,K,grid,rg", [(512, 1024, 40, 3, 16, 1), (700, 2000, 129, 4, 64, 2),
-                                               (300, 160, 7, 5, 8, 8), (2000, 20000, 1024, 2, 256, 1)])
+_SHAPES = [(512, 1024, 40, 3, 16, 1), (700, 2000, 129, 4, 64, 2), (300, 160, 7, 5, 8, 8), (2000, 20000, 1024, 2, 256, 1)]
+# layout 1 (the register tile's own lanes) takes one row group and slices of at most 80 floats
+_CASES = [(*sh, layout) for sh in _SHAPES for layout in (0, 1)
+          if layout == 0 or (sh[5] == 1 and -(-(sh[1] // 4) // 4) <= 5 * sh[4])]
+
+
+@pytest.mark.parametrize("m,n,eta,K,grid,rg,layout", _CASES)
 def test_gather_reads_every_sampled_row_once(cuda, rsk_lib, m, n, eta, K, grid, rg, layout):
     import torch
     from paper_2203_10838_amd import rsk
-    if layout == 1 and (rg != 1 or -(-(n // 4) // 4) > 5 * grid):
-        pytest.skip("the register tile's lanes take one row group and slices of at most 80 floats")
     rng = np.random.default_rng(m + n)
     A = rng.standard_normal((m, n)).astype(np.float32)
     idx = inputs.index_stream(np.ones(m), K, eta, m + 1)
