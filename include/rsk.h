@@ -241,7 +241,8 @@ int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
  *   path RSK_TUNE_DENSE:    key (dtype, m, n, eta);    v0 = kernel (1..3), v1 = grid.
  *   path RSK_TUNE_MULTIRHS: key (dtype, m, n, eta, R); v0 = S (splits of the n columns in
  *                           A_tau X), v1 = S2 (row splits of A_tau^T C: 1, 2, 4 or 8), v2 = the
- *                           forward's kernel (1 step kernels, 2 one persistent launch; 0 = built-in).
+ *                           kernel (1 step kernels, 2 one persistent launch, 3 wide-tile step
+ *                           kernels; 0 = built-in). The adjoint takes the tile of v2 = 3 as well.
  *   path RSK_TUNE_BATCHED:  key (dtype, m = the class's upper bound on a system's step bytes
  *                           eta * n * element size; n = eta = 0; R = the batched launch: 0
  *                           general kernel, 2 register tile); v0 = row bytes per workgroup for
@@ -451,12 +452,15 @@ int32_t rsk_plan_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *item
  *   X       device, n x R row-major, out.
  * Requires R % 4 == 0, n % 4 == 0, ld % 4 == 0, eta <= 4096, A 16-byte aligned; the
  * monitor and y_out are not supported here (RSK_ERR_UNSUPPORTED).
- * p->kernel: 1 = the step kernels (four launches per step), 2 = one persistent
- * cooperative launch for all K steps (the same products and sums as the step
- * kernels, tiles passed between workgroups through device-coherent stores and
- * per-tile counters), 0 = a tuned choice (rsk_tune_*), else 1. Device faults
- * and status_dev follow the single-RHS conventions (with kernel 2, X* and X
- * are unspecified after a fault).
+ * p->kernel: 1 = the step kernels (four launches per step, 64 x 64 product
+ * tiles), 2 = one persistent cooperative launch for all K steps (the same
+ * products and sums as the step kernels, tiles passed between workgroups
+ * through device-coherent stores and per-tile counters), 3 = the step kernels
+ * with wide product tiles (128 x 128, or 128 x 64 when R <= 64; eta padded to
+ * a multiple of 128), 0 = a tuned choice (rsk_tune_*), else 1. Kernels 1 and 3
+ * compute the same iteration with differently blocked sums (equal to rounding).
+ * Device faults and status_dev follow the single-RHS conventions (with kernel
+ * 2, X* and X are unspecified after a fault).
  */
 int32_t rsk_workspace_size_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, size_t *bytes);
 int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, const rsk_params *p, void *X_star,
@@ -466,9 +470,9 @@ int32_t rsk_avg_solve_multirhs(const rsk_dense *A, const void *B, int32_t R, con
  * The split of rsk_avg_solve_multirhs's two products for A, R and p, without
  * running it. out: host int32[5] = { S: splits of the n columns in A_tau X
  * (fixed-order sum of S partials), columns per split, S2: splits of a step's
- * rows in A_tau^T C (1: one workgroup per 64 x 64 output tile over all rows),
- * eta rounded up to a multiple of 64, the kernel (1 step kernels, 2 one
- * persistent launch) }.
+ * rows in A_tau^T C (1: one workgroup per output tile over all rows), eta
+ * rounded up to a multiple of the tile edge (64, or 128 for kernel 3), the
+ * kernel (1 step kernels, 2 one persistent launch, 3 wide-tile step kernels) }.
  */
 int32_t rsk_plan_multirhs(const rsk_dense *A, int32_t R, const rsk_params *p, int32_t *out);
 

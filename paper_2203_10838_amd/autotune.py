@@ -146,14 +146,14 @@ def multirhs_candidates(A: torch.Tensor, R: int, eta: int) -> list:
     max_s = max(1, (n + 63) // 64)        # a tuned split keeps at least 64 columns (one stage)
     svals = sorted({s for s in (1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128) if s <= max_s})
     s2vals = [s2 for s2 in (1, 2, 4, 8) if s2 <= max(1, (eta + 15) // 16)]
-    return [(s, s2, kernel) for kernel in (1, 2) for s in svals for s2 in s2vals]
+    return [(s, s2, kernel) for kernel in (1, 2, 3) for s in svals for s2 in s2vals]
 
 
 def tune_multirhs(A: torch.Tensor, B: torch.Tensor, *, eta: int, lam: float, alpha: float,
                   index_stream: torch.Tensor, steps: int = 4, reps: int = 3, candidates: Optional[Iterable] = None,
                   install: bool = True, rownorm2_t: Optional[torch.Tensor] = None) -> dict:
     """Time (S, S2, kernel) candidates of the multi-RHS forward (kernel 1: step kernels, 2: one persistent
-    launch); install the fastest for (dtype, m, n, eta, R)."""
+    launch, 3: step kernels with wide product tiles); install the fastest for (dtype, m, n, eta, R)."""
     m, n = A.shape
     R = B.shape[1]
     dtype = rsk._dtype_code(A)

@@ -434,7 +434,9 @@ int32_t solve_csr_t(const rsk_csr* A, const void* b, const rsk_params* p, void* 
 struct MultiPlan {
   int S, eta_pad, S2;
   int64_t kspan;
-  int kernel;       // 1: step kernels (four per step), 2: one persistent launch for all K steps
+  int kernel;       // 1: step kernels (four per step), 2: one persistent launch for all K steps,
+                    // 3: the step kernels with wide product tiles (128 x 128, or 128 x 64 for R <= 64)
+  int tile;         // 64 (kernels 1, 2) or 128 (kernel 3): the tile edge of the products
   int pS;           // persistent launch: its split of the n columns (kspan rounded up to 64)
   int64_t pkspan;
   size_t offY, offC, offW, offCnt, cnt_words, bytes;
@@ -446,11 +448,16 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   if ((R % 4) || (A->n % 4) || (A->ld % 4) || (((uintptr_t)A->val) % 16)) return RSK_ERR_UNSUPPORTED;
   if (p->x_ref || p->y_out || p->check_every) return RSK_ERR_UNSUPPORTED;
   if (p->eta > 4096) return RSK_ERR_UNSUPPORTED;  // the sampled rows of a step are staged in LDS
-  pl->eta_pad = (p->eta + 63) / 64 * 64;
-  const int tiles = (pl->eta_pad / 64) * ((R + 63) / 64);
+  if (p->kernel < 0 || p->kernel > 3) return RSK_ERR_INVALID_ARG;
   const int cus = device_cus() > 0 ? device_cus() : 256;
   rsk_tune_entry te;
   const bool tuned = tune_find(RSK_TUNE_MULTIRHS, A->dtype, A->m, A->n, p->eta, R, &te);
+  // the kernel: p->kernel 1, 2 or 3 as asked, else a tuned choice, else the step kernels
+  pl->kernel = p->kernel >= 1 ? p->kernel : (tuned && te.v2 >= 1 && te.v2 <= 3 ? (int)te.v2 : 1);
+  pl->tile = pl->kernel == 3 ? 128 : 64;
+  const int tn = pl->tile == 128 && R <= 64 ? 64 : pl->tile;  // the R edge of a product tile
+  pl->eta_pad = (p->eta + pl->tile - 1) / pl->tile * pl->tile;
+  const int tiles = (pl->eta_pad / pl->tile) * ((R + tn - 1) / tn);
   int S = (3 * cus + tiles - 1) / tiles;  // about three workgroups per CU for the n-long products
   if (S >= 8) S = (S + 7) / 8 * 8;        // whole XCD rounds: the tiles of a split share one L2
   if (tuned && te.v0 >= 1) S = (int)(te.v0 < 4096 ? te.v0 : 4096);
@@ -463,7 +470,7 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   pl->S = (int)((A->n + pl->kspan - 1) / pl->kspan);
   // the A_tau^T products write n x R: with fewer 64 x 64 tiles than CUs their sampled rows
   // are split over S2 workgroups (at least 64 rows each) and summed in a second kernel
-  const int att_tiles = (int)((A->n + 63) / 64) * ((R + 63) / 64);
+  const int att_tiles = (int)((A->n + pl->tile - 1) / pl->tile) * ((R + tn - 1) / tn);
   int S2 = cus / att_tiles;
   // at least 64 rows a split by the built-in rule, at least 16 for a tuned split
   const int max_s2 = tuned && te.v1 >= 1 ? (p->eta + 15) / 16 : (p->eta + 63) / 64;
@@ -472,9 +479,6 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   if (S2 > max_s2) S2 = max_s2;
   S2 = S2 >= 8 ? 8 : S2 >= 4 ? 4 : S2 >= 2 ? 2 : 1;  // the reduction kernels take 2, 4 or 8
   pl->S2 = S2;
-  // the kernel: p->kernel 1 or 2 as asked, else a tuned choice, else the step kernels
-  pl->kernel = p->kernel == 1 || p->kernel == 2 ? p->kernel : (tuned && (te.v2 == 1 || te.v2 == 2) ? (int)te.v2 : 1);
-  if (p->kernel == 3) return RSK_ERR_INVALID_ARG;
   pl->pkspan = (pl->kspan + 63) / 64 * 64;
   pl->pS = (int)((A->n + pl->pkspan - 1) / pl->pkspan);
   const int64_t gt = pl->eta_pad / 64, gr = (R + 63) / 64, gn = (A->n + 63) / 64;
@@ -581,7 +585,7 @@ void fill_multirhs(const rsk_dense* A, const void* B, int32_t R, const rsk_param
   a.x_star = (float*)X_star; a.x = (float*)X; a.warm = p->warm_start ? 1 : 0;
   a.status = p->status_dev;
   a.Y = (float*)(w + pl.offY); a.C = (float*)(w + pl.offC);
-  a.S = pl.S; a.eta_pad = pl.eta_pad; a.kspan = pl.kspan;
+  a.S = pl.S; a.eta_pad = pl.eta_pad; a.kspan = pl.kspan; a.tile = pl.tile;
   // the row-split epilogue moves float4 of X* and X: used only when both are 16-byte aligned
   const bool al = ((uintptr_t)X_star) % 16 == 0 && ((uintptr_t)X) % 16 == 0;
   a.S2 = (pl.S2 > 1 && al) ? pl.S2 : 1;

@@ -176,6 +176,7 @@ struct MultiRhsArgs {
   float* Wp = nullptr;    // S2 x n x R partials of A_tau^T C when S2 > 1
   unsigned* ycnt = nullptr;  // per 64 x 64 tile of R_tau: split partials counted (zero before a solve)
   unsigned* wcnt = nullptr;  // per 64 x 64 tile of A_tau^T C: row-split partials counted (zero before a solve)
+  int tile = 64;          // product tile edge of the step kernels: 64, or 128 (eta_pad a multiple of 128)
 };
 // ckpt (nullable): x*_k is copied to ckpt[k / ckpt_every] before every step k with k % ckpt_every == 0.
 hipError_t launch_multirhs(const MultiRhsArgs& a, hipStream_t stream, float* ckpt = nullptr, int64_t ckpt_every = 1);

@@ -46,25 +46,45 @@ struct Stage {
   float4 a[4], b[4];
 };
 
+// A stage loaded without branches: every load reads a valid address, and the positions that lie
+// outside the product are zeroed only when the stage is stored to LDS (a select right after the
+// load would wait for the load there and then, instead of under the current stage's products).
+struct StageM {
+  float4 a[4], b[4];
+  bool ka[4], kb[4];
+};
+
+// v where keep holds, else zeros; element-wise selects (a select of the whole vector would go
+// through private memory)
+__device__ __forceinline__ float4 keep4(bool keep, float4 v) {
+  return make_float4(keep ? v.x : 0.f, keep ? v.y : 0.f, keep ? v.z : 0.f, keep ? v.w : 0.f);
+}
+
 template <bool A_ROWS>
 __device__ __forceinline__ void mma_stage_t(const float* As, const float (*Bs)[LDP], int wm, int wn, int lane,
                                             f4 (&acc)[2][2]) {
   const int li = lane & 15, lk = lane >> 4;
+  // Every fragment of the stage is read before the first product, so the reads' latencies
+  // overlap each other and the products instead of stalling each group of four products.
+  float a[SK / 4][2], b[SK / 4][2];
 #pragma unroll
-  for (int k0 = 0; k0 < SK; k0 += 4) {
-    float a[2], b[2];
+  for (int s = 0; s < SK / 4; ++s) {
+    const int k0 = 4 * s;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int m = wm * 32 + i * 16 + li;
-      a[i] = A_ROWS ? As[m * LDA + k0 + lk] : As[(k0 + lk) * LDP + m];
+      a[s][i] = A_ROWS ? As[m * LDA + k0 + lk] : As[(k0 + lk) * LDP + m];
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = Bs[k0 + lk][wn * 32 + j * 16 + li];
+    for (int j = 0; j < 2; ++j) b[s][j] = Bs[k0 + lk][wn * 32 + j * 16 + li];
+  }
+  __builtin_amdgcn_sched_barrier(0);  // keeps the scheduler from interleaving the reads back in
+#pragma unroll
+  for (int s = 0; s < SK / 4; ++s)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
-  }
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[s][i], b[s][j], acc[i][j]);
 }
 
 __device__ __forceinline__ void mma_stage(const float (*As)[LDP], const float (*Bs)[LDP], int wm, int wn, int lane,
@@ -82,25 +102,36 @@ __device__ __forceinline__ void att_mainloop(const float* __restrict__ A, int64_
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = tid >> 4, lc = (tid & 15) * 4;
   const bool colok = j0 + lc < n, rok = r0 + lc < R;
-  auto load = [&](int tb, Stage& st) {
+  // Branch-free: every load reads a valid address (out-of-range positions read row taus[0],
+  // column 0 or C row 0) and the value is replaced by zero afterwards, so the eight loads of a
+  // stage issue back to back.
+  const int64_t jc = colok ? j0 + lc : 0;
+  const int rc = rok ? r0 + lc : 0;
+  auto load = [&](int tb, StageM& st) {
+    int rows[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int t = tb + lr + 16 * i;
+      rows[i] = taus[t < eta ? t : 0];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int t = tb + lr + 16 * i;
       const bool ok = t < eta;
-      st.a[i] = (ok && colok) ? *reinterpret_cast<const float4*>(A + (int64_t)taus[ok ? t : 0] * ld + j0 + lc)
-                              : make_float4(0.f, 0.f, 0.f, 0.f);
-      st.b[i] = (ok && rok) ? *reinterpret_cast<const float4*>(C + (size_t)t * R + r0 + lc)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
+      st.a[i] = *reinterpret_cast<const float4*>(A + (int64_t)rows[i] * ld + jc);
+      st.b[i] = *reinterpret_cast<const float4*>(C + (size_t)(ok ? t : 0) * R + rc);
+      st.ka[i] = ok && colok;
+      st.kb[i] = ok && rok;
     }
   };
-  Stage st;
-  load(0, st);
+  StageM st;
+  if (eta > 0) load(0, st);
   for (int tb = 0; tb < eta; tb += SK) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      *reinterpret_cast<float4*>(&As[lr + 16 * i][lc]) = st.a[i];
-      *reinterpret_cast<float4*>(&Bs[lr + 16 * i][lc]) = st.b[i];
+      *reinterpret_cast<float4*>(&As[lr + 16 * i][lc]) = keep4(st.ka[i], st.a[i]);
+      *reinterpret_cast<float4*>(&Bs[lr + 16 * i][lc]) = keep4(st.kb[i], st.b[i]);
     }
     __syncthreads();
     if (tb + SK < eta) load(tb + SK, st);
@@ -138,9 +169,13 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
                                                   int gt, int gr, int S, int* status, int64_t m, int64_t k) {
   __shared__ __align__(16) float Ar[BM][LDA];
   __shared__ __align__(16) float Bs[SK][LDP];
+  // With the index check (m > 0) the fault word is read here and used only where it matters (the
+  // index fault and the progress count): its round trip overlaps the index and first operand
+  // loads, and after an earlier fault the partials are computed all the same and never used.
+  // Without the check the rows may only be read when no fault is recorded.
   __shared__ int flag;
-  if (any_fault(status, &flag)) return;
-  if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicMax(status + 1, (int)k);
+  if (m == 0 && any_fault(status, &flag)) return;
+  const int st0 = status[0];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int id = blockIdx.x, T = gt * gr;
@@ -171,19 +206,25 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
     if (m > 0 && (row < 0 || (int64_t)row >= m)) { bad = 1; row = 0; }
     arow[i] = A + (int64_t)row * ld;
   }
-  if (bad) {
+  if (bad && st0 == 0) {
     set_status(status, ST_INDEX);
     atomicMax(status + 1, (int)k);
   }
+  // steps before k completed (status[1] only grows; a fault at step k records k as well)
+  if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0 && st0 == 0) atomicMax(status + 1, (int)k);
   const bool rok = r0 + lc < R;
-  auto load = [&](int64_t jb, Stage& st) {
+  const int rc = rok ? r0 + lc : 0;
+  // Branch-free: positions past the split's columns read column 0 (of the same row, or row 0
+  // of X) and are replaced by zero, so the eight loads of a stage issue back to back.
+  auto load = [&](int64_t jb, StageM& st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t c = jb + lc;
-      st.a[i] = (aok[i] && c < j_end) ? *reinterpret_cast<const float4*>(arow[i] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
       const int64_t jj = jb + lr + 16 * i;
-      st.b[i] = (jj < j_end && rok) ? *reinterpret_cast<const float4*>(X + jj * R + r0 + lc)
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      st.a[i] = *reinterpret_cast<const float4*>(arow[i] + (c < j_end ? c : 0));
+      st.b[i] = *reinterpret_cast<const float4*>(X + (jj < j_end ? jj : 0) * R + rc);
+      st.ka[i] = aok[i] && c < j_end;
+      st.kb[i] = jj < j_end && rok;
     }
   };
 
@@ -193,15 +234,15 @@ __global__ __launch_bounds__(NTH) void gemm_at_x(const float* __restrict__ A, in
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  Stage st;
+  StageM st;
   load(j_begin, st);
   for (int64_t jb = j_begin; jb < j_end; jb += SK) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = lr + 16 * i;
-      *reinterpret_cast<float4*>(&Ar[m][lc]) = st.a[i];
-      *reinterpret_cast<float4*>(&Bs[m][lc]) = st.b[i];
+      *reinterpret_cast<float4*>(&Ar[m][lc]) = keep4(st.ka[i], st.a[i]);
+      *reinterpret_cast<float4*>(&Bs[m][lc]) = keep4(st.kb[i], st.b[i]);
     }
     __syncthreads();
     if (jb + SK < j_end) load(jb + SK, st);
@@ -244,7 +285,7 @@ __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, con
                             const float* __restrict__ B, int R, const float* __restrict__ r2,
                             const float* __restrict__ row_w, float alpha, const float* __restrict__ alpha_k,
                             int64_t k, float* __restrict__ C, float* __restrict__ Rh, int* status) {
-  if (status[0]) return;
+  const int st0 = status[0];  // read with the first loads, checked before the rows are used
   const float scale = (alpha_k ? alpha_k[k] : alpha) / (float)eta;
   const size_t total = (size_t)eta_pad * R;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
@@ -253,6 +294,7 @@ __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, con
     if (t < eta) {
       const int i = tau[t];
       const float y = split_sum(Y, S, total, e);
+      if (st0) return;  // an earlier fault: the step's rows may be out of range
       const float rn = weighted_rn(r2, row_w, i);
       if (rn == 0.f) set_status(status, ST_ZERO_ROW);
       const float res = y - B[(int64_t)i * R + r];
@@ -286,7 +328,9 @@ __global__ __launch_bounds__(NTH) void gemm_att_c_update(const float* __restrict
                                                          const float* __restrict__ C, int R, const float* Zin,
                                                          float* Zout, float* __restrict__ X, float lambda,
                                                          const int* status) {
-  if (status[0]) return;
+  // the fault word travels with the step's indices: the rows are read only when no fault is
+  // recorded (an index fault of this step leaves out-of-range indices in tau)
+  const int st0 = status[0];
   __shared__ __align__(16) float As[SK][LDP];
   __shared__ __align__(16) float Bs[SK][LDP];
   __shared__ int taus[kMaxTauLds];
@@ -296,6 +340,7 @@ __global__ __launch_bounds__(NTH) void gemm_att_c_update(const float* __restrict
   const int r0 = blockIdx.y * BN;
   stage_tau(tau, eta, taus);
   __syncthreads();
+  if (st0) return;
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -326,7 +371,7 @@ __global__ __launch_bounds__(NTH) void gemm_att_partial(const float* __restrict_
                                                         const int32_t* __restrict__ tau, int eta,
                                                         const float* __restrict__ C, int R, float* __restrict__ Wp,
                                                         const int* status) {
-  if (status[0]) return;
+  const int st0 = status[0];  // checked once the indices are staged, as in gemm_att_c_update
   __shared__ __align__(16) float As[SK][LDP];
   __shared__ __align__(16) float Bs[SK][LDP];
   __shared__ int taus[kMaxTauLds];
@@ -338,6 +383,7 @@ __global__ __launch_bounds__(NTH) void gemm_att_partial(const float* __restrict_
   const int t0 = (int)((int64_t)s * eta / S2), t1 = (int)((int64_t)(s + 1) * eta / S2);
   stage_tau(tau + t0, t1 - t0, taus);
   __syncthreads();
+  if (st0) return;
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -363,13 +409,14 @@ template <int S2>
 __global__ __launch_bounds__(NTH) void att_reduce_update(const float* __restrict__ Wp, int64_t nr4,
                                                          const float* Zin, float* Zout, float* __restrict__ X,
                                                          float lambda, const int* status) {
-  if (status[0]) return;
+  const int st0 = status[0];  // checked before the first write: the loads overlap its round trip
   const float4* W4 = reinterpret_cast<const float4*>(Wp);
   for (int64_t e = blockIdx.x * (int64_t)NTH + threadIdx.x; e < nr4; e += (int64_t)gridDim.x * NTH) {
     float4 w[S2];
 #pragma unroll
     for (int q = 0; q < S2; ++q) w[q] = W4[q * nr4 + e];
     float4 z = reinterpret_cast<const float4*>(Zin)[e];
+    if (st0) return;
     float4 t = w[0];
 #pragma unroll
     for (int q = 1; q < S2; ++q) {
@@ -394,6 +441,304 @@ __global__ void init_multirhs(float* Xs, float* X, size_t total, float lambda, i
     Xs[e] = z;
     X[e] = shrink(z, lambda);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Wide-tile products (the plan's tile = 128): TM x TN outputs per 256-thread workgroup
+// (TM = 128; TN = 128, or 64 for R <= 64), four waves of (TM/2) x (TN/2), each a grid of
+// (TM/32) x (TN/32) v_mfma_f32_16x16x4f32 blocks. K advances 32 per stage. A tile of twice the
+// width reads half the bytes per product of the 64 x 64 tiles: those are bound by the rate at
+// which a CU pulls its operands through L2 (the same step time whether the sampled rows spread
+// over the whole matrix or fit in L2), not by HBM or by the matrix cores.
+// Loads are branch-free (every address valid; positions outside the product are zeroed when
+// the stage is stored to LDS), and each stage's loads are issued before the previous stage's
+// products.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int SKW = 32;  // K per stage of the wide-tile products
+
+template <int TN>
+struct WideMap {  // a row of TN floats: TN/4 float4 across consecutive threads
+  static constexpr int cpr = TN / 4;           // float4 per row
+  static constexpr int rpp = NTH / cpr;        // rows per pass
+  static constexpr int passes = SKW / rpp;     // passes over the SKW rows of a stage
+};
+
+template <int TM, int TN>
+__device__ __forceinline__ void mma_stage_w(const float* As, int a_rows, const float* Bs, int wm, int wn,
+                                            int lane, f4 (&acc)[TM / 32][TN / 32]) {
+  // a_rows: As is row-major [TM][SKW + 4] (true) or k-major [SKW][TM + 16] (false)
+  constexpr int BI = TM / 32, BJ = TN / 32, PB = TN + 16, PA = TM + 16, LDR = SKW + 4;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < SKW; k0 += 4) {
+    float a[BI], b[BJ];
+#pragma unroll
+    for (int i = 0; i < BI; ++i) {
+      const int m = wm * (TM / 2) + i * 16 + li;
+      a[i] = a_rows ? As[m * LDR + k0 + lk] : As[(k0 + lk) * PA + m];
+    }
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) b[j] = Bs[(k0 + lk) * PB + wn * (TN / 2) + j * 16 + li];
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+  }
+}
+
+// acc = A_tau^T C over the sampled rows t < eta (taus in LDS) for output columns j0.. (TM) and
+// right-hand sides r0.. (TN): the A operand is k-major in memory (row tau_t, columns j), as is C.
+template <int TM, int TN>
+__device__ __forceinline__ void att_mainloop_w(const float* __restrict__ A, int64_t ld, int64_t n,
+                                               const int* taus, int eta, const float* __restrict__ C, int R,
+                                               int64_t j0, int r0, float* As, float* Bs,
+                                               f4 (&acc)[TM / 32][TN / 32]) {
+  using MA = WideMap<TM>;
+  using MB = WideMap<TN>;
+  constexpr int PA = TM + 16, PB = TN + 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int ar = tid / MA::cpr, ac = (tid % MA::cpr) * 4;
+  const int br = tid / MB::cpr, bc = (tid % MB::cpr) * 4;
+  const bool colok = j0 + ac < n, rok = r0 + bc < R;
+  const int64_t jc = colok ? j0 + ac : 0;
+  const int rc = rok ? r0 + bc : 0;
+  struct Buf {
+    float4 a[MA::passes], b[MB::passes];
+    bool ka[MA::passes], kb[MB::passes];
+  };
+  auto load = [&](int tb, Buf& st) {
+    int rows[MA::passes];
+#pragma unroll
+    for (int i = 0; i < MA::passes; ++i) {
+      const int t = tb + ar + MA::rpp * i;
+      rows[i] = taus[t < eta ? t : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < MA::passes; ++i) {
+      const int t = tb + ar + MA::rpp * i;
+      st.a[i] = *reinterpret_cast<const float4*>(A + (int64_t)rows[i] * ld + jc);
+      st.ka[i] = t < eta && colok;
+    }
+#pragma unroll
+    for (int i = 0; i < MB::passes; ++i) {
+      const int t = tb + br + MB::rpp * i;
+      st.b[i] = *reinterpret_cast<const float4*>(C + (size_t)(t < eta ? t : 0) * R + rc);
+      st.kb[i] = t < eta && rok;
+    }
+  };
+  auto stage = [&](const Buf& st) {
+    // nothing moves across: a select hoisted above this point would wait for the other buffer
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MA::passes; ++i)
+      *reinterpret_cast<float4*>(&As[(ar + MA::rpp * i) * PA + ac]) = keep4(st.ka[i], st.a[i]);
+#pragma unroll
+    for (int i = 0; i < MB::passes; ++i)
+      *reinterpret_cast<float4*>(&Bs[(br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
+    __syncthreads();
+  };
+  // Two register buffers: the loads of the next two stages are in flight during a stage's
+  // products (the workgroup is alone on its CU, so no other workgroup covers its load latency).
+  // The stages run in pairs with unconditional loads, so that each stage waits only for its own
+  // buffer; an odd count ends with a stage of zeros (adding exact zeros changes no sum).
+  const int npair = (eta + 2 * SKW - 1) / (2 * SKW);
+  if (npair == 0) return;
+  Buf b0, b1;
+  load(0, b0);
+  load(SKW, b1);
+  for (int q = 0; q + 1 < npair; ++q) {
+    stage(b0);
+    load((2 * q + 2) * SKW, b0);
+    mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
+    stage(b1);
+    load((2 * q + 3) * SKW, b1);
+    mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
+  }
+  stage(b0);
+  mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
+  stage(b1);
+  mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
+}
+
+template <int TM, int TN>
+__device__ __forceinline__ void zero_acc(f4 (&acc)[TM / 32][TN / 32]) {
+#pragma unroll
+  for (int i = 0; i < TM / 32; ++i)
+#pragma unroll
+    for (int j = 0; j < TN / 32; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+}  // namespace
+
+// Y[s][t][r] = sum_{j in split s} A[tau_t, j] X[j, r], TM x TN tiles (eta_pad a multiple of TM).
+// Grid, XCD order, index check and status as gemm_at_x.
+template <int TM, int TN>
+__global__ __launch_bounds__(NTH) void gemm_at_x_w(const float* __restrict__ A, int64_t ld, int64_t n,
+                                                   const int32_t* __restrict__ tau, int eta,
+                                                   const float* __restrict__ X, int R, float* __restrict__ Y,
+                                                   int eta_pad, int64_t kspan, int gt, int gr, int S, int* status,
+                                                   int64_t m, int64_t k) {
+  constexpr int LDR = SKW + 4, PB = TN + 16;
+  using MA = WideMap<SKW>;  // a row piece of SKW floats: 8 float4
+  using MB = WideMap<TN>;
+  __shared__ __align__(16) float Ar[TM * LDR];
+  __shared__ __align__(16) float Bs[SKW * PB];
+  __shared__ int flag;
+  if (m == 0 && any_fault(status, &flag)) return;
+  const int st0 = status[0];  // used late, as in gemm_at_x
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int id = blockIdx.x, T = gt * gr;
+  int tile, s;
+  if (S % 8 == 0) {
+    const int q = id / 8;
+    tile = q % T;
+    s = id % 8 + 8 * (q / T);
+  } else {
+    tile = id % T;
+    s = id / T;
+  }
+  const int t0 = (tile % gt) * TM, r0 = (tile / gt) * TN;
+  const int64_t j_begin = (int64_t)s * kspan;
+  int64_t j_end = j_begin + kspan;
+  if (j_end > n) j_end = n;
+
+  // A: thread -> row t0 + ar + MA::rpp * i (TM / MA::rpp rows), 4 columns at ac of the stage
+  constexpr int AP = TM / MA::rpp;
+  const int ar = tid / MA::cpr, ac = (tid % MA::cpr) * 4;
+  const float* arow[AP];
+  int bad = 0;
+#pragma unroll
+  for (int i = 0; i < AP; ++i) {
+    const int t = t0 + ar + MA::rpp * i;
+    int row = t < eta ? tau[t] : 0;
+    if (m > 0 && (row < 0 || (int64_t)row >= m)) { bad = 1; row = 0; }
+    arow[i] = A + (int64_t)row * ld;
+  }
+  if (bad && st0 == 0) {
+    set_status(status, ST_INDEX);
+    atomicMax(status + 1, (int)k);
+  }
+  // steps before k completed (status[1] only grows; a fault at step k records k as well)
+  if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0 && st0 == 0) atomicMax(status + 1, (int)k);
+  // X: thread -> rows br + MB::rpp * i of the stage, 4 columns at bc
+  const int br = tid / MB::cpr, bc = (tid % MB::cpr) * 4;
+  const bool rok = r0 + bc < R;
+  const int rc = rok ? r0 + bc : 0;
+  struct Buf {
+    float4 a[AP], b[MB::passes];
+    bool ka[AP], kb[MB::passes];
+  };
+  auto load = [&](int64_t jb, Buf& st) {
+    const int64_t c = jb + ac;
+#pragma unroll
+    for (int i = 0; i < AP; ++i) {
+      st.a[i] = *reinterpret_cast<const float4*>(arow[i] + (c < j_end ? c : 0));
+      st.ka[i] = c < j_end;
+    }
+#pragma unroll
+    for (int i = 0; i < MB::passes; ++i) {
+      const int64_t jj = jb + br + MB::rpp * i;
+      st.b[i] = *reinterpret_cast<const float4*>(X + (jj < j_end ? jj : 0) * R + rc);
+      st.kb[i] = jj < j_end && rok;
+    }
+  };
+  auto stage = [&](const Buf& st) {
+    // nothing moves across: a select hoisted above this point would wait for the other buffer
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < AP; ++i)
+      *reinterpret_cast<float4*>(&Ar[(ar + MA::rpp * i) * LDR + ac]) = keep4(st.ka[i], st.a[i]);
+#pragma unroll
+    for (int i = 0; i < MB::passes; ++i)
+      *reinterpret_cast<float4*>(&Bs[(br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
+    __syncthreads();
+  };
+  f4 acc[TM / 32][TN / 32];
+  zero_acc<TM, TN>(acc);
+  // two register buffers, stages in pairs with unconditional loads (as att_mainloop_w)
+  const int npair = j_end > j_begin ? (int)((j_end - j_begin + 2 * SKW - 1) / (2 * SKW)) : 0;
+  if (npair > 0) {
+    Buf b0, b1;
+    load(j_begin, b0);
+    load(j_begin + SKW, b1);
+    for (int q = 0; q + 1 < npair; ++q) {
+      stage(b0);
+      load(j_begin + (int64_t)(2 * q + 2) * SKW, b0);
+      mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
+      stage(b1);
+      load(j_begin + (int64_t)(2 * q + 3) * SKW, b1);
+      mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
+    }
+    stage(b0);
+    mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
+    stage(b1);
+    mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
+  }
+  // D layout: column lane%16, rows 4*(lane/16) + v
+  float* Ys = Y + (size_t)s * eta_pad * R;
+#pragma unroll
+  for (int i = 0; i < TM / 32; ++i)
+#pragma unroll
+    for (int j = 0; j < TN / 32; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = t0 + wm * (TM / 2) + i * 16 + 4 * (lane >> 4) + v;
+        const int r = r0 + wn * (TN / 2) + j * 16 + (lane & 15);
+        if (r < R) Ys[(size_t)t * R + r] = acc[i][j][v];
+      }
+}
+
+// W = A_tau^T C over the sampled rows [s2 eta / S2, (s2 + 1) eta / S2) (s2 = blockIdx.z).
+// UPDATE (S2 = 1): Zout = Zin - W, X = S_lambda(Zout); else W goes to Wp[s2] (summed by
+// att_reduce_update / att_reduce_adj). grid = (ceil(n/TM), ceil(R/TN), S2).
+template <int TM, int TN, bool UPDATE>
+__global__ __launch_bounds__(NTH) void gemm_att_w(const float* __restrict__ A, int64_t ld, int64_t n,
+                                                  const int32_t* __restrict__ tau, int eta,
+                                                  const float* __restrict__ C, int R, const float* Zin, float* Zout,
+                                                  float* __restrict__ X, float lambda, float* __restrict__ Wp,
+                                                  const int* status) {
+  const int st0 = status[0];  // checked once the indices are staged, as in gemm_att_c_update
+  __shared__ __align__(16) float As[SKW * (TM + 16)];
+  __shared__ __align__(16) float Bs[SKW * (TN + 16)];
+  __shared__ int taus[kMaxTauLds];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t j0 = (int64_t)blockIdx.x * TM;
+  const int r0 = blockIdx.y * TN;
+  const int s2 = blockIdx.z, S2 = gridDim.z;
+  const int tb0 = (int)((int64_t)s2 * eta / S2), tb1 = (int)((int64_t)(s2 + 1) * eta / S2);
+  stage_tau(tau + tb0, tb1 - tb0, taus);
+  __syncthreads();
+  if (st0) return;
+  f4 acc[TM / 32][TN / 32];
+  zero_acc<TM, TN>(acc);
+  att_mainloop_w<TM, TN>(A, ld, n, taus, tb1 - tb0, C + (size_t)tb0 * R, R, j0, r0, As, Bs, acc);
+  float* W = UPDATE ? nullptr : Wp + (size_t)s2 * n * R;
+#pragma unroll
+  for (int i = 0; i < TM / 32; ++i)
+#pragma unroll
+    for (int j = 0; j < TN / 32; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t jj = j0 + wm * (TM / 2) + i * 16 + 4 * (lane >> 4) + v;
+        const int r = r0 + wn * (TN / 2) + j * 16 + (lane & 15);
+        if (jj < n && r < R) {
+          const size_t o = (size_t)jj * R + r;
+          if constexpr (UPDATE) {
+            const float z = Zin[o] - acc[i][j][v];
+            Zout[o] = z;
+            X[o] = shrink(z, lambda);
+          } else {
+            W[o] = acc[i][j][v];
+          }
+        }
+      }
 }
 
 namespace {
@@ -464,21 +809,67 @@ __global__ void steps_done(int* status, int64_t K) {
   if (threadIdx.x == 0 && status[0] == 0) status[1] = (int)K;
 }
 
+// A_tau X (split-K partials into Y) for step k with the plan's tile; m > 0: with the index check.
+static void launch_at_x(const MultiRhsArgs& a, const int32_t* tk, const float* X, int64_t m, int64_t k,
+                        hipStream_t stream) {
+  if (a.tile == 128) {
+    const int gt = a.eta_pad / 128;
+    if (a.R > 64) {
+      const int gr = (a.R + 127) / 128;
+      hipLaunchKernelGGL((gemm_at_x_w<128, 128>), dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk,
+                         a.eta, X, a.R, a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status, m, k);
+    } else {
+      hipLaunchKernelGGL((gemm_at_x_w<128, 64>), dim3(gt * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta,
+                         X, a.R, a.Y, a.eta_pad, a.kspan, gt, 1, a.S, a.status, m, k);
+    }
+    return;
+  }
+  const int gt = (a.eta + BM - 1) / BM;
+  const int gr = (a.R + BN - 1) / BN;
+  hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, X, a.R, a.Y,
+                     a.eta_pad, a.kspan, gt, gr, a.S, a.status, m, k);
+}
+
+// W = A_tau^T C with the plan's tile: the S2 = 1 update (Zout = Zin - W, X = S_lambda) when
+// update is set, else the S2 row-split partials into Wp.
+static void launch_att(const MultiRhsArgs& a, const int32_t* tk, const float* C, const float* zin, float* zout,
+                       bool update, hipStream_t stream) {
+  const unsigned gn = (unsigned)((a.n + 127) / 128), z = update ? 1u : (unsigned)a.S2;
+  if (a.R > 64) {
+    const dim3 g(gn, (unsigned)((a.R + 127) / 128), z);
+    if (update)
+      hipLaunchKernelGGL((gemm_att_w<128, 128, true>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
+                         zin, zout, a.x, a.lambda, a.Wp, a.status);
+    else
+      hipLaunchKernelGGL((gemm_att_w<128, 128, false>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
+                         zin, zout, a.x, a.lambda, a.Wp, a.status);
+  } else {
+    const dim3 g(gn, 1, z);
+    if (update)
+      hipLaunchKernelGGL((gemm_att_w<128, 64, true>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
+                         zin, zout, a.x, a.lambda, a.Wp, a.status);
+    else
+      hipLaunchKernelGGL((gemm_att_w<128, 64, false>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
+                         zin, zout, a.x, a.lambda, a.Wp, a.status);
+  }
+}
+
 // One forward step k: R_tau from x (with the step's index check), C, Zout = Zin - A_tau^T C,
 // x = S_lambda(Zout).
 static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, float* zout, float* rh,
                           hipStream_t stream) {
-  const int gt = (a.eta + BM - 1) / BM;
   const int gr = (a.R + BN - 1) / BN;
   const int gn = (int)((a.n + BM - 1) / BM);
   const int32_t* tk = a.idx + k * (int64_t)a.eta;
-  hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.x, a.R,
-                     a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status, a.m, k);
+  launch_at_x(a, tk, a.x, a.m, k, stream);
   hipLaunchKernelGGL(coef_kernel, dim3(512), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta, a.B, a.R, a.r2,
                      a.row_w, a.alpha, a.alpha_k, k, a.C, rh, a.status);
   if (a.S2 > 1) {
-    hipLaunchKernelGGL(gemm_att_partial, dim3(gn, gr, a.S2), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C,
-                       a.R, a.Wp, a.status);
+    if (a.tile == 128)
+      launch_att(a, tk, a.C, zin, zout, false, stream);
+    else
+      hipLaunchKernelGGL(gemm_att_partial, dim3(gn, gr, a.S2), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C,
+                         a.R, a.Wp, a.status);
     const int64_t nr4 = a.n * a.R / 4;
     const dim3 rg((unsigned)((nr4 + NTH - 1) / NTH < 1024 ? (nr4 + NTH - 1) / NTH : 1024));
     if (a.S2 == 2)
@@ -487,6 +878,8 @@ static void multirhs_step(const MultiRhsArgs& a, int64_t k, const float* zin, fl
       hipLaunchKernelGGL(att_reduce_update<4>, rg, dim3(NTH), 0, stream, a.Wp, nr4, zin, zout, a.x, a.lambda, a.status);
     else
       hipLaunchKernelGGL(att_reduce_update<8>, rg, dim3(NTH), 0, stream, a.Wp, nr4, zin, zout, a.x, a.lambda, a.status);
+  } else if (a.tile == 128) {
+    launch_att(a, tk, a.C, zin, zout, true, stream);
   } else {
     hipLaunchKernelGGL(gemm_att_c_update, dim3(gn, gr), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, a.C, a.R,
                        zin, zout, a.x, a.lambda, a.status);
@@ -1140,15 +1533,17 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
     for (int64_t k = k1 - 1; k >= k0; --k) {
       const int64_t j = k - k0;
       const int32_t* tk = a.idx + k * (int64_t)a.eta;
-      hipLaunchKernelGGL(gemm_at_x, dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, d.zbar,
-                         a.R, a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status, (int64_t)0, k);
+      launch_at_x(a, tk, d.zbar, 0, k, stream);
       hipLaunchKernelGGL(adj_coef, dim3(kAdjCoefBlocks), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta,
                          d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
       hipLaunchKernelGGL(adj_bbar, dim3((unsigned)(((size_t)a.eta * a.R + 255) / 256)), dim3(256),
                          adj_bbar_lds(a.eta), stream, tk, a.eta, a.C, a.R, d.Bbar, a.status);
       if (a.S2 > 1) {
-        hipLaunchKernelGGL(gemm_att_partial, dim3(gn, gr, a.S2), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta,
-                           a.C, a.R, a.Wp, a.status);
+        if (a.tile == 128)
+          launch_att(a, tk, a.C, nullptr, nullptr, false, stream);
+        else
+          hipLaunchKernelGGL(gemm_att_partial, dim3(gn, gr, a.S2), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta,
+                             a.C, a.R, a.Wp, a.status);
         const float* zk = d.Zh + (size_t)j * total;
         double* lp = d.lam_part + kAdjSeedBlocks + (size_t)k * nblk_att;
         if (a.S2 == 2)

@@ -144,7 +144,8 @@ def gather_rate(A: torch.Tensor, index_stream: torch.Tensor, *, eta: int, K: int
 
 def plan_multirhs(A: torch.Tensor, R: int, *, eta: int, K: int = 1, kernel: int = 0) -> dict:
     """The split rsk_avg_solve_multirhs would use (nothing is queued): S column splits of A_tau X
-    (and the columns per split), S2 row splits of A_tau^T C, eta padded to a multiple of 64."""
+    (and the columns per split), S2 row splits of A_tau^T C, eta padded to a multiple of the
+    product tile edge (64, or 128 for kernel 3), the kernel."""
     d = dense_desc(A)
     dummy = torch.empty(2, dtype=torch.int32, device=A.device)
     params = _abi.RskParams(0.0, int(eta), 1.0, None, int(K), dummy.data_ptr(), 0, A.data_ptr(), 0, None, 0, 0.0,
@@ -312,7 +313,8 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
                    row_w: Optional[torch.Tensor] = None, kernel: int = 0, check: bool = True) -> SolveResult:
     """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major).
 
-    ``kernel``: 1 the step kernels, 2 one persistent launch for all K steps, 0 the library's choice.
+    ``kernel``: 1 the step kernels, 2 one persistent launch for all K steps, 3 the step kernels with
+    wide product tiles, 0 the library's choice.
 
     With ``ckpt`` (ceil(K/ckpt_every) x n x R float32) the x* checkpoints the
     adjoint recomputes from are written as well.

@@ -270,7 +270,7 @@ static void check_multirhs_adjoint(void) {
   d.n = 8192; d.ld = 8192;
   for (int R = 4; R <= 512; R *= 2)
     for (int eta = 1; eta <= 4096; eta *= 4)
-      for (int kern = 0; kern < 4; ++kern) {
+      for (int kern = 0; kern < 5; ++kern) {
         rsk_params q = params(eta, 50);
         q.kernel = kern;
         expect_in("multirhs sweep", rsk_plan_multirhs(&d, R, &q, plan), ok | BIT(RSK_ERR_INVALID_ARG));

@@ -75,6 +75,26 @@ def test_adjoint_matches_oracle_adjoint(cuda, rsk_lib, C):
     check_vec(adj.alpha_bar, ab, 1e-4, what="dL/dalpha_k")
 
 
+def test_adjoint_wide_tiles_match_oracle_adjoint(cuda, rsk_lib):
+    """The adjoint with the wide product tiles (a tuned choice of kernel 3 for the instance's key:
+    the forward, the recomputation and the reverse products all take it) against the FP64 oracle."""
+    from paper_2203_10838_amd import _abi, autotune
+    A, B, Xh, eta, K, lam, ak, idx = _instance()
+    m, n, R = A.shape[0], A.shape[1], B.shape[1]
+    autotune.set_entry(_abi.RSK_TUNE_MULTIRHS, _abi.RSK_F32, m=m, n=n, eta=eta, R=R, v0=1, v1=1, v2=3)
+    try:
+        fo = oracle.rska_multirhs(A, B, lam, eta, 1.0, K, idx, alpha_k=ak.astype(np.float64))
+        xbar = 2 * (fo["x"] - Xh.astype(np.float64))
+        f, adj = _gpu_forward_adjoint(A, B, eta, K, lam, ak, idx, 5, lambda _x: xbar, cuda)
+    finally:
+        autotune.erase(_abi.RSK_TUNE_MULTIRHS, _abi.RSK_F32, m=m, n=n, eta=eta, R=R)
+    check_columns(f.x_star, f.x, fo, lam, 1e-4, min_support=4)
+    bb, lb, ab = _oracle_grads(A, B, eta, K, lam, ak, idx, xbar)
+    check_vec(adj.Bbar, bb, 1e-4, what="dL/dB")
+    assert abs(float(adj.lambda_bar.cpu()[0]) - lb) <= 1e-4 * max(1.0, abs(lb))
+    check_vec(adj.alpha_bar, ab, 1e-4, what="dL/dalpha_k")
+
+
 def test_adjoint_matches_fp64_central_differences(cuda, rsk_lib):
     A, B, Xh, eta, K, lam, ak, idx = _instance()
     f, adj = _gpu_forward_adjoint(A, B, eta, K, lam, ak, idx, 7, lambda x: 2 * (x - Xh), cuda)

@@ -15,9 +15,13 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
+@pytest.mark.parametrize("kernel", [0, 3])
 @pytest.mark.parametrize("m,n,R,eta,K", [(3000, 1000, 64, 100, 40), (2000, 516, 12, 37, 60), (5000, 2048, 128, 300, 15),
-                                         (300, 64, 4, 5, 200)])
-def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K):
+                                         (300, 64, 4, 5, 200), (4000, 1288, 200, 150, 12)])
+def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K, kernel):
+    """Kernel 0 is the library's choice (64 x 64 product tiles), kernel 3 the wide tiles (128 x 128,
+    128 x 64 for R <= 64): ragged n (516, 1288), R below, at and above one wide tile (12, 64, 128,
+    200), the row-split update (S2 > 1) and the direct one (eta <= 64)."""
     from paper_2203_10838_amd import rsk
     sysd = inputs.multirhs_system(m, n, R, max(1, n // 20), seed=m + R)
     A, B = sysd["A"], sysd["B"]
@@ -25,13 +29,20 @@ def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K):
     A64 = A.astype(np.float64)
     s = np.linalg.svd(A64, compute_uv=False)
     alpha = oracle.optimal_alpha(eta, float((A64 * A64).sum()), float(s[0] ** 2))
-    res = rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda))
+    At, Bt = _t(A, cuda), _t(B, cuda)
+    if kernel == 3:
+        plan = rsk.plan_multirhs(At, R, eta=eta, K=K, kernel=3)
+        assert plan["kernel"] == 3 and plan["eta_pad"] % 128 == 0, plan
+    res = rsk.solve_multirhs(At, Bt, lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=kernel)
     assert res.status == 0 and res.k_done == K
     ref = oracle.rska_multirhs(A, B, 0.5, eta, alpha, K, idx)
     check_columns(res.x_star, res.x, ref, 0.5, 1e-4, min_support=R)
 
 
-def test_multirhs_per_step_alpha_and_errors(cuda, rsk_lib):
+@pytest.mark.parametrize("kernel", [1, 3])
+def test_multirhs_per_step_alpha_and_errors(cuda, rsk_lib, kernel):
+    """Per-step alpha_k against the oracle; an out-of-range index at step 5 stops the solve there
+    (status [INDEX_RANGE, 5]) without any kernel reading the bad row, on either tile size."""
     import torch
     from paper_2203_10838_amd import rsk
     sysd = inputs.multirhs_system(1200, 400, 8, 10, seed=5)
@@ -40,27 +51,34 @@ def test_multirhs_per_step_alpha_and_errors(cuda, rsk_lib):
     idx = inputs.index_stream(inputs.row_sampling_weights(A), K, eta, 6)
     ak = np.linspace(5.0, 12.0, K).astype(np.float32)
     res = rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.3, eta=eta, alpha=1.0, K=K, index_stream=_t(idx, cuda),
-                             alpha_k=_t(ak, cuda))
+                             alpha_k=_t(ak, cuda), kernel=kernel)
     ref = oracle.rska_multirhs(A, B, 0.3, eta, 1.0, K, idx, alpha_k=ak.astype(np.float64))
     check_columns(res.x_star, res.x, ref, 0.3, 1e-4, min_support=8)
     bad = idx.copy()
     bad[5 * eta + 3] = 1200
     with pytest.raises(rsk.RskError) as e:
-        rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.3, eta=eta, alpha=8.0, K=K, index_stream=_t(bad, cuda))
+        rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.3, eta=eta, alpha=8.0, K=K, index_stream=_t(bad, cuda),
+                           kernel=kernel)
     assert e.value.name == "RSK_ERR_INDEX_RANGE"
     r = rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.3, eta=eta, alpha=8.0, K=K, index_stream=_t(bad, cuda),
-                           check=False)
+                           check=False, kernel=kernel)
     torch.cuda.synchronize()
     assert r.status_dev.cpu().tolist() == [6, 5]
+    # the first five steps ran: x* equals the clean run's after 5 steps
+    r5 = rsk.solve_multirhs(_t(A, cuda), _t(B, cuda), lam=0.3, eta=eta, alpha=8.0, K=5, index_stream=_t(idx, cuda),
+                            kernel=kernel)
+    assert torch.equal(r.x_star, r5.x_star)
 
 
 @pytest.mark.timeout(300)
-def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib):
+@pytest.mark.parametrize("kernel", [1, 3])
+def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib, kernel):
     """The shared-A workload at its own shape: A 32768 x 8192 float32 N(0,1) drawn on the device,
     R = 256 right-hand sides B = A X_hat (5% N(0,1) nonzeros a column), eta = 820, alpha = alpha*,
-    lambda = 1, 20 steps. Its 512 output tiles of 64 x 64 run the A_tau^T C update without a row
-    split over 13 stages of 64 rows. Eight seeded columns against the FP64 oracle on the rows the
-    stream touches."""
+    lambda = 1, 20 steps. Kernel 1: its 512 output tiles of 64 x 64 run the A_tau^T C update
+    without a row split over 13 stages of 64 rows. Kernel 3: 128 x 128 tiles (eta padded to 896),
+    the update split over the sampled rows in two halves of 13 stages of 32. Eight seeded columns
+    against the FP64 oracle on the rows the stream touches."""
     import torch
     from paper_2203_10838_amd import rsk
     m, n, R, eta, K, lam, seed = 32768, 8192, 256, 820, 20, 1.0, 20310838 + 300 + 7
@@ -84,10 +102,13 @@ def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib):
         s2 = float(v.double().norm())
         v = v / v.norm()
     alpha = params.optimal_alpha(eta, float(wn.sum()), s2)
-    plan = rsk.plan_multirhs(A, R, eta=eta, K=K)
-    assert plan["S2"] == 1 and plan["eta_pad"] == 832, plan
+    plan = rsk.plan_multirhs(A, R, eta=eta, K=K, kernel=kernel)
+    if kernel == 1:
+        assert plan["S2"] == 1 and plan["eta_pad"] == 832, plan
+    else:
+        assert plan["kernel"] == 3 and plan["S2"] == 2 and plan["eta_pad"] == 896, plan
     idx = inputs.index_stream(wn, K, eta, seed + 1)
-    res = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda))
+    res = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=kernel)
     assert res.status == 0 and res.k_done == K
     cols = sorted(np.random.default_rng(seed + 2).choice(R, 8, replace=False).tolist())
     uniq, local = np.unique(idx, return_inverse=True)
