@@ -260,7 +260,7 @@ hipError_t launch_batched_rt(const rsk_batch_item* items, const int32_t* order, 
   uint64_t join_ticks = join_ticks_minute();
   BatchWgTable t = tab;
   void* args[] = {&items, &order, &nsys, &ticket0, &woff, &queue, &regions, &t, &join_ticks};
-  return hipLaunchCooperativeKernel((const void*)&rska_batched_rt, dim3(grid), dim3(kBrtThreads), args, 0, stream);
+  return launch_persistent((const void*)&rska_batched_rt, dim3(grid), dim3(kBrtThreads), args, 0, stream);
 }
 
 static void* batched_fn(int dtype, int vec) {
@@ -290,7 +290,7 @@ hipError_t launch_batched(const rsk_batch_item* items, const int32_t* order, int
   BatchWgTable t = tab;
   void* args[] = {&items, &order, &nsys, &ticket0, &woff, &queue, &regions, &t, &join_ticks};
   // co-residency of the whole grid: a group forms only from running workgroups
-  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kDenseThreads), args, (unsigned)lds, stream);
+  return launch_persistent(fn, dim3(grid), dim3(kDenseThreads), args, (unsigned)lds, stream);
 }
 
 }  // namespace rsk

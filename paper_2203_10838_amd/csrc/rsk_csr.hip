@@ -575,7 +575,7 @@ template <typename T>
 hipError_t launch_csr_grid(CsrArgs<T>& a, hipStream_t stream) {
   if (a.G < 1 || a.G > csr_grid_max_resident<T>()) return hipErrorCooperativeLaunchTooLarge;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)&rska_csr_grid<T>, dim3(a.G), dim3(kGridThreads), args, 0, stream);
+  return launch_persistent((const void*)&rska_csr_grid<T>, dim3(a.G), dim3(kGridThreads), args, 0, stream);
 }
 
 template int csr_grid_max_resident<float>();

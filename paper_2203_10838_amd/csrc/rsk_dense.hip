@@ -14,6 +14,8 @@
 //   4. c_t = (alpha_k/eta) (r_t - b_{tau_t}) / ||a_{tau_t}||^2;
 //   5. x*_j -= sum_t c_t A[tau_t, j] for the own columns, x_j = S_lambda(x*_j);
 //   6. every check_every steps, ||x - x_ref|| / ||x_ref|| (monitor).
+#include <cstdlib>
+
 #include "rsk_dense_run.hpp"
 
 namespace rsk {
@@ -98,6 +100,15 @@ int dense_max_grid(int vec, int eta, int wq_max, int tile_cache, int64_t xr_elem
   return per_cu * cus;
 }
 
+hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args, unsigned lds, hipStream_t stream) {
+  static const bool coop = [] {
+    const char* e = getenv("RSK_COOPERATIVE");
+    return !(e && e[0] == '0' && e[1] == 0);
+  }();
+  return coop ? hipLaunchCooperativeKernel(fn, grid, block, args, lds, stream)
+              : hipLaunchKernel(fn, grid, block, args, lds, stream);
+}
+
 template <typename T>
 hipError_t launch_dense(DenseArgs<T>& a, int vec, hipStream_t stream, int* max_grid_out) {
   size_t lds = 0;
@@ -107,7 +118,7 @@ hipError_t launch_dense(DenseArgs<T>& a, int vec, hipStream_t stream, int* max_g
   if (maxg < a.G) return hipErrorCooperativeLaunchTooLarge;
   void* fn = dense_kernel_for<T>(vec);
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(fn, dim3(a.G), dim3(kDenseThreads), args, (unsigned)lds, stream);
+  return launch_persistent(fn, dim3(a.G), dim3(kDenseThreads), args, (unsigned)lds, stream);
 }
 
 template <typename T>

@@ -553,7 +553,7 @@ hipError_t launch_dense_rt(DenseArgs<float>& a, int nt, int rp, int cpl, int rg,
   if (a.G % rg != 0 || (rg > 1 && !a.xU)) return hipErrorInvalidValue;
   if (a.G > kMaxG || dense_rt_max_grid(nt, rp, cpl, rg) < a.G) return hipErrorCooperativeLaunchTooLarge;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(fn, dim3(a.G), dim3(nt), args, 0, stream);
+  return launch_persistent(fn, dim3(a.G), dim3(nt), args, 0, stream);
 }
 
 }  // namespace rsk

@@ -319,6 +319,16 @@ hipError_t launch_rownorm2_csr(const int64_t* row_ptr, const T* val, int64_t m, 
 
 hipError_t launch_zero_words(u64* p, size_t nwords, hipStream_t stream);
 
+// Launch of a persistent kernel whose workgroups wait for one another. Cooperative by default:
+// the runtime guarantees that all of them are resident at once. With the environment variable
+// RSK_COOPERATIVE=0 (read once per process) the same grid goes out as a plain launch: the callers
+// have already checked that it fits the device's resident capacity, so on an otherwise idle GPU
+// every workgroup is resident all the same, and the bounded waits turn anything else into
+// RSK_ERR_ABORTED. It exists for tools that do not follow a process with a cooperative launch
+// to a clean end (under the profiler of this ROCm release such processes have ended with a
+// segmentation fault in their exit path, after the profiler had written its results).
+hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args, unsigned lds, hipStream_t stream);
+
 // float32 register-tile kernel: NT threads, RP row passes of NT/(4 RG) rows, CPL float4 chunks
 // per lane, RG row groups (1 or 2) of G/RG column slices
 int dense_rt_max_grid(int nt, int rp, int cpl, int rg);

@@ -1195,7 +1195,7 @@ hipError_t launch_multirhs_persistent(const MultiRhsArgs& a, const MrpWork& w, i
   float* ck = ckpt;
   int64_t ce = ckpt_every > 0 ? ckpt_every : 1;
   void* args[] = {&aa, &ww, &ck, &ce};
-  return hipLaunchCooperativeKernel((const void*)&multirhs_persistent, dim3(grid), dim3(NTH), args, 0, stream);
+  return launch_persistent((const void*)&multirhs_persistent, dim3(grid), dim3(NTH), args, 0, stream);
 }
 
 // ---------------------------------------------------------------------------
