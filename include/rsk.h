@@ -99,9 +99,9 @@ typedef struct {
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register
-                                  tile, 3 = float32 register tile over two row groups (see
-                                  rsk_avg_solve_dense); CSR: 0, 1 or 2; multi-RHS: 0, 1 or 2 (see
-                                  rsk_avg_solve_multirhs) */
+                                  tile, 3 = float32 register tile over two row groups, 4 = one workgroup
+                                  with the step in registers (see rsk_avg_solve_dense); CSR: 0, 1 or 2;
+                                  multi-RHS: 0..3 (see rsk_avg_solve_multirhs) */
   const void *row_w;           /* nullable device array (m, dtype of A): per-row weights w_i, the diagonal W of
                                   Definition 1 (variants v3/v4 of Sec. 5); row i is relaxed by alpha (or
                                   alpha_k[k]) times w_i. Dense, CSR and multi-RHS solves; not the adjoint or
@@ -238,7 +238,7 @@ int32_t rsk_bsk_solve_dense(const rsk_dense *A, const void *b, const rsk_params 
  * launches the library supports: results are those of the explicit choice,
  * bit for bit, and a tuned choice that does not apply to a matrix (alignment,
  * leading dimension) falls back to the built-in rule.
- *   path RSK_TUNE_DENSE:    key (dtype, m, n, eta);    v0 = kernel (1..3), v1 = grid.
+ *   path RSK_TUNE_DENSE:    key (dtype, m, n, eta);    v0 = kernel (1..4), v1 = grid.
  *   path RSK_TUNE_MULTIRHS: key (dtype, m, n, eta, R); v0 = S (splits of the n columns in
  *                           A_tau X), v1 = S2 (row splits of A_tau^T C: 1, 2, 4 or 8), v2 = the
  *                           kernel (1 step kernels, 2 one persistent launch, 3 wide-tile step
@@ -323,11 +323,16 @@ int32_t rsk_workspace_size_csr(const rsk_csr *A, const rsk_params *p, size_t *by
  * row groups: each workgroup reads half of a step's rows over a slice twice
  * as wide (at most 160 columns), and the two workgroups of a slice add their
  * parts of the x* update in a third exchange (same requirements as 2, an
- * even number of workgroups). 0 = the
- * library's choice: for float32, 3 for 88 <= eta <= 800, else 2, where the
- * register tile applies; else 1. Kernels 2 and 3 sum in
- * different orders (results agree to rounding); each gives bitwise
- * reproducible x* and x (y_out: see rsk_params).
+ * even number of workgroups); 4 = one workgroup of 256 threads with the
+ * step in registers and no exchange between workgroups (float32 and float64,
+ * any alignment; n <= 2048 and eta <= 32 / ceil-to-power-of-two(n / 256),
+ * p->grid 0 or 1), the next step's rows loaded during the step: for small
+ * systems, whose steps are bound by latency. 0 = the library's choice: for
+ * float64 steps of at most 64 KB that kernel 4 takes, 4; for float32, 3 for
+ * 88 <= eta <= 800, else 2, where the register tile applies; else 1. The
+ * kernels sum in different orders (results agree to rounding); each gives
+ * bitwise reproducible x* and x (y_out: see rsk_params; kernel 4 applies y in
+ * a fixed order as well).
  * A kernel that does not apply to the shape returns RSK_ERR_UNSUPPORTED.
  */
 int32_t rsk_avg_solve_dense(const rsk_dense *A, const void *b, const rsk_params *p, void *x_star, void *x,

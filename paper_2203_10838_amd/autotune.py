@@ -5,8 +5,9 @@ batched per-system workgroup targets with wg_bytes = 0). ``save``/``load`` keep 
 text cache file; the library also loads the file named by RSK_TUNE_CACHE at its first lookup.
 
 What is tuned, per key:
-* dense (dtype, m, n, eta): the kernel (general; register tile with one or two row groups) and
-  its workgroup count, among the launches rsk_plan_dense accepts;
+* dense (dtype, m, n, eta): the kernel (general; register tile with one or two row groups; one
+  workgroup with the step in registers) and its workgroup count, among the launches rsk_plan_dense
+  accepts;
 * multi-RHS (dtype, m, n, eta, R): S, the column splits of A_tau X, and S2, the row splits of
   A_tau^T C;
 * batched (dtype, size class of a system's step bytes eta*n*s, launch: general kernel or register
@@ -93,8 +94,8 @@ def dense_candidates(A: torch.Tensor, eta: int) -> list:
     cus = torch.cuda.get_device_properties(A.device).multi_processor_count
     grids = sorted({g for g in (1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128, 160, 192, 224, 256, cus) if 1 <= g <= cus})
     seen, out = set(), []
-    for kernel in (2, 3, 1):
-        for g in grids:
+    for kernel in (2, 3, 1, 4):
+        for g in (grids if kernel != 4 else [1]):
             try:
                 plan = rsk.plan_dense(A, eta=eta, grid=g, kernel=kernel)
             except rsk.RskError:

@@ -107,6 +107,8 @@ constexpr size_t kPipeTileBytes = 128 * 1024;
 // it is bound by latency, not bytes: one workgroup (no exchange) while the step and its rows are
 // small, else about 4 KB of rows per workgroup on 16..128 workgroups, the whole chip for big steps.
 constexpr size_t kOneWgStepBytes = 32 * 1024, kOneWgRowBytes = 16 * 1024;
+// the one-workgroup register kernel (kernel 4) is the float64 default for steps up to this size
+constexpr double kSmallStepBytes = 64.0 * 1024;
 constexpr size_t kBytesPerWg = 4 * 1024;
 constexpr int kMinSpreadG = 16, kMaxSpreadG = 128;
 constexpr size_t kFullGridStepBytes = size_t(8) << 20;
@@ -142,14 +144,14 @@ int32_t check_params(const rsk_params* p, int64_t m) {
   if (p->K > 0 && !p->index_stream) return RSK_ERR_INVALID_ARG;
   if (!p->rownorm2 || !p->status_dev) return RSK_ERR_INVALID_ARG;
   if (p->check_every < 0 || !(p->tol >= 0.0) || p->grid < 0) return RSK_ERR_INVALID_ARG;
-  if (p->kernel < 0 || p->kernel > 3) return RSK_ERR_INVALID_ARG;
+  if (p->kernel < 0 || p->kernel > 4) return RSK_ERR_INVALID_ARG;
   if (p->x_ref && p->check_every > 0 && p->err_hist == nullptr && p->tol <= 0.0) return RSK_ERR_INVALID_ARG;
   (void)m;
   return RSK_OK;
 }
 
 struct DensePlan {
-  int kernel;  // 1 general, 2 register tile
+  int kernel;  // 1 general, 2 register tile, 4 one workgroup with the step in registers
   int nt, rp, cpl, rg;
   int vec, G, two_hop, tile_cache, wq_max, lpr, W;
   int64_t nchunks;
@@ -232,7 +234,7 @@ template <typename T>
 int32_t plan_dense(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   rsk_tune_entry e;
   if (p->kernel == 0 && p->grid == 0 &&
-      tune_find(RSK_TUNE_DENSE, A->dtype, A->m, A->n, p->eta, 0, &e) && e.v0 >= 1 && e.v0 <= 3 && e.v1 >= 1) {
+      tune_find(RSK_TUNE_DENSE, A->dtype, A->m, A->n, p->eta, 0, &e) && e.v0 >= 1 && e.v0 <= 4 && e.v1 >= 1) {
     rsk_params q = *p;
     q.kernel = (int32_t)e.v0;
     q.grid = (int32_t)e.v1;
@@ -249,6 +251,17 @@ template <typename T>
 int32_t plan_dense_fixed(const rsk_dense* A, const rsk_params* p, DensePlan* pl) {
   const size_t s = sizeof(T);
   pl->kernel = 1; pl->nt = pl->rp = pl->cpl = 0; pl->rg = 1;
+  // one workgroup, the step in registers: asked for, or by default for a small system whose step
+  // is bound by latency (a float64 step of at most kSmallStepBytes)
+  const int cpt = rsk::dense_small_cpt(A->n, p->eta);
+  if (p->kernel == 4 || (p->kernel == 0 && p->grid <= 1 && cpt && A->dtype == RSK_F64 &&
+                         (double)p->eta * (double)A->n * (double)s <= kSmallStepBytes)) {
+    if (!cpt || p->grid > 1) return RSK_ERR_UNSUPPORTED;
+    pl->kernel = 4; pl->nt = 256; pl->cpl = cpt; pl->vec = 1; pl->W = (int)(s / 4);
+    pl->nchunks = A->n; pl->G = 1; pl->wq_max = (int)A->n; pl->lpr = 1; pl->tile_cache = 0; pl->two_hop = 0;
+    dense_ws_layout(1, p->eta, pl->W, 0, pl);
+    return RSK_OK;
+  }
   // float32: the register-tile kernel wherever its shape limits allow; its exchange is cheaper
   // than the general kernel's at every step size measured, one row per step included
   if (p->kernel == 3) return plan_dense_rt(A, p, 2, pl) ? RSK_OK : RSK_ERR_UNSUPPORTED;
@@ -347,6 +360,7 @@ int32_t solve_dense_t(const rsk_dense* A, const void* b, const rsk_params* p, vo
       return RSK_ERR_HIP;
     return RSK_OK;
   }
+  if (pl.kernel == 4) return rsk::launch_dense_small<T>(a, stream) == hipSuccess ? RSK_OK : RSK_ERR_HIP;
   int maxg = 0;
   if (rsk::launch_dense<T>(a, pl.vec, stream, &maxg) != hipSuccess) return RSK_ERR_HIP;
   return RSK_OK;
@@ -374,7 +388,7 @@ template <typename T>
 int32_t plan_csr(const rsk_csr* A, const rsk_params* p, CsrPlan* pl) {
   const int cus = device_cus() > 0 ? device_cus() : 1;
   const int rpp = rsk::kCsrGridRowsPerPass;
-  if (p->kernel == 3) return RSK_ERR_INVALID_ARG;  // a dense kernel
+  if (p->kernel == 3 || p->kernel == 4) return RSK_ERR_INVALID_ARG;  // dense kernels
   const bool grid = p->kernel == 2 || (p->kernel == 0 && p->eta >= 4);
   pl->kernel = grid ? 2 : 1;
   pl->G = 1;
@@ -1272,11 +1286,11 @@ int32_t rsk_plan_dense(const rsk_dense* A, const rsk_params* p, int32_t* out) {
   st = A->dtype == RSK_F64 ? plan_dense<double>(A, p, &pl) : plan_dense<float>(A, p, &pl);
   if (st) return st;
   const bool rt = pl.kernel == 2;
-  out[0] = rt ? (pl.rg > 1 ? 3 : 2) : 1;
+  out[0] = rt ? (pl.rg > 1 ? 3 : 2) : pl.kernel;
   out[1] = pl.G;
   out[2] = rt ? pl.nt : rsk::kDenseThreads;
   out[3] = rt ? pl.rp : 0;
-  out[4] = rt ? pl.cpl : 0;
+  out[4] = rt || pl.kernel == 4 ? pl.cpl : 0;
   out[5] = pl.rg;
   out[6] = pl.two_hop ? 2 : 1;
   out[7] = pl.vec;

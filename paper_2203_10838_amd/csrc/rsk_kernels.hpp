@@ -319,6 +319,12 @@ hipError_t launch_rownorm2_csr(const int64_t* row_ptr, const T* val, int64_t m, 
 
 hipError_t launch_zero_words(u64* p, size_t nwords, hipStream_t stream);
 
+// One-workgroup dense kernel with the step in registers (rsk_dense_small.hip): columns a thread
+// (1, 2, 4 or 8) for n columns and eta rows a step, 0 where it does not apply.
+int dense_small_cpt(int64_t n, int eta);
+template <typename T>
+hipError_t launch_dense_small(DenseArgs<T>& a, hipStream_t stream);
+
 // Launch of a persistent kernel whose workgroups wait for one another. Cooperative by default:
 // the runtime guarantees that all of them are resident at once. With the environment variable
 // RSK_COOPERATIVE=0 (read once per process) the same grid goes out as a plain launch: the callers

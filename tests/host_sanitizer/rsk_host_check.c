@@ -204,7 +204,7 @@ static void check_dense(void) {
   for (int a = 0; a < 4; ++a)
     for (int c = 0; c < 4; ++c)
       for (int e = 0; e < 6; ++e)
-        for (int kern = 0; kern < 5; ++kern)
+        for (int kern = 0; kern < 6; ++kern)
           for (int dt = 0; dt < 2; ++dt) {
             rsk_dense dd = dense(ms[a], ns[c], ns[c] + (c & 1), dt);
             rsk_params pp = params(etas[e], 100);
@@ -228,6 +228,7 @@ static void check_csr(void) {
   expect_in("csr ws with y", rsk_workspace_size_csr(&c, &p, &nb), BIT(RSK_OK) | BIT(RSK_ERR_UNSUPPORTED));
   p.eta = 4097; expect("csr eta > 4096", rsk_workspace_size_csr(&c, &p, &nb), RSK_ERR_UNSUPPORTED); p.eta = 8;
   p.kernel = 3; expect("csr dense kernel", rsk_workspace_size_csr(&c, &p, &nb), RSK_ERR_INVALID_ARG); p.kernel = 0;
+  p.kernel = 4; expect("csr dense kernel 4", rsk_workspace_size_csr(&c, &p, &nb), RSK_ERR_INVALID_ARG); p.kernel = 0;
   c.row_ptr = NULL; expect("csr no row_ptr", rsk_workspace_size_csr(&c, &p, &nb), RSK_ERR_INVALID_ARG);
   c.row_ptr = (const int64_t*)DEV(0x1000);
   c.m = 0; expect("csr m 0", rsk_workspace_size_csr(&c, &p, &nb), RSK_ERR_INVALID_ARG); c.m = 100;
