@@ -26,6 +26,37 @@ namespace {
 constexpr int kSmallThreads = 256;
 constexpr int kSmallWaves = kSmallThreads / 64;
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sums of N values over the 64 lanes of a wave, every lane getting every sum: within each DPP row
+// of 16 lanes by rotations of 8, 4, 2, 1, then across rows by xor 16 and 32. One level for all N
+// values before the next, so their latencies overlap. A fixed order: the same bits on every run.
+template <typename T, int N>
+__device__ __forceinline__ void lane_rows_sum(T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x128>(v[i]);  // row_ror:8
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x124>(v[i]);  // row_ror:4
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x122>(v[i]);  // row_ror:2
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x121>(v[i]);  // row_ror:1
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 16);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32);
+}
+
 template <int CPT>
 struct SmallShape {
   static constexpr int emax = 32 / CPT;  // rows a step: the tile is at most 32 elements a thread
@@ -136,16 +167,19 @@ __global__ __launch_bounds__(kSmallThreads) void rska_dense_small(DenseArgs<T> a
     load_tile(rows_sh[s2], fill, fb, fn, fw);
     if (tid == 0) badw[s0] = 0;  // its last reader was step k - 2, before that step's first barrier
 
-    // partial dots over the own columns, summed over the wave
+    // partial dots over the own columns, summed over the wave level by level across the rows, so
+    // that the rows' exchange latencies overlap (rows past eta are summed too and never read)
+    T p[EMAX];
 #pragma unroll
-    for (int t = 0; t < EMAX; ++t)
-      if (t < eta) {
-        T p = T(0);
+    for (int t = 0; t < EMAX; ++t) {
+      p[t] = T(0);
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) p += cur[t][c] * xv[c];
-        p = wave_sum(p);
-        if (lane == 0) part[wave][t] = p;
-      }
+      for (int c = 0; c < CPT; ++c) p[t] += cur[t][c] * xv[c];
+    }
+    lane_rows_sum<T, EMAX>(p);
+    if (lane == 0)
+#pragma unroll
+      for (int t = 0; t < EMAX; ++t) part[wave][t] = p[t];
     __syncthreads();
     store_index(k + 3, i3);
     int flag = 0;
