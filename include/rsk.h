@@ -92,10 +92,10 @@ typedef struct {
   double tol;                  /* with the monitor: stop early once the relative error is <= tol (0 = never) */
   double *err_hist;            /* nullable device array, K/check_every entries (double) */
   void *y_out;                 /* nullable device array (m, dtype of A), in/out: y[tau_t] -= c_t, so x* = A^T y.
-                                  CSR: each row's slots of a step are applied once, in a fixed order, so y is
-                                  bitwise reproducible. Dense: summed with floating-point atomics, so where a
-                                  row is drawn more than once in a step y is reproducible to rounding only
-                                  (x* and x stay bitwise reproducible) */
+                                  CSR and dense kernel 4: each row's slots of a step are applied once, in a
+                                  fixed order, so y is bitwise reproducible. Dense kernels 1-3: summed with
+                                  floating-point atomics, so where a row is drawn more than once in a step y
+                                  is reproducible to rounding only (x* and x stay bitwise reproducible) */
   int32_t *status_dev;         /* device int32[2]: [0] status (0 = ok), [1] steps completed. Required. */
   int32_t grid;                /* workgroups of the persistent kernel; 0 = chosen by the library */
   int32_t kernel;              /* dense kernel: 0 = chosen by the library, 1 = general, 2 = float32 register
