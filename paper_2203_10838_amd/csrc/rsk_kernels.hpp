@@ -332,7 +332,9 @@ hipError_t launch_dense_small(DenseArgs<T>& a, hipStream_t stream);
 // every workgroup is resident all the same, and the bounded waits turn anything else into
 // RSK_ERR_ABORTED. It exists for tools that do not follow a process with a cooperative launch
 // to a clean end (under the profiler of this ROCm release such processes have ended with a
-// segmentation fault in their exit path, after the profiler had written its results).
+// segmentation fault in their exit path, after the profiler had written its results), and for
+// several processes on one GPU (a cooperative launch has failed in one process while another
+// process that had made cooperative launches was alive).
 hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args, unsigned lds, hipStream_t stream);
 
 // float32 register-tile kernel: NT threads, RP row passes of NT/(4 RG) rows, CPL float4 chunks

@@ -1,7 +1,8 @@
 """The persistent kernels launched without the cooperative flag (RSK_COOPERATIVE=0, read once per
-process, so the solves run in a child process): the same grid, hence the same iteration, bit for
-bit, as the cooperative launch, for the register-tile and general dense kernels, the CSR grid
-kernel and a batched launch."""
+process, so those solves run in a child process; the cooperative ones run in the test's own
+process, which holds the device's cooperative-launch resources once it has made such a launch):
+the same grid, hence the same iteration, bit for bit, for the register-tile and general dense
+kernels, the CSR grid kernel and a batched launch."""
 import os
 import subprocess
 import sys
@@ -15,11 +16,9 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-_CHILD = r'''
-import sys
+_SOLVES = r'''
 import numpy as np
 import torch
-sys.path.insert(0, sys.argv[1])
 from paper_2203_10838_amd import inputs, rsk
 dev = torch.device("cuda:0")
 T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -43,23 +42,31 @@ for i in range(3):
 rb = rsk.solve_batched(sys_)
 for i in range(3):
     out[f"batched{i}"] = rb.x_star[i].cpu().numpy()
-np.savez(sys.argv[2], **out)
 '''
 
+_CHILD = "import sys\nsys.path.insert(0, sys.argv[1])\n" + _SOLVES + "np.savez(sys.argv[2], **out)\n"
 
-def _run(tmp_path, coop):
-    f = str(tmp_path / f"out_{coop}.npz")
-    env = dict(os.environ, RSK_COOPERATIVE=coop)
-    print(f"child solve, RSK_COOPERATIVE={coop}", flush=True)
+
+def _plain(tmp_path):
+    f = str(tmp_path / "out_plain.npz")
+    env = dict(os.environ, RSK_COOPERATIVE="0")
+    print("child solve, RSK_COOPERATIVE=0", flush=True)
     res = subprocess.run([sys.executable, "-c", _CHILD, ROOT, f], env=env, capture_output=True, text=True,
                          timeout=240)
     assert res.returncode == 0, res.stderr[-2000:]
     return dict(np.load(f))
 
 
-def test_plain_launch_equals_cooperative(rsk_lib, tmp_path):
-    plain = _run(tmp_path, "0")
-    coop = _run(tmp_path, "1")
+def _cooperative():
+    assert os.environ.get("RSK_COOPERATIVE", "1") != "0", "the test process must launch cooperatively"
+    scope = {}
+    exec(_SOLVES, scope)
+    return scope["out"]
+
+
+def test_plain_launch_equals_cooperative(rsk_lib, cuda, tmp_path):
+    coop = _cooperative()
+    plain = _plain(tmp_path)
     assert sorted(plain) == sorted(coop)
     for k in coop:
         assert np.array_equal(plain[k], coop[k]), k
