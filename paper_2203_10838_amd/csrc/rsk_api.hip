@@ -658,7 +658,7 @@ int32_t adj_layout(const rsk_dense* A, int32_t R, const rsk_params* p, int32_t c
   L->offRh = o; o = align256(o + (size_t)C * er);
   L->offX = o; o = align256(o + nr);
   L->offZbar = o; o = align256(o + nr);
-  L->offAbar = o; o = align256(o + rsk::adjoint_abar_parts(p->K) * sizeof(double));
+  L->offAbar = o; o = align256(o + rsk::adjoint_abar_parts(p->K, pl.eta_pad, R) * sizeof(double));
   L->offLam = o; o = align256(o + rsk::adjoint_lam_parts(A->n, R, p->K) * sizeof(double));
   L->bytes = o;
   return RSK_OK;

@@ -212,7 +212,7 @@ struct AdjointArgs {
 };
 constexpr int kAdjMaxEtaHost = 4096;
 size_t adjoint_lam_parts(int64_t n, int R, int64_t K);
-size_t adjoint_abar_parts(int64_t K);
+size_t adjoint_abar_parts(int64_t K, int eta_pad, int R);
 hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream);
 
 // Batched independent systems. System s is solved by G_s workgroups running

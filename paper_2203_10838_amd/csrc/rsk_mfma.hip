@@ -1216,7 +1216,12 @@ hipError_t launch_multirhs_persistent(const MultiRhsArgs& a, const MrpWork& w, i
 // over workgroups go through per-block partials added in a fixed order.
 // ---------------------------------------------------------------------------
 
-constexpr int kAdjCoefBlocks = 64;
+// workgroups of adj_coef_bbar: one (t, r) element a thread up to this many, grid-stride beyond
+constexpr int kAdjCoefBlocks = 1024;
+__host__ __device__ inline int adj_coef_blocks(int eta_pad, int R) {
+  const int64_t b = ((int64_t)eta_pad * R + 255) / 256;
+  return (int)(b < 1 ? 1 : b > kAdjCoefBlocks ? kAdjCoefBlocks : b);
+}
 
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1247,41 +1252,9 @@ __global__ __launch_bounds__(256) void adj_seed(const float* __restrict__ zK, co
   if (threadIdx.x == 0) lam_part[blockIdx.x] = status[0] ? 0.0 : t;
 }
 
-// rbar and the alphabar partials of step k. grid = kAdjCoefBlocks, grid-stride over eta_pad x R.
-__global__ __launch_bounds__(256) void adj_coef(const float* __restrict__ Y, int S, int eta_pad,
-                                                const int32_t* __restrict__ tau, int eta, const float* __restrict__ Rk,
-                                                int R, const float* __restrict__ r2, const float* __restrict__ alpha_k,
-                                                int64_t k, float* __restrict__ Rbar, double* __restrict__ abar_part,
-                                                const int* status) {
-  __shared__ double red[4];
-  const size_t total = (size_t)eta_pad * R;
-  const float ak = alpha_k[k];
-  double acc = 0.0;
-  if (!status[0]) {
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-      const int t = (int)(e / R);
-      float rb = 0.f;
-      if (t < eta) {
-        const float y = split_sum(Y, S, total, e);
-        const float cbar = -y;
-        const float rn = r2[tau[t]];
-        rb = (ak / (float)eta) * cbar / rn;
-        acc += (double)cbar * (double)Rk[e] / ((double)eta * (double)rn);
-      }
-      Rbar[e] = rb;
-    }
-  }
-  const double t = block_sum_d(acc, red);
-  if (threadIdx.x == 0) abar_part[k * kAdjCoefBlocks + blockIdx.x] = t;
-}
-
-// Bbar[tau_t][r] -= rbar[t][r]; rows repeated within the step are summed in
-// ascending t by their first occurrence (no two threads touch one element).
-// Every workgroup builds an LDS hash table of the step's rows (first
-// occurrence and count per row), then takes one (t, r) element per thread,
-// so all read-modify-writes are in flight at once; only a repeated row scans
-// for its later occurrences. grid = ceil(eta * R / 256); dynamic LDS
-// adj_bbar_lds(eta) bytes (table size H = the power of two >= 2 eta).
+// The step's rows in an LDS hash table (first occurrence and count per row, table size H = the
+// power of two >= 2 eta) and the positions of the repeated ones: adj_hash_size(eta) slots,
+// adj_bbar_lds(eta) bytes.
 constexpr int kAdjMaxEta = 4096;
 __host__ __device__ inline int adj_hash_size(int eta) {
   int h = 16;
@@ -1290,67 +1263,99 @@ __host__ __device__ inline int adj_hash_size(int eta) {
 }
 size_t adj_bbar_lds(int eta) { return (size_t)adj_hash_size(eta) * 12 + (size_t)eta * 8 + 16; }
 
-__global__ __launch_bounds__(256) void adj_bbar(const int32_t* __restrict__ tau, int eta,
-                                                const float* __restrict__ Rbar, int R, float* __restrict__ Bbar,
-                                                const int* status) {
+// rbar = (alpha_k/eta) D^-2 cbar and the alphabar partials of step k (grid-stride over eta_pad x R,
+// grid = adj_coef_blocks(eta_pad, R)), and Bbar[tau_t][r] -= rbar[t][r] for the same elements: rows repeated
+// within the step are summed in ascending t by their first occurrence (no two threads touch one
+// element of Bbar), which adds the rbar of the later occurrences, recomputed from the split
+// partials with the same operations (the values stored for them, bit for bit), so no element waits
+// for another workgroup. Every workgroup builds the step's hash table of rows. Dynamic LDS
+// adj_bbar_lds(eta) bytes.
+__global__ __launch_bounds__(256) void adj_coef_bbar(const float* __restrict__ Y, int S, int eta_pad,
+                                                     const int32_t* __restrict__ tau, int eta,
+                                                     const float* __restrict__ Rk, int R, const float* __restrict__ r2,
+                                                     const float* __restrict__ alpha_k, int64_t k,
+                                                     float* __restrict__ Rbar, double* __restrict__ abar_part,
+                                                     float* __restrict__ Bbar, const int* status) {
   extern __shared__ int hsm[];
-  if (status[0]) return;
+  __shared__ double red[4];
   const int H = adj_hash_size(eta);
   int* hkey = hsm;
   int* hmin = hsm + H;
   int* hcnt = hsm + 2 * H;
   int* st = hsm + 3 * H;
-  int* dup = st + eta;   // positions of the repeated rows, in no particular order
+  int* dup = st + eta;
   int* ndup = dup + eta;
-  for (int i = threadIdx.x; i < H; i += blockDim.x) {
-    hkey[i] = -1;
-    hmin[i] = INT_MAX;
-    hcnt[i] = 0;
-  }
-  if (threadIdx.x == 0) *ndup = 0;
-  for (int t = threadIdx.x; t < eta; t += blockDim.x) st[t] = tau[t];
-  __syncthreads();
-  for (int t = threadIdx.x; t < eta; t += blockDim.x) {
-    const int key = st[t];
-    int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
-    for (;;) {  // at most eta distinct keys in a table of H >= 2 eta slots: a free or matching slot exists
-      const int prev = atomicCAS(&hkey[h], -1, key);
-      if (prev == -1 || prev == key) break;
-      h = (h + 1) & (H - 1);
+  const size_t total = (size_t)eta_pad * R;
+  const float ak = alpha_k[k];
+  double acc = 0.0;
+  const bool live = status[0] == 0;
+  if (live) {
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+      hkey[i] = -1;
+      hmin[i] = INT_MAX;
+      hcnt[i] = 0;
     }
-    atomicMin(&hmin[h], t);
-    atomicAdd(&hcnt[h], 1);
+    if (threadIdx.x == 0) *ndup = 0;
+    for (int t = threadIdx.x; t < eta; t += blockDim.x) st[t] = tau[t];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < eta; t += blockDim.x) {
-    const int key = st[t];
-    int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
-    while (hkey[h] != key) h = (h + 1) & (H - 1);
-    if (hcnt[h] > 1) dup[atomicAdd(ndup, 1)] = t;
-  }
-  __syncthreads();
-  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (e >= (size_t)eta * R) return;
-  const int t = (int)(e / R), r = (int)(e % R);
-  const int key = st[t];
-  int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
-  while (hkey[h] != key) h = (h + 1) & (H - 1);
-  if (hmin[h] != t) return;
-  float sum = Rbar[(size_t)t * R + r];
-  const int cnt = hcnt[h], nd = *ndup;
-  // the other occurrences of the row, in ascending position: each pass takes the smallest
-  // position above the last one among the repeated rows
-  for (int c = 1, last = t; c < cnt; ++c) {
-    int next = INT_MAX;
-    for (int i = 0; i < nd; ++i) {
-      const int u = dup[i];
-      if (u > last && u < next && st[u] == key) next = u;
+  if (live)
+    for (int t = threadIdx.x; t < eta; t += blockDim.x) {
+      const int key = st[t];
+      int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
+      for (;;) {  // at most eta distinct keys in a table of H >= 2 eta slots: a free or matching slot exists
+        const int prev = atomicCAS(&hkey[h], -1, key);
+        if (prev == -1 || prev == key) break;
+        h = (h + 1) & (H - 1);
+      }
+      atomicMin(&hmin[h], t);
+      atomicAdd(&hcnt[h], 1);
     }
-    if (next == INT_MAX) break;  // cannot happen: every occurrence of a repeated row is listed
-    sum += Rbar[(size_t)next * R + r];
-    last = next;
+  __syncthreads();
+  if (live)
+    for (int t = threadIdx.x; t < eta; t += blockDim.x) {
+      const int key = st[t];
+      int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
+      while (hkey[h] != key) h = (h + 1) & (H - 1);
+      if (hcnt[h] > 1) dup[atomicAdd(ndup, 1)] = t;
+    }
+  __syncthreads();
+  if (live) {
+    const int nd = *ndup;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+      const int t = (int)(e / R), r = (int)(e % R);
+      float rb = 0.f;
+      if (t < eta) {
+        const int key = st[t];
+        const float cbar = -split_sum(Y, S, total, e);
+        const float rn = r2[key];
+        rb = (ak / (float)eta) * cbar / rn;
+        acc += (double)cbar * (double)Rk[e] / ((double)eta * (double)rn);
+        int h = (int)(((unsigned)key * 2654435761u) & (unsigned)(H - 1));
+        while (hkey[h] != key) h = (h + 1) & (H - 1);
+        if (hmin[h] == t) {
+          float sum = rb;
+          const int cnt = hcnt[h];
+          // the other occurrences of the row, in ascending position
+          for (int c = 1, last = t; c < cnt; ++c) {
+            int next = INT_MAX;
+            for (int i = 0; i < nd; ++i) {
+              const int u = dup[i];
+              if (u > last && u < next && st[u] == key) next = u;
+            }
+            if (next == INT_MAX) break;  // cannot happen: every occurrence of a repeated row is listed
+            const float cb2 = -split_sum(Y, S, total, (size_t)next * R + r);
+            sum += (ak / (float)eta) * cb2 / rn;
+            last = next;
+          }
+          Bbar[(int64_t)key * R + r] -= sum;
+        }
+      }
+      Rbar[e] = rb;
+    }
   }
-  Bbar[(int64_t)key * R + r] -= sum;
+  const double t = block_sum_d(acc, red);
+  if (threadIdx.x == 0) abar_part[k * gridDim.x + blockIdx.x] = t;
 }
 
 // xbar = A_tau^T Rbar (MFMA as gemm_att_c_update); epilogue zbar += m_k . xbar and the
@@ -1462,14 +1467,14 @@ __global__ __launch_bounds__(NTH) void att_reduce_adj(const float* __restrict__ 
 }
 
 // alpha_bar[k] = sum of the step's partials; lambda_bar = seed partials, then steps 0..K-1, each in order.
-__global__ __launch_bounds__(256) void adj_finish(const double* __restrict__ abar_part,
+__global__ __launch_bounds__(256) void adj_finish(const double* __restrict__ abar_part, int nblk_coef,
                                                   const double* __restrict__ lam_part, int64_t K, int nblk_att,
                                                   float* __restrict__ alpha_bar, double* __restrict__ lambda_bar,
                                                   const int* status) {
   __shared__ double red[256];
   for (int64_t k = threadIdx.x; k < K; k += blockDim.x) {
     double s = 0.0;
-    for (int b = 0; b < kAdjCoefBlocks; ++b) s += abar_part[k * kAdjCoefBlocks + b];
+    for (int b = 0; b < nblk_coef; ++b) s += abar_part[k * nblk_coef + b];
     alpha_bar[k] = status[0] ? 0.f : (float)s;
   }
   // lam_part: [kAdjSeedBlocks] seed, then K x nblk_att
@@ -1496,7 +1501,9 @@ size_t adjoint_lam_parts(int64_t n, int R, int64_t K) {
   const int gn = (int)((n + BM - 1) / BM);
   return kAdjSeedBlocks + (size_t)K * gn * gr;
 }
-size_t adjoint_abar_parts(int64_t K) { return (size_t)(K > 0 ? K : 1) * kAdjCoefBlocks; }
+size_t adjoint_abar_parts(int64_t K, int eta_pad, int R) {
+  return (size_t)(K > 0 ? K : 1) * adj_coef_blocks(eta_pad, R);
+}
 
 hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
   const MultiRhsArgs& a = d.f;
@@ -1506,7 +1513,8 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
   const int gr = (a.R + BN - 1) / BN;
   const int gn = (int)((a.n + BM - 1) / BM);
   const int nblk_att = gn * gr;
-  if (hipFuncSetAttribute((const void*)&adj_bbar, hipFuncAttributeMaxDynamicSharedMemorySize,
+  const int nblk_coef = adj_coef_blocks(a.eta_pad, a.R);
+  if (hipFuncSetAttribute((const void*)&adj_coef_bbar, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)adj_bbar_lds(a.eta)) != hipSuccess)
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(fill_zero_f32, dim3(1024), dim3(256), 0, stream, d.Bbar, (size_t)a.m * a.R);
@@ -1534,10 +1542,9 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
       const int64_t j = k - k0;
       const int32_t* tk = a.idx + k * (int64_t)a.eta;
       launch_at_x(a, tk, d.zbar, 0, k, stream);
-      hipLaunchKernelGGL(adj_coef, dim3(kAdjCoefBlocks), dim3(256), 0, stream, a.Y, a.S, a.eta_pad, tk, a.eta,
-                         d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part, a.status);
-      hipLaunchKernelGGL(adj_bbar, dim3((unsigned)(((size_t)a.eta * a.R + 255) / 256)), dim3(256),
-                         adj_bbar_lds(a.eta), stream, tk, a.eta, a.C, a.R, d.Bbar, a.status);
+      hipLaunchKernelGGL(adj_coef_bbar, dim3(nblk_coef), dim3(256), adj_bbar_lds(a.eta), stream, a.Y, a.S,
+                         a.eta_pad, tk, a.eta, d.Rh + (size_t)j * etot, a.R, a.r2, a.alpha_k, k, a.C, d.abar_part,
+                         d.Bbar, a.status);
       if (a.S2 > 1) {
         if (a.tile == 128)
           launch_att(a, tk, a.C, nullptr, nullptr, false, stream);
@@ -1562,7 +1569,8 @@ hipError_t launch_adjoint(const AdjointArgs& d, hipStream_t stream) {
       }
     }
   }
-  hipLaunchKernelGGL(adj_finish, dim3(1), dim3(256), 0, stream, d.abar_part, d.lam_part, a.K, nblk_att, d.alpha_bar,
+  hipLaunchKernelGGL(adj_finish, dim3(1), dim3(256), 0, stream, d.abar_part, nblk_coef, d.lam_part, a.K, nblk_att,
+                     d.alpha_bar,
                      d.lambda_bar, a.status);
   return hipGetLastError();
 }
