@@ -486,6 +486,9 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   // are split over S2 workgroups (at least 64 rows each) and summed in a second kernel
   const int att_tiles = (int)((A->n + pl->tile - 1) / pl->tile) * ((R + tn - 1) / tn);
   int S2 = cus / att_tiles;
+  // the wide tiles' fused update (no row split) runs 128 x 64 tiles: when those fill the device
+  // there is nothing to split
+  if (pl->tile == 128 && R > 64 && ((A->n + 127) / 128) * ((R + 63) / 64) >= cus) S2 = 1;
   // at least 64 rows a split by the built-in rule, at least 16 for a tuned split
   const int max_s2 = tuned && te.v1 >= 1 ? (p->eta + 15) / 16 : (p->eta + 63) / 64;
   if (S2 > max_s2) S2 = max_s2;

@@ -457,30 +457,34 @@ __global__ void init_multirhs(float* Xs, float* X, size_t total, float lambda, i
 namespace {
 
 constexpr int SKW = 32;  // K per stage of the wide-tile products
+// The wide-tile products run 512 threads: 8 waves in a 4 x 2 grid over the tile, two a SIMD, so
+// that one wave's MFMAs cover the other's LDS reads and barriers (with one wave a SIMD they are
+// exposed: these grids put about one workgroup on each CU).
+constexpr int NTW = 512, WGM = 4, WGN = 2;
 
 template <int TN>
 struct WideMap {  // a row of TN floats: TN/4 float4 across consecutive threads
   static constexpr int cpr = TN / 4;           // float4 per row
-  static constexpr int rpp = NTH / cpr;        // rows per pass
+  static constexpr int rpp = NTW / cpr;        // rows per pass
   static constexpr int passes = SKW / rpp;     // passes over the SKW rows of a stage
 };
 
 template <int TM, int TN>
 __device__ __forceinline__ void mma_stage_w(const float* As, int a_rows, const float* Bs, int wm, int wn,
-                                            int lane, f4 (&acc)[TM / 32][TN / 32]) {
+                                            int lane, f4 (&acc)[TM / (16 * WGM)][TN / (16 * WGN)]) {
   // a_rows: As is row-major [TM][SKW + 4] (true) or k-major [SKW][TM + 16] (false)
-  constexpr int BI = TM / 32, BJ = TN / 32, PB = TN + 16, PA = TM + 16, LDR = SKW + 4;
+  constexpr int BI = TM / (16 * WGM), BJ = TN / (16 * WGN), PB = TN + 16, PA = TM + 16, LDR = SKW + 4;
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int k0 = 0; k0 < SKW; k0 += 4) {
     float a[BI], b[BJ];
 #pragma unroll
     for (int i = 0; i < BI; ++i) {
-      const int m = wm * (TM / 2) + i * 16 + li;
+      const int m = wm * (TM / WGM) + i * 16 + li;
       a[i] = a_rows ? As[m * LDR + k0 + lk] : As[(k0 + lk) * PA + m];
     }
 #pragma unroll
-    for (int j = 0; j < BJ; ++j) b[j] = Bs[(k0 + lk) * PB + wn * (TN / 2) + j * 16 + li];
+    for (int j = 0; j < BJ; ++j) b[j] = Bs[(k0 + lk) * PB + wn * (TN / WGN) + j * 16 + li];
 #pragma unroll
     for (int i = 0; i < BI; ++i)
 #pragma unroll
@@ -494,10 +498,12 @@ template <int TM, int TN>
 __device__ __forceinline__ void att_mainloop_w(const float* __restrict__ A, int64_t ld, int64_t n,
                                                const int* taus, int eta, const float* __restrict__ C, int R,
                                                int64_t j0, int r0, float* As, float* Bs,
-                                               f4 (&acc)[TM / 32][TN / 32]) {
+                                               f4 (&acc)[TM / (16 * WGM)][TN / (16 * WGN)]) {
   using MA = WideMap<TM>;
   using MB = WideMap<TN>;
   constexpr int PA = TM + 16, PB = TN + 16;
+  static_assert(MA::passes >= 1 && MB::passes >= 1 && MA::passes * MA::rpp == SKW && MB::passes * MB::rpp == SKW,
+                "a stage's rows split into whole passes");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int ar = tid / MA::cpr, ac = (tid % MA::cpr) * 4;
@@ -565,11 +571,11 @@ __device__ __forceinline__ void att_mainloop_w(const float* __restrict__ A, int6
 }
 
 template <int TM, int TN>
-__device__ __forceinline__ void zero_acc(f4 (&acc)[TM / 32][TN / 32]) {
+__device__ __forceinline__ void zero_acc(f4 (&acc)[TM / (16 * WGM)][TN / (16 * WGN)]) {
 #pragma unroll
-  for (int i = 0; i < TM / 32; ++i)
+  for (int i = 0; i < TM / (16 * WGM); ++i)
 #pragma unroll
-    for (int j = 0; j < TN / 32; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TN / (16 * WGN); ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 }
 
 }  // namespace
@@ -577,7 +583,7 @@ __device__ __forceinline__ void zero_acc(f4 (&acc)[TM / 32][TN / 32]) {
 // Y[s][t][r] = sum_{j in split s} A[tau_t, j] X[j, r], TM x TN tiles (eta_pad a multiple of TM).
 // Grid, XCD order, index check and status as gemm_at_x.
 template <int TM, int TN>
-__global__ __launch_bounds__(NTH) void gemm_at_x_w(const float* __restrict__ A, int64_t ld, int64_t n,
+__global__ __launch_bounds__(NTW) void gemm_at_x_w(const float* __restrict__ A, int64_t ld, int64_t n,
                                                    const int32_t* __restrict__ tau, int eta,
                                                    const float* __restrict__ X, int R, float* __restrict__ Y,
                                                    int eta_pad, int64_t kspan, int gt, int gr, int S, int* status,
@@ -609,6 +615,7 @@ __global__ __launch_bounds__(NTH) void gemm_at_x_w(const float* __restrict__ A, 
 
   // A: thread -> row t0 + ar + MA::rpp * i (TM / MA::rpp rows), 4 columns at ac of the stage
   constexpr int AP = TM / MA::rpp;
+  static_assert(AP * MA::rpp == TM && MB::passes >= 1 && MB::passes * MB::rpp == SKW, "whole passes");
   const int ar = tid / MA::cpr, ac = (tid % MA::cpr) * 4;
   const float* arow[AP];
   int bad = 0;
@@ -659,7 +666,7 @@ __global__ __launch_bounds__(NTH) void gemm_at_x_w(const float* __restrict__ A, 
       *reinterpret_cast<float4*>(&Bs[(br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
     __syncthreads();
   };
-  f4 acc[TM / 32][TN / 32];
+  f4 acc[TM / (16 * WGM)][TN / (16 * WGN)];
   zero_acc<TM, TN>(acc);
   // two register buffers, stages in pairs with unconditional loads (as att_mainloop_w)
   const int npair = j_end > j_begin ? (int)((j_end - j_begin + 2 * SKW - 1) / (2 * SKW)) : 0;
@@ -683,13 +690,13 @@ __global__ __launch_bounds__(NTH) void gemm_at_x_w(const float* __restrict__ A, 
   // D layout: column lane%16, rows 4*(lane/16) + v
   float* Ys = Y + (size_t)s * eta_pad * R;
 #pragma unroll
-  for (int i = 0; i < TM / 32; ++i)
+  for (int i = 0; i < TM / (16 * WGM); ++i)
 #pragma unroll
-    for (int j = 0; j < TN / 32; ++j)
+    for (int j = 0; j < TN / (16 * WGN); ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int t = t0 + wm * (TM / 2) + i * 16 + 4 * (lane >> 4) + v;
-        const int r = r0 + wn * (TN / 2) + j * 16 + (lane & 15);
+        const int t = t0 + wm * (TM / WGM) + i * 16 + 4 * (lane >> 4) + v;
+        const int r = r0 + wn * (TN / WGN) + j * 16 + (lane & 15);
         if (r < R) Ys[(size_t)t * R + r] = acc[i][j][v];
       }
 }
@@ -698,7 +705,7 @@ __global__ __launch_bounds__(NTH) void gemm_at_x_w(const float* __restrict__ A, 
 // UPDATE (S2 = 1): Zout = Zin - W, X = S_lambda(Zout); else W goes to Wp[s2] (summed by
 // att_reduce_update / att_reduce_adj). grid = (ceil(n/TM), ceil(R/TN), S2).
 template <int TM, int TN, bool UPDATE>
-__global__ __launch_bounds__(NTH) void gemm_att_w(const float* __restrict__ A, int64_t ld, int64_t n,
+__global__ __launch_bounds__(NTW) void gemm_att_w(const float* __restrict__ A, int64_t ld, int64_t n,
                                                   const int32_t* __restrict__ tau, int eta,
                                                   const float* __restrict__ C, int R, const float* Zin, float* Zout,
                                                   float* __restrict__ X, float lambda, float* __restrict__ Wp,
@@ -716,18 +723,18 @@ __global__ __launch_bounds__(NTH) void gemm_att_w(const float* __restrict__ A, i
   stage_tau(tau + tb0, tb1 - tb0, taus);
   __syncthreads();
   if (st0) return;
-  f4 acc[TM / 32][TN / 32];
+  f4 acc[TM / (16 * WGM)][TN / (16 * WGN)];
   zero_acc<TM, TN>(acc);
   att_mainloop_w<TM, TN>(A, ld, n, taus, tb1 - tb0, C + (size_t)tb0 * R, R, j0, r0, As, Bs, acc);
   float* W = UPDATE ? nullptr : Wp + (size_t)s2 * n * R;
 #pragma unroll
-  for (int i = 0; i < TM / 32; ++i)
+  for (int i = 0; i < TM / (16 * WGM); ++i)
 #pragma unroll
-    for (int j = 0; j < TN / 32; ++j)
+    for (int j = 0; j < TN / (16 * WGN); ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t jj = j0 + wm * (TM / 2) + i * 16 + 4 * (lane >> 4) + v;
-        const int r = r0 + wn * (TN / 2) + j * 16 + (lane & 15);
+        const int64_t jj = j0 + wm * (TM / WGM) + i * 16 + 4 * (lane >> 4) + v;
+        const int r = r0 + wn * (TN / WGN) + j * 16 + (lane & 15);
         if (jj < n && r < R) {
           const size_t o = (size_t)jj * R + r;
           if constexpr (UPDATE) {
@@ -816,10 +823,10 @@ static void launch_at_x(const MultiRhsArgs& a, const int32_t* tk, const float* X
     const int gt = a.eta_pad / 128;
     if (a.R > 64) {
       const int gr = (a.R + 127) / 128;
-      hipLaunchKernelGGL((gemm_at_x_w<128, 128>), dim3(gt * gr * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk,
+      hipLaunchKernelGGL((gemm_at_x_w<128, 128>), dim3(gt * gr * a.S), dim3(NTW), 0, stream, a.A, a.ld, a.n, tk,
                          a.eta, X, a.R, a.Y, a.eta_pad, a.kspan, gt, gr, a.S, a.status, m, k);
     } else {
-      hipLaunchKernelGGL((gemm_at_x_w<128, 64>), dim3(gt * a.S), dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta,
+      hipLaunchKernelGGL((gemm_at_x_w<128, 64>), dim3(gt * a.S), dim3(NTW), 0, stream, a.A, a.ld, a.n, tk, a.eta,
                          X, a.R, a.Y, a.eta_pad, a.kspan, gt, 1, a.S, a.status, m, k);
     }
     return;
@@ -835,23 +842,21 @@ static void launch_at_x(const MultiRhsArgs& a, const int32_t* tk, const float* X
 static void launch_att(const MultiRhsArgs& a, const int32_t* tk, const float* C, const float* zin, float* zout,
                        bool update, hipStream_t stream) {
   const unsigned gn = (unsigned)((a.n + 127) / 128), z = update ? 1u : (unsigned)a.S2;
-  if (a.R > 64) {
+  if (a.R > 64 && !update) {
     const dim3 g(gn, (unsigned)((a.R + 127) / 128), z);
-    if (update)
-      hipLaunchKernelGGL((gemm_att_w<128, 128, true>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
-                         zin, zout, a.x, a.lambda, a.Wp, a.status);
-    else
-      hipLaunchKernelGGL((gemm_att_w<128, 128, false>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
-                         zin, zout, a.x, a.lambda, a.Wp, a.status);
-  } else {
-    const dim3 g(gn, 1, z);
-    if (update)
-      hipLaunchKernelGGL((gemm_att_w<128, 64, true>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
-                         zin, zout, a.x, a.lambda, a.Wp, a.status);
-    else
-      hipLaunchKernelGGL((gemm_att_w<128, 64, false>), g, dim3(NTH), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
-                         zin, zout, a.x, a.lambda, a.Wp, a.status);
+    hipLaunchKernelGGL((gemm_att_w<128, 128, false>), g, dim3(NTW), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R,
+                       zin, zout, a.x, a.lambda, a.Wp, a.status);
+    return;
   }
+  // The fused update (no row split) takes 128 x 64 tiles at every R: twice the workgroups of
+  // 128 x 128 tiles, and no partials to reduce.
+  const dim3 g(gn, (unsigned)((a.R + 63) / 64), z);
+  if (update)
+    hipLaunchKernelGGL((gemm_att_w<128, 64, true>), g, dim3(NTW), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R, zin,
+                       zout, a.x, a.lambda, a.Wp, a.status);
+  else
+    hipLaunchKernelGGL((gemm_att_w<128, 64, false>), g, dim3(NTW), 0, stream, a.A, a.ld, a.n, tk, a.eta, C, a.R, zin,
+                       zout, a.x, a.lambda, a.Wp, a.status);
 }
 
 // One forward step k: R_tau from x (with the step's index check), C, Zout = Zin - A_tau^T C,

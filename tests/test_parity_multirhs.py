@@ -17,11 +17,12 @@ def _t(a, dev):
 
 @pytest.mark.parametrize("kernel", [0, 3])
 @pytest.mark.parametrize("m,n,R,eta,K", [(3000, 1000, 64, 100, 40), (2000, 516, 12, 37, 60), (5000, 2048, 128, 300, 15),
-                                         (300, 64, 4, 5, 200), (4000, 1288, 200, 150, 12)])
+                                         (300, 64, 4, 5, 200), (4000, 1288, 200, 150, 12), (3000, 700, 200, 50, 30)])
 def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K, kernel):
     """Kernel 0 is the library's choice (64 x 64 product tiles), kernel 3 the wide tiles (128 x 128,
-    128 x 64 for R <= 64): ragged n (516, 1288), R below, at and above one wide tile (12, 64, 128,
-    200), the row-split update (S2 > 1) and the direct one (eta <= 64)."""
+    128 x 64 for R <= 64 and for the fused update): ragged n (516, 700, 1288), R below, at and above
+    one wide tile (12, 64, 128, 200), the row-split update (S2 > 1) and the direct one (eta <= 64,
+    also at R = 200: four 64-column update tiles, the last one ragged)."""
     from paper_2203_10838_amd import rsk
     sysd = inputs.multirhs_system(m, n, R, max(1, n // 20), seed=m + R)
     A, B = sysd["A"], sysd["B"]
@@ -76,9 +77,9 @@ def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib, kernel)
     """The shared-A workload at its own shape: A 32768 x 8192 float32 N(0,1) drawn on the device,
     R = 256 right-hand sides B = A X_hat (5% N(0,1) nonzeros a column), eta = 820, alpha = alpha*,
     lambda = 1, 20 steps. Kernel 1: its 512 output tiles of 64 x 64 run the A_tau^T C update
-    without a row split over 13 stages of 64 rows. Kernel 3: 128 x 128 tiles (eta padded to 896),
-    the update split over the sampled rows in two halves of 13 stages of 32. Eight seeded columns
-    against the FP64 oracle on the rows the stream touches."""
+    without a row split over 13 stages of 64 rows. Kernel 3: R_tau on 128 x 128 tiles (eta padded to
+    896), the fused update on 128 x 64 tiles (256 of them, no row split) over 26 stages of 32 rows.
+    Eight seeded columns against the FP64 oracle on the rows the stream touches."""
     import torch
     from paper_2203_10838_amd import rsk
     m, n, R, eta, K, lam, seed = 32768, 8192, 256, 820, 20, 1.0, 20310838 + 300 + 7
@@ -106,7 +107,8 @@ def test_multirhs_shared_a_workload_shape_sampled_columns(cuda, rsk_lib, kernel)
     if kernel == 1:
         assert plan["S2"] == 1 and plan["eta_pad"] == 832, plan
     else:
-        assert plan["kernel"] == 3 and plan["S2"] == 2 and plan["eta_pad"] == 896, plan
+        # 64 x 4 update tiles of 128 x 64 fill the 256 CUs: no row split
+        assert plan["kernel"] == 3 and plan["S2"] == 1 and plan["eta_pad"] == 896, plan
     idx = inputs.index_stream(wn, K, eta, seed + 1)
     res = rsk.solve_multirhs(A, B, lam=lam, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=kernel)
     assert res.status == 0 and res.k_done == K
