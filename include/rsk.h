@@ -461,9 +461,11 @@ int32_t rsk_plan_batched(int32_t nsys, int32_t dtype, const rsk_batch_item *item
  * tiles), 2 = one persistent cooperative launch for all K steps (the same
  * products and sums as the step kernels, tiles passed between workgroups
  * through device-coherent stores and per-tile counters), 3 = the step kernels
- * with wide product tiles (128 x 128, or 128 x 64 when R <= 64; eta padded to
- * a multiple of 128), 0 = a tuned choice (rsk_tune_*), else 1. Kernels 1 and 3
- * compute the same iteration with differently blocked sums (equal to rounding).
+ * with wide product tiles (128 x 128 for A_tau X, 128 x 64 for the fused update
+ * and whenever R <= 64; 512-thread workgroups; eta padded to a multiple of 128),
+ * 0 = a tuned choice (rsk_tune_*), else 3 when R > 64 and eta >= 128, else 1.
+ * Kernels 1 and 3 compute the same iteration with differently blocked sums
+ * (equal to rounding).
  * Device faults and status_dev follow the single-RHS conventions (with kernel
  * 2, X* and X are unspecified after a fault).
  */

@@ -466,14 +466,19 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   const int cus = device_cus() > 0 ? device_cus() : 256;
   rsk_tune_entry te;
   const bool tuned = tune_find(RSK_TUNE_MULTIRHS, A->dtype, A->m, A->n, p->eta, R, &te);
-  // the kernel: p->kernel 1, 2 or 3 as asked, else a tuned choice, else the step kernels
-  pl->kernel = p->kernel >= 1 ? p->kernel : (tuned && te.v2 >= 1 && te.v2 <= 3 ? (int)te.v2 : 1);
+  // the kernel: p->kernel 1, 2 or 3 as asked, else a tuned choice, else the wide-tile step kernels
+  // when R and eta each fill at least one 128 tile, the 64 x 64 ones below that
+  pl->kernel = p->kernel >= 1 ? p->kernel
+             : (tuned && te.v2 >= 1 && te.v2 <= 3 ? (int)te.v2 : (R > 64 && p->eta >= 128 ? 3 : 1));
   pl->tile = pl->kernel == 3 ? 128 : 64;
   const int tn = pl->tile == 128 && R <= 64 ? 64 : pl->tile;  // the R edge of a product tile
   pl->eta_pad = (p->eta + pl->tile - 1) / pl->tile * pl->tile;
   const int tiles = (pl->eta_pad / pl->tile) * ((R + tn - 1) / tn);
-  int S = (3 * cus + tiles - 1) / tiles;  // about three workgroups per CU for the n-long products
-  if (S >= 8) S = (S + 7) / 8 * 8;        // whole XCD rounds: the tiles of a split share one L2
+  // about three 256-thread workgroups per CU for the n-long products, or one 512-thread wide-tile
+  // workgroup (rounded down: a second round on some CUs costs more than a few idle ones), in whole
+  // XCD rounds (the tiles of a split share one L2)
+  int S = pl->tile == 128 ? cus / tiles : (3 * cus + tiles - 1) / tiles;
+  if (S >= 8) S = pl->tile == 128 ? S / 8 * 8 : (S + 7) / 8 * 8;
   if (tuned && te.v0 >= 1) S = (int)(te.v0 < 4096 ? te.v0 : 4096);
   // at least 256 columns a split by the built-in rule, at least 64 (one stage) for a tuned split
   const int64_t max_s = tuned && te.v0 >= 1 ? (A->n + 63) / 64 : (A->n + 255) / 256;

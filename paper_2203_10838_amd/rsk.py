@@ -314,7 +314,7 @@ def solve_multirhs(A: torch.Tensor, B: torch.Tensor, *, lam: float, eta: int, al
     """K RSKA steps for the R columns of B (m x R) at once; X*, X are n x R (row-major).
 
     ``kernel``: 1 the step kernels, 2 one persistent launch for all K steps, 3 the step kernels with
-    wide product tiles, 0 the library's choice.
+    wide product tiles, 0 the library's choice (a tuned one, else 3 when R > 64 and eta >= 128, else 1).
 
     With ``ckpt`` (ceil(K/ckpt_every) x n x R float32) the x* checkpoints the
     adjoint recomputes from are written as well.

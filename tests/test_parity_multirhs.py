@@ -15,12 +15,13 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-@pytest.mark.parametrize("kernel", [0, 3])
+@pytest.mark.parametrize("kernel", [0, 1, 3])
 @pytest.mark.parametrize("m,n,R,eta,K", [(3000, 1000, 64, 100, 40), (2000, 516, 12, 37, 60), (5000, 2048, 128, 300, 15),
                                          (300, 64, 4, 5, 200), (4000, 1288, 200, 150, 12), (3000, 700, 200, 50, 30)])
 def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K, kernel):
-    """Kernel 0 is the library's choice (64 x 64 product tiles), kernel 3 the wide tiles (128 x 128,
-    128 x 64 for R <= 64 and for the fused update): ragged n (516, 700, 1288), R below, at and above
+    """Kernel 0 is the library's choice (the wide tiles when R > 64 and eta >= 128, else 64 x 64),
+    1 the 64 x 64 product tiles, 3 the wide tiles (128 x 128, 128 x 64 for R <= 64 and for the fused
+    update): ragged n (516, 700, 1288), R below, at and above
     one wide tile (12, 64, 128, 200), the row-split update (S2 > 1) and the direct one (eta <= 64,
     also at R = 200: four 64-column update tiles, the last one ragged)."""
     from paper_2203_10838_amd import rsk
@@ -31,9 +32,11 @@ def test_multirhs_matches_oracle_per_column(cuda, rsk_lib, m, n, R, eta, K, kern
     s = np.linalg.svd(A64, compute_uv=False)
     alpha = oracle.optimal_alpha(eta, float((A64 * A64).sum()), float(s[0] ** 2))
     At, Bt = _t(A, cuda), _t(B, cuda)
-    if kernel == 3:
-        plan = rsk.plan_multirhs(At, R, eta=eta, K=K, kernel=3)
+    plan = rsk.plan_multirhs(At, R, eta=eta, K=K, kernel=kernel)
+    if kernel == 3 or (kernel == 0 and R > 64 and eta >= 128):
         assert plan["kernel"] == 3 and plan["eta_pad"] % 128 == 0, plan
+    else:
+        assert plan["kernel"] == 1, plan
     res = rsk.solve_multirhs(At, Bt, lam=0.5, eta=eta, alpha=alpha, K=K, index_stream=_t(idx, cuda), kernel=kernel)
     assert res.status == 0 and res.k_done == K
     ref = oracle.rska_multirhs(A, B, 0.5, eta, alpha, K, idx)
