@@ -723,14 +723,29 @@ __global__ __launch_bounds__(NTW) void gemm_att_w(const float* __restrict__ A, i
   stage_tau(tau + tb0, tb1 - tb0, taus);
   __syncthreads();
   if (st0) return;
-  f4 acc[TM / (16 * WGM)][TN / (16 * WGN)];
+  constexpr int BI = TM / (16 * WGM), BJ = TN / (16 * WGN);
+  // the update's x* inputs load before the products (in flight under them), not after
+  float zin[UPDATE ? BI : 1][UPDATE ? BJ : 1][4];
+  if constexpr (UPDATE) {
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t jj = j0 + wm * (TM / WGM) + i * 16 + 4 * (lane >> 4) + v;
+          const int r = r0 + wn * (TN / WGN) + j * 16 + (lane & 15);
+          zin[i][j][v] = Zin[jj < n && r < R ? (size_t)jj * R + r : 0];
+        }
+  }
+  f4 acc[BI][BJ];
   zero_acc<TM, TN>(acc);
   att_mainloop_w<TM, TN>(A, ld, n, taus, tb1 - tb0, C + (size_t)tb0 * R, R, j0, r0, As, Bs, acc);
   float* W = UPDATE ? nullptr : Wp + (size_t)s2 * n * R;
 #pragma unroll
-  for (int i = 0; i < TM / (16 * WGM); ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < TN / (16 * WGN); ++j)
+    for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t jj = j0 + wm * (TM / WGM) + i * 16 + 4 * (lane >> 4) + v;
@@ -738,7 +753,7 @@ __global__ __launch_bounds__(NTW) void gemm_att_w(const float* __restrict__ A, i
         if (jj < n && r < R) {
           const size_t o = (size_t)jj * R + r;
           if constexpr (UPDATE) {
-            const float z = Zin[o] - acc[i][j][v];
+            const float z = zin[i][j][v] - acc[i][j][v];
             Zout[o] = z;
             X[o] = shrink(z, lambda);
           } else {
