@@ -535,39 +535,43 @@ __device__ __forceinline__ void att_mainloop_w(const float* __restrict__ A, int6
       st.kb[i] = t < eta && rok;
     }
   };
-  auto stage = [&](const Buf& st) {
+  constexpr int ASZ = SKW * PA, BSZ = SKW * PB;  // floats of one LDS buffer of each operand
+  auto put = [&](const Buf& st, int buf) {
     // nothing moves across: a select hoisted above this point would wait for the other buffer
     __builtin_amdgcn_sched_barrier(0);
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < MA::passes; ++i)
-      *reinterpret_cast<float4*>(&As[(ar + MA::rpp * i) * PA + ac]) = keep4(st.ka[i], st.a[i]);
+      *reinterpret_cast<float4*>(&As[buf * ASZ + (ar + MA::rpp * i) * PA + ac]) = keep4(st.ka[i], st.a[i]);
 #pragma unroll
     for (int i = 0; i < MB::passes; ++i)
-      *reinterpret_cast<float4*>(&Bs[(br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
-    __syncthreads();
+      *reinterpret_cast<float4*>(&Bs[buf * BSZ + (br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
   };
-  // Two register buffers: the loads of the next two stages are in flight during a stage's
-  // products (the workgroup is alone on its CU, so no other workgroup covers its load latency).
-  // The stages run in pairs with unconditional loads, so that each stage waits only for its own
-  // buffer; an odd count ends with a stage of zeros (adding exact zeros changes no sum).
+  // Two register buffers and two LDS buffers: stage s + 1 is stored to LDS while stage s's
+  // products run from the other buffer (one barrier a stage), and the loads of the stage after
+  // that are in flight meanwhile (the workgroup is alone on its CU, so no other workgroup covers
+  // its load latency). Stage j's loads go to register buffer j % 2, unconditionally, so each
+  // store waits only for its own buffer; an odd count ends with a stage of zeros (adding exact
+  // zeros changes no sum).
   const int npair = (eta + 2 * SKW - 1) / (2 * SKW);
   if (npair == 0) return;
   Buf b0, b1;
   load(0, b0);
   load(SKW, b1);
-  for (int q = 0; q + 1 < npair; ++q) {
-    stage(b0);
-    load((2 * q + 2) * SKW, b0);
-    mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
-    stage(b1);
+  put(b0, 0);
+  load(2 * SKW, b0);
+  __syncthreads();
+  for (int q = 0; q < npair; ++q) {
+    mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);  // stage 2q
+    put(b1, 1);                                         // stage 2q + 1
     load((2 * q + 3) * SKW, b1);
-    mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
+    __syncthreads();
+    mma_stage_w<TM, TN>(As + ASZ, 0, Bs + BSZ, wm, wn, lane, acc);
+    if (q + 1 < npair) {
+      put(b0, 0);  // stage 2q + 2
+      load((2 * q + 4) * SKW, b0);
+    }
+    __syncthreads();
   }
-  stage(b0);
-  mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
-  stage(b1);
-  mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);
 }
 
 template <int TM, int TN>
@@ -591,8 +595,8 @@ __global__ __launch_bounds__(NTW) void gemm_at_x_w(const float* __restrict__ A, 
   constexpr int LDR = SKW + 4, PB = TN + 16;
   using MA = WideMap<SKW>;  // a row piece of SKW floats: 8 float4
   using MB = WideMap<TN>;
-  __shared__ __align__(16) float Ar[TM * LDR];
-  __shared__ __align__(16) float Bs[SKW * PB];
+  __shared__ __align__(16) float Ar[2 * TM * LDR];
+  __shared__ __align__(16) float Bs[2 * SKW * PB];
   __shared__ int flag;
   if (m == 0 && any_fault(status, &flag)) return;
   const int st0 = status[0];  // used late, as in gemm_at_x
@@ -654,38 +658,40 @@ __global__ __launch_bounds__(NTW) void gemm_at_x_w(const float* __restrict__ A, 
       st.kb[i] = jj < j_end && rok;
     }
   };
-  auto stage = [&](const Buf& st) {
+  constexpr int ASZ = TM * LDR, BSZ = SKW * PB;  // floats of one LDS buffer of each operand
+  auto put = [&](const Buf& st, int buf) {
     // nothing moves across: a select hoisted above this point would wait for the other buffer
     __builtin_amdgcn_sched_barrier(0);
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < AP; ++i)
-      *reinterpret_cast<float4*>(&Ar[(ar + MA::rpp * i) * LDR + ac]) = keep4(st.ka[i], st.a[i]);
+      *reinterpret_cast<float4*>(&Ar[buf * ASZ + (ar + MA::rpp * i) * LDR + ac]) = keep4(st.ka[i], st.a[i]);
 #pragma unroll
     for (int i = 0; i < MB::passes; ++i)
-      *reinterpret_cast<float4*>(&Bs[(br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
-    __syncthreads();
+      *reinterpret_cast<float4*>(&Bs[buf * BSZ + (br + MB::rpp * i) * PB + bc]) = keep4(st.kb[i], st.b[i]);
   };
   f4 acc[TM / (16 * WGM)][TN / (16 * WGN)];
   zero_acc<TM, TN>(acc);
-  // two register buffers, stages in pairs with unconditional loads (as att_mainloop_w)
+  // two register buffers and two LDS buffers, one barrier a stage (as att_mainloop_w)
   const int npair = j_end > j_begin ? (int)((j_end - j_begin + 2 * SKW - 1) / (2 * SKW)) : 0;
   if (npair > 0) {
     Buf b0, b1;
     load(j_begin, b0);
     load(j_begin + SKW, b1);
-    for (int q = 0; q + 1 < npair; ++q) {
-      stage(b0);
-      load(j_begin + (int64_t)(2 * q + 2) * SKW, b0);
-      mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
-      stage(b1);
+    put(b0, 0);
+    load(j_begin + 2 * SKW, b0);
+    __syncthreads();
+    for (int q = 0; q < npair; ++q) {
+      mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);  // stage 2q
+      put(b1, 1);                                         // stage 2q + 1
       load(j_begin + (int64_t)(2 * q + 3) * SKW, b1);
-      mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
+      __syncthreads();
+      mma_stage_w<TM, TN>(Ar + ASZ, 1, Bs + BSZ, wm, wn, lane, acc);
+      if (q + 1 < npair) {
+        put(b0, 0);  // stage 2q + 2
+        load(j_begin + (int64_t)(2 * q + 4) * SKW, b0);
+      }
+      __syncthreads();
     }
-    stage(b0);
-    mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
-    stage(b1);
-    mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);
   }
   // D layout: column lane%16, rows 4*(lane/16) + v
   float* Ys = Y + (size_t)s * eta_pad * R;
@@ -711,8 +717,8 @@ __global__ __launch_bounds__(NTW) void gemm_att_w(const float* __restrict__ A, i
                                                   float* __restrict__ X, float lambda, float* __restrict__ Wp,
                                                   const int* status) {
   const int st0 = status[0];  // checked once the indices are staged, as in gemm_att_c_update
-  __shared__ __align__(16) float As[SKW * (TM + 16)];
-  __shared__ __align__(16) float Bs[SKW * (TN + 16)];
+  __shared__ __align__(16) float As[2 * SKW * (TM + 16)];
+  __shared__ __align__(16) float Bs[2 * SKW * (TN + 16)];
   __shared__ int taus[kMaxTauLds];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
