@@ -549,24 +549,24 @@ __device__ __forceinline__ void att_mainloop_w(const float* __restrict__ A, int6
   // Two register buffers and two LDS buffers: stage s + 1 is stored to LDS while stage s's
   // products run from the other buffer (one barrier a stage), and the loads of the stage after
   // that are in flight meanwhile (the workgroup is alone on its CU, so no other workgroup covers
-  // its load latency). Stage j's loads go to register buffer j % 2, unconditionally, so each
-  // store waits only for its own buffer; an odd count ends with a stage of zeros (adding exact
-  // zeros changes no sum).
-  const int npair = (eta + 2 * SKW - 1) / (2 * SKW);
-  if (npair == 0) return;
+  // its load latency). Stage j's loads go to register buffer j % 2, unconditionally (rows past
+  // the end are clamped and stored as zeros), so each store waits only for its own buffer.
+  const int nst = (eta + SKW - 1) / SKW;
+  if (nst == 0) return;
   Buf b0, b1;
   load(0, b0);
   load(SKW, b1);
   put(b0, 0);
   load(2 * SKW, b0);
   __syncthreads();
-  for (int q = 0; q < npair; ++q) {
+  for (int q = 0; 2 * q < nst; ++q) {
     mma_stage_w<TM, TN>(As, 0, Bs, wm, wn, lane, acc);  // stage 2q
+    if (2 * q + 1 >= nst) break;
     put(b1, 1);                                         // stage 2q + 1
     load((2 * q + 3) * SKW, b1);
     __syncthreads();
     mma_stage_w<TM, TN>(As + ASZ, 0, Bs + BSZ, wm, wn, lane, acc);
-    if (q + 1 < npair) {
+    if (2 * q + 2 < nst) {
       put(b0, 0);  // stage 2q + 2
       load((2 * q + 4) * SKW, b0);
     }
@@ -672,21 +672,22 @@ __global__ __launch_bounds__(NTW) void gemm_at_x_w(const float* __restrict__ A, 
   f4 acc[TM / (16 * WGM)][TN / (16 * WGN)];
   zero_acc<TM, TN>(acc);
   // two register buffers and two LDS buffers, one barrier a stage (as att_mainloop_w)
-  const int npair = j_end > j_begin ? (int)((j_end - j_begin + 2 * SKW - 1) / (2 * SKW)) : 0;
-  if (npair > 0) {
+  const int nst = j_end > j_begin ? (int)((j_end - j_begin + SKW - 1) / SKW) : 0;
+  if (nst > 0) {
     Buf b0, b1;
     load(j_begin, b0);
     load(j_begin + SKW, b1);
     put(b0, 0);
     load(j_begin + 2 * SKW, b0);
     __syncthreads();
-    for (int q = 0; q < npair; ++q) {
+    for (int q = 0; 2 * q < nst; ++q) {
       mma_stage_w<TM, TN>(Ar, 1, Bs, wm, wn, lane, acc);  // stage 2q
+      if (2 * q + 1 >= nst) break;
       put(b1, 1);                                         // stage 2q + 1
       load(j_begin + (int64_t)(2 * q + 3) * SKW, b1);
       __syncthreads();
       mma_stage_w<TM, TN>(Ar + ASZ, 1, Bs + BSZ, wm, wn, lane, acc);
-      if (q + 1 < npair) {
+      if (2 * q + 2 < nst) {
         put(b0, 0);  // stage 2q + 2
         load(j_begin + (int64_t)(2 * q + 4) * SKW, b0);
       }
