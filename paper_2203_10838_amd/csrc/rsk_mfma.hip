@@ -279,7 +279,9 @@ __device__ __forceinline__ float split_sum(const float* __restrict__ Y, int S, s
 }
 
 // C[t][r] = (alpha_k/eta) (sum_s Y[s][t][r] - B[tau_t, r]) / ||a_tau_t||^2; checks the step's
-// indices and coefficients, marks the step done. grid-stride over eta_pad x R.
+// indices and coefficients, marks the step done. One thread per 4 consecutive r (R % 4 == 0), in
+// one pass when the grid covers eta_pad x R / 4, else grid-stride; the S partials load as float4
+// before the row index is needed, and sum in split order (as split_sum).
 // With Rh non-null the residuals R_tau = sum_s Y_s - B_tau are stored as well (the adjoint's recompute).
 __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, const int32_t* __restrict__ tau, int eta,
                             const float* __restrict__ B, int R, const float* __restrict__ r2,
@@ -288,23 +290,53 @@ __global__ void coef_kernel(const float* __restrict__ Y, int S, int eta_pad, con
   const int st0 = status[0];  // read with the first loads, checked before the rows are used
   const float scale = (alpha_k ? alpha_k[k] : alpha) / (float)eta;
   const size_t total = (size_t)eta_pad * R;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int t = (int)(e / R), r = (int)(e % R);
-    float c = 0.f;
+  const int R4 = R / 4;
+  for (size_t e4 = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e4 < total / 4;
+       e4 += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e4 / R4), r = (int)(e4 % R4) * 4;
+    const size_t e = e4 * 4;
+    float c[4] = {0.f, 0.f, 0.f, 0.f}, res[4] = {0.f, 0.f, 0.f, 0.f};
     if (t < eta) {
       const int i = tau[t];
-      const float y = split_sum(Y, S, total, e);
+      float y[4] = {0.f, 0.f, 0.f, 0.f};
+      int s = 0;
+      for (; s + 8 <= S; s += 8) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const float4*>(Y + (size_t)(s + u) * total + e);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          y[0] += v[u].x;
+          y[1] += v[u].y;
+          y[2] += v[u].z;
+          y[3] += v[u].w;
+        }
+      }
+      for (; s < S; ++s) {
+        const float4 v = *reinterpret_cast<const float4*>(Y + (size_t)s * total + e);
+        y[0] += v.x;
+        y[1] += v.y;
+        y[2] += v.z;
+        y[3] += v.w;
+      }
       if (st0) return;  // an earlier fault: the step's rows may be out of range
       const float rn = weighted_rn(r2, row_w, i);
       if (rn == 0.f) set_status(status, ST_ZERO_ROW);
-      const float res = y - B[(int64_t)i * R + r];
-      if (Rh) Rh[e] = res;
-      c = scale * res / rn;
-      if (!isfinite(c)) set_status(status, ST_NONFINITE);
-    } else if (Rh) {
-      Rh[e] = 0.f;
+      const float* Bi = B + (int64_t)i * R + r;  // B need not be 16-byte aligned
+      bool bad = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        res[u] = y[u] - Bi[u];
+        c[u] = scale * res[u] / rn;
+        bad |= !isfinite(c[u]);
+      }
+      if (bad) set_status(status, ST_NONFINITE);
     }
-    C[e] = c;
+    if (Rh) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Rh[e + u] = res[u];
+    }
+    *reinterpret_cast<float4*>(C + e) = make_float4(c[0], c[1], c[2], c[3]);
   }
 }
 
