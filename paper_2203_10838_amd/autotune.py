@@ -142,10 +142,15 @@ def tune_dense(A: torch.Tensor, b: torch.Tensor, *, eta: int, lam: float, alpha:
 
 
 def multirhs_candidates(A: torch.Tensor, R: int, eta: int) -> list:
-    """(S, S2) pairs: column splits of A_tau X (at least 256 columns a split) and row splits of A_tau^T C."""
+    """(S, S2) pairs: column splits of A_tau X (at least 64 columns a split) and row splits of A_tau^T C.
+    Besides powers of two and whole XCD rounds, the splits that put one wide-tile workgroup on each CU
+    (CUs / tiles and one less)."""
     n = A.shape[1]
     max_s = max(1, (n + 63) // 64)        # a tuned split keeps at least 64 columns (one stage)
-    svals = sorted({s for s in (1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128) if s <= max_s})
+    cus = torch.cuda.get_device_properties(A.device).multi_processor_count if A.is_cuda else 256
+    tiles = -(-eta // 128) * (-(-R // 128) if R > 64 else 1)
+    fill = cus // tiles
+    svals = sorted({s for s in (1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128, fill, fill - 1) if 1 <= s <= max_s})
     s2vals = [s2 for s2 in (1, 2, 4, 8) if s2 <= max(1, (eta + 15) // 16)]
     return [(s, s2, kernel) for kernel in (1, 2, 3) for s in svals for s2 in s2vals]
 

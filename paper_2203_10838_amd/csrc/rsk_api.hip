@@ -474,11 +474,11 @@ int32_t plan_multirhs(const rsk_dense* A, int32_t R, const rsk_params* p, MultiP
   const int tn = pl->tile == 128 && R <= 64 ? 64 : pl->tile;  // the R edge of a product tile
   pl->eta_pad = (p->eta + pl->tile - 1) / pl->tile * pl->tile;
   const int tiles = (pl->eta_pad / pl->tile) * ((R + tn - 1) / tn);
-  // about three 256-thread workgroups per CU for the n-long products, or one 512-thread wide-tile
-  // workgroup (rounded down: a second round on some CUs costs more than a few idle ones), in whole
-  // XCD rounds (the tiles of a split share one L2)
+  // about three 256-thread workgroups per CU for the n-long products, in whole XCD rounds (the
+  // tiles of a split share one L2); or one 512-thread wide-tile workgroup per CU, rounded down (a
+  // second round on some CUs costs more than a few idle CUs or the L2 sharing)
   int S = pl->tile == 128 ? cus / tiles : (3 * cus + tiles - 1) / tiles;
-  if (S >= 8) S = pl->tile == 128 ? S / 8 * 8 : (S + 7) / 8 * 8;
+  if (S >= 8 && pl->tile != 128) S = (S + 7) / 8 * 8;
   if (tuned && te.v0 >= 1) S = (int)(te.v0 < 4096 ? te.v0 : 4096);
   // at least 256 columns a split by the built-in rule, at least 64 (one stage) for a tuned split
   const int64_t max_s = tuned && te.v0 >= 1 ? (A->n + 63) / 64 : (A->n + 255) / 256;
