@@ -115,8 +115,11 @@ constexpr size_t kFullGridStepBytes = size_t(8) << 20;
 using rsk::kOneHopWords;
 // the automatic choice takes two row groups of the register-tile kernel for eta in this range
 // (measured on 20000 columns: below it one group is as fast, the step being bound by the
-// exchange; above it the third exchange hop costs more than the wider row pieces save)
+// exchange; above it the third exchange hop costs more than the wider row pieces save), unless one
+// group's whole next-step tile fits the kernel's LDS prefetch (kRtPfBytes of LDS): then one group
+// is faster (20000 columns, eta = 96 ... 256: 4-7% shorter steps)
 constexpr int kRtTwoGroupMinEta = 88, kRtTwoGroupMaxEta = 800;
+constexpr int kRtPfBytes = 147456;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t elem_size(int32_t dt) { return dt == RSK_F64 ? 8 : 4; }
@@ -266,8 +269,11 @@ int32_t plan_dense_fixed(const rsk_dense* A, const rsk_params* p, DensePlan* pl)
   // than the general kernel's at every step size measured, one row per step included
   if (p->kernel == 3) return plan_dense_rt(A, p, 2, pl) ? RSK_OK : RSK_ERR_UNSUPPORTED;
   if (p->kernel == 2 || (p->kernel == 0 && A->dtype == RSK_F32)) {
-    if (p->kernel == 0 && p->eta >= kRtTwoGroupMinEta && p->eta <= kRtTwoGroupMaxEta && plan_dense_rt(A, p, 2, pl))
-      return RSK_OK;
+    if (p->kernel == 0 && p->eta >= kRtTwoGroupMinEta && p->eta <= kRtTwoGroupMaxEta) {
+      DensePlan one = *pl;
+      const bool whole = plan_dense_rt(A, p, 1, &one) && one.rp * one.cpl <= kRtPfBytes / (one.nt * 16);
+      if (!whole && plan_dense_rt(A, p, 2, pl)) return RSK_OK;
+    }
     if (plan_dense_rt(A, p, 1, pl)) return RSK_OK;
     if (p->kernel == 2) return RSK_ERR_UNSUPPORTED;
   }

@@ -187,14 +187,15 @@ def test_two_row_groups_headline_workload(cuda, rsk_lib):
 
 
 def test_library_choice_of_row_groups(cuda, rsk_lib):
-    """kernel = 0 plans two row groups for 88 <= eta <= 800 and one group outside that range on a
-    20000-column float32 system (rsk_plan_dense), runs bitwise what the explicit kernel runs, and
-    matches the oracle on the rows the stream touches."""
+    """kernel = 0 plans two row groups for 88 <= eta <= 800 unless one group's whole next-step tile
+    fits the LDS prefetch (eta <= 256 at 20000 columns: one pass of five slots a thread), and one
+    group outside that range, on a 20000-column float32 system (rsk_plan_dense); runs bitwise what the
+    explicit kernel runs, and matches the oracle on the rows the stream touches."""
     import torch
     from paper_2203_10838_amd import rsk
     sysd = inputs.dense_system_device(6000, 20000, 100, seed=77, noise_rel=0.01, device=cuda)
     A, b = sysd["A"], torch.from_numpy(sysd["b"]).to(cuda)
-    for eta, twin in ((88, 3), (300, 3), (800, 3), (801, 2), (1024, 2), (87, 2), (64, 2)):
+    for eta, twin in ((88, 2), (256, 2), (257, 3), (300, 3), (800, 3), (801, 2), (1024, 2), (87, 2), (64, 2)):
         plan = rsk.plan_dense(A, eta=eta)
         assert plan["kernel"] == twin and plan["row_groups"] == (2 if twin == 3 else 1), (eta, plan)
         K = 12
