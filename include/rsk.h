@@ -329,7 +329,9 @@ int32_t rsk_workspace_size_csr(const rsk_csr *A, const rsk_params *p, size_t *by
  * p->grid 0 or 1), the next step's rows loaded during the step: for small
  * systems, whose steps are bound by latency. 0 = the library's choice: for
  * float64 steps of at most 64 KB that kernel 4 takes, 4; for float32, 3 for
- * 88 <= eta <= 800, else 2, where the register tile applies; else 1. The
+ * 88 <= eta <= 800 unless kernel 2's whole next-step tile fits its LDS
+ * prefetch (one row pass of at most 9 float4 slots a thread), else 2, where
+ * the register tile applies; else 1. The
  * kernels sum in different orders (results agree to rounding); each gives
  * bitwise reproducible x* and x (y_out: see rsk_params; kernel 4 applies y in
  * a fixed order as well).
